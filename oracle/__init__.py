@@ -1,0 +1,12 @@
+"""TEST INFRASTRUCTURE -- the fp64 CPU oracle of the slice-reconciliation hot path.
+
+Plain, slow, obviously-correct reference used only by ``tests/``, the smoke
+check and the benchmark's CPU-baseline leg.  It shares no code with the HIP
+library and never imports it.
+
+* :mod:`oracle.slicing` -- quantiser/slicer and slice LLRs (NumPy/SciPy, fp64);
+* :mod:`oracle.bp`      -- syndrome, flooding sum-product / normalized min-sum,
+  unrolled min-sum with its reverse-mode derivative (plain C, fp64, via ctypes).
+"""
+from .slicing import GRAY, BINARY, quantize, slice_llr, log_interval_probs  # noqa: F401
+from .bp import syndrome, decode, nms_unrolled, round_half, build, SP, NMS  # noqa: F401

@@ -1,0 +1,378 @@
+/*
+ * TEST INFRASTRUCTURE -- the fp64 CPU oracle for the LDPC part of the
+ * slice-reconciliation hot path.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library; the product path
+ * never does.  It shares no code, header or table with the HIP library.
+ *
+ * Conventions (the paper names the belief-propagation decoder but fixes no
+ * variant; the readings taken here are listed in the design notes):
+ *   - an LLR is ln P(bit = 0) / P(bit = 1); hard decision b = 1 iff L < 0;
+ *   - sign(x) = -1 iff x < 0 (so -0.0 counts as +);
+ *   - syndrome decoding: every check-to-variable message of check c is
+ *     multiplied by (1 - 2 s_c), s_c being the syndrome bit Bob sends
+ *     (Sec. II Step 5, Sec. III-B steps 2-4);
+ *   - flooding schedule: all checks, then all variables, per iteration;
+ *   - the syndrome of the hard decisions is tested before the first
+ *     iteration and after every iteration (failure detection, Sec. II Step 5).
+ *
+ * Every function below is plain loops in double precision, written to be
+ * read against its definition rather than to be fast.  OpenMP splits the
+ * independent frames (sub-blocks, Sec. III-A) across host threads.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_SP 0
+#define ORC_NMS 1
+
+/* ------------------------------------------------------------------------ */
+/* syndrome s_c = XOR_{v in N(c)} b_v   (Sec. II Step 5; Sec. III-B step 2)  */
+/* ------------------------------------------------------------------------ */
+int orc_syndrome(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                 int32_t F, const uint8_t* bits, const uint8_t* s_ref,
+                 uint8_t* s_out, int32_t* n_unsat)
+{
+    for (int32_t f = 0; f < F; ++f) {
+        const uint8_t* b = bits + (int64_t)f * n;
+        int32_t u = 0;
+        for (int32_t c = 0; c < m; ++c) {
+            int s = 0;
+            for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) s ^= (b[col_idx[e]] & 1);
+            if (s_out) s_out[(int64_t)f * m + c] = (uint8_t)s;
+            int ref = s_ref ? (s_ref[(int64_t)f * m + c] & 1) : 0;
+            u += (s != ref);
+        }
+        if (n_unsat) n_unsat[f] = u;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* binary16 storage emulation: round-to-nearest-even to the IEEE half grid,   */
+/* saturating at +-65504 (largest finite half).                               */
+/* ------------------------------------------------------------------------ */
+double orc_round_half(double x)
+{
+    if (isnan(x)) return x;
+    double a = fabs(x);
+    if (a >= 65504.0) return copysign(65504.0, x);
+    if (a == 0.0) return x;
+    int e;
+    frexp(a, &e);                 /* a = f * 2^e, f in [0.5, 1) -> exponent of a is e-1 */
+    int ex = e - 1;
+    if (ex < -14) ex = -14;       /* subnormal halves share the 2^-24 spacing */
+    double ulp = ldexp(1.0, ex - 10);
+    double r = nearbyint(a / ulp) * ulp;   /* default rounding mode: nearest-even */
+    if (r > 65504.0) r = 65504.0;
+    return copysign(r, x);
+}
+
+/* phi(x) = -ln tanh(x/2) = ln(1 + 2/(e^x - 1)), phi(0) = +inf, phi(+inf) = 0. */
+static double phi(double x)
+{
+    if (x == 0.0) return INFINITY;
+    if (isinf(x)) return 0.0;
+    return log1p(2.0 / expm1(x));
+}
+
+static inline int neg(double x) { return x < 0.0; }
+
+/* Column view of a CSR matrix: for variable v, the CSR edge ids of its checks
+ * in ascending check order. */
+typedef struct { int32_t* ptr; int32_t* edge; } colview;
+
+static colview make_colview(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx)
+{
+    colview cv;
+    int64_t E = row_ptr[m];
+    cv.ptr = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+    cv.edge = (int32_t*)malloc((size_t)(E > 0 ? E : 1) * sizeof(int32_t));
+    for (int64_t e = 0; e < E; ++e) cv.ptr[col_idx[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) cv.ptr[v + 1] += cv.ptr[v];
+    int32_t* fill = (int32_t*)malloc((size_t)n * sizeof(int32_t) + 1);
+    for (int32_t v = 0; v < n; ++v) fill[v] = cv.ptr[v];
+    for (int32_t c = 0; c < m; ++c)                      /* rows ascending -> checks ascending */
+        for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) cv.edge[fill[col_idx[e]]++] = e;
+    free(fill);
+    return cv;
+}
+
+static void free_colview(colview* cv) { free(cv->ptr); free(cv->edge); }
+
+/* Number of checks whose parity over the hard decisions differs from s. */
+static int32_t count_unsat(int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                           const double* L, const uint8_t* s)
+{
+    int32_t u = 0;
+    for (int32_t c = 0; c < m; ++c) {
+        int p = s ? (s[c] & 1) : 0;
+        for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) p ^= neg(L[col_idx[e]]);
+        u += p;
+    }
+    return u;
+}
+
+/*
+ * Flooding belief propagation on F frames that share one parity-check matrix.
+ *
+ * algo = ORC_SP (sum-product):
+ *   c2v_e = (1 - 2 s_c) * prod_{k != e} sign(v2c_k) * phi( sum_{k != e} phi(|v2c_k|) )
+ *   with every v2c first clamped to [-clamp, clamp].
+ * algo = ORC_NMS (normalized min-sum):
+ *   c2v_e = w * (1 - 2 s_c) * prod_{k != e} sign(v2c_k) * min_{k != e} |v2c_k|,
+ *   w = weights[t * n_types + type_e] when weights != NULL, else alpha.
+ * Both:  v2c_e = L_ch[v] + sum_{c' in N(v), c' != c} c2v_{c'}  (extrinsic);
+ *        L_post[v] = L_ch[v] + sum_{c in N(v)} c2v_c.
+ * store_half != 0 rounds every stored c2v to binary16 (nearest-even, saturating).
+ *
+ * Iteration t = 0..T: the hard decisions of L_post(t) are tested against the
+ * syndrome (L_post(0) = L_ch); with early_stop the frame ends at the first t
+ * with no unsatisfied check; otherwise (or if never satisfied) it ends at T.
+ * Outputs: bits, L_post, iters = that t, ok = [no unsatisfied check at t].
+ * Optional traces ([F][T+1][n] / [F][T+1]): L_post(t), the scale
+ * |L_ch| + sum |c2v| of each posterior sum, and the unsatisfied-check count;
+ * entries after a frame's stop are left untouched.
+ */
+int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+               const uint8_t* edge_type, int32_t n_types,
+               int32_t F, const double* llr, const uint8_t* syn,
+               int32_t algo, int32_t T, int32_t early_stop, int32_t store_half,
+               double alpha, const double* weights, double clamp,
+               uint8_t* bits, double* post, int32_t* iters, uint8_t* ok,
+               double* trace, double* trace_scale, int32_t* trace_unsat)
+{
+    if (n <= 0 || m < 0 || F < 0 || T < 0) return -1;
+    const int64_t E = row_ptr[m];
+    colview cv = make_colview(n, m, row_ptr, col_idx);
+    int32_t maxdeg = 0;
+    for (int32_t c = 0; c < m; ++c)
+        if (row_ptr[c + 1] - row_ptr[c] > maxdeg) maxdeg = row_ptr[c + 1] - row_ptr[c];
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t f = 0; f < F; ++f) {
+        const double* Lch = llr + (int64_t)f * n;
+        const uint8_t* s = syn ? syn + (int64_t)f * m : NULL;
+        double* c2v = (double*)calloc((size_t)(E > 0 ? E : 1), sizeof(double));
+        double* v2c = (double*)malloc((size_t)(E > 0 ? E : 1) * sizeof(double));
+        double* Lp = (double*)malloc((size_t)n * sizeof(double));
+        double* mag = (double*)malloc((size_t)(maxdeg > 0 ? maxdeg : 1) * sizeof(double));
+        for (int32_t v = 0; v < n; ++v) Lp[v] = Lch[v];
+
+        int32_t t = 0;
+        for (;;) {
+            int32_t u = count_unsat(m, row_ptr, col_idx, Lp, s);
+            if (trace) memcpy(trace + ((int64_t)f * (T + 1) + t) * n, Lp, (size_t)n * sizeof(double));
+            if (trace_scale) {
+                double* sc = trace_scale + ((int64_t)f * (T + 1) + t) * n;
+                for (int32_t v = 0; v < n; ++v) {
+                    double a = fabs(Lch[v]);
+                    if (t > 0)
+                        for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a += fabs(c2v[cv.edge[k]]);
+                    sc[v] = a;
+                }
+            }
+            if (trace_unsat) trace_unsat[(int64_t)f * (T + 1) + t] = u;
+            if ((early_stop && u == 0) || t == T) {
+                iters[f] = t;
+                ok[f] = (uint8_t)(u == 0);
+                break;
+            }
+
+            /* variable-to-check: extrinsic sums */
+            for (int32_t v = 0; v < n; ++v) {
+                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) {
+                    double a = Lch[v];
+                    for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
+                        if (k2 != k) a += c2v[cv.edge[k2]];
+                    v2c[cv.edge[k]] = a;
+                }
+            }
+
+            /* check-to-variable */
+            for (int32_t c = 0; c < m; ++c) {
+                const int32_t e0 = row_ptr[c], e1 = row_ptr[c + 1];
+                const double ssign = (s && (s[c] & 1)) ? -1.0 : 1.0;
+                for (int32_t e = e0; e < e1; ++e) {
+                    double x = v2c[e];
+                    if (algo == ORC_SP) {
+                        if (x > clamp) x = clamp;
+                        if (x < -clamp) x = -clamp;
+                    }
+                    mag[e - e0] = x;
+                }
+                for (int32_t e = e0; e < e1; ++e) {
+                    double sg = ssign;
+                    for (int32_t k = e0; k < e1; ++k)
+                        if (k != e && neg(mag[k - e0])) sg = -sg;
+                    double out;
+                    if (algo == ORC_SP) {
+                        double acc = 0.0;
+                        for (int32_t k = e0; k < e1; ++k)
+                            if (k != e) acc += phi(fabs(mag[k - e0]));
+                        out = sg * phi(acc);
+                    } else {
+                        double mn = INFINITY;
+                        for (int32_t k = e0; k < e1; ++k)
+                            if (k != e && fabs(mag[k - e0]) < mn) mn = fabs(mag[k - e0]);
+                        double w = weights ? weights[(int64_t)t * n_types + (edge_type ? edge_type[e] : 0)] : alpha;
+                        out = w * (sg * mn);
+                    }
+                    c2v[e] = store_half ? orc_round_half(out) : out;
+                }
+            }
+
+            /* posteriors */
+            for (int32_t v = 0; v < n; ++v) {
+                double a = Lch[v];
+                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a += c2v[cv.edge[k]];
+                Lp[v] = a;
+            }
+            ++t;
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            if (bits) bits[(int64_t)f * n + v] = (uint8_t)neg(Lp[v]);
+            if (post) post[(int64_t)f * n + v] = Lp[v];
+        }
+        free(c2v); free(v2c); free(Lp); free(mag);
+    }
+    free_colview(&cv);
+    return 0;
+}
+
+/*
+ * Unrolled normalized min-sum (T iterations, no early stop, no clamp) and its
+ * reverse-mode derivative.
+ *   forward: as orc_decode with algo = NMS and weights w[t][type];
+ *   loss:    l = (1/(F n)) sum_{f,v} softplus( -(1 - 2 b_v) L_post,v(T) ),
+ *            the binary cross-entropy of P(b = 1) = sigmoid(-L) against the true bits b.
+ *   grads:   dl/dw [T][n_types]; optionally dl/dL_ch [F][n].
+ * The derivative of |x| is taken as sign(x) with sign(0) = +1; the derivative
+ * of the minimum over k != e goes to its lowest-index minimiser; sign products
+ * are piecewise constant.  All intermediate messages are kept (a full tape).
+ */
+int orc_nms_unrolled(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                     const uint8_t* edge_type, int32_t n_types,
+                     int32_t F, const double* llr, const uint8_t* syn, const uint8_t* truth,
+                     int32_t T, const double* weights,
+                     double* loss_out, double* post_out, double* dw, double* dllr)
+{
+    if (n <= 0 || m < 0 || F < 0 || T < 1) return -1;
+    const int64_t E = row_ptr[m];
+    colview cv = make_colview(n, m, row_ptr, col_idx);
+    const double inv_count = 1.0 / ((double)F * (double)n);
+    /* per-frame partial results, summed in frame order afterwards so that the
+     * result does not depend on the thread count */
+    double* dw_frame = (double*)calloc((size_t)(F > 0 ? F : 1) * T * n_types, sizeof(double));
+    double* loss_frame = (double*)calloc((size_t)(F > 0 ? F : 1), sizeof(double));
+
+#pragma omp parallel
+    {
+        double* c2v = (double*)malloc((size_t)(T + 1) * (E > 0 ? E : 1) * sizeof(double)); /* c2v(t), t = 0..T */
+        double* v2c = (double*)malloc((size_t)T * (E > 0 ? E : 1) * sizeof(double));       /* v2c(t), t = 0..T-1 */
+        double* g_c2v = (double*)malloc((size_t)(E > 0 ? E : 1) * sizeof(double));
+        double* g_v2c = (double*)malloc((size_t)(E > 0 ? E : 1) * sizeof(double));
+        double* Lp = (double*)malloc((size_t)n * sizeof(double));
+        double* gL = (double*)malloc((size_t)n * sizeof(double));
+
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t f = 0; f < F; ++f) {
+            const double* Lch = llr + (int64_t)f * n;
+            const uint8_t* s = syn ? syn + (int64_t)f * m : NULL;
+            const uint8_t* b = truth + (int64_t)f * n;
+            double* dw_loc = dw_frame + (int64_t)f * T * n_types;
+            double loss_loc = 0.0;
+            for (int64_t e = 0; e < E; ++e) c2v[e] = 0.0;
+            /* forward */
+            for (int32_t t = 0; t < T; ++t) {
+                const double* cin = c2v + (int64_t)t * E;
+                double* vt = v2c + (int64_t)t * E;
+                double* cout = c2v + (int64_t)(t + 1) * E;
+                for (int32_t v = 0; v < n; ++v)
+                    for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) {
+                        double a = Lch[v];
+                        for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
+                            if (k2 != k) a += cin[cv.edge[k2]];
+                        vt[cv.edge[k]] = a;
+                    }
+                for (int32_t c = 0; c < m; ++c) {
+                    const double ssign = (s && (s[c] & 1)) ? -1.0 : 1.0;
+                    for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+                        double sg = ssign, mn = INFINITY;
+                        for (int32_t k = row_ptr[c]; k < row_ptr[c + 1]; ++k) {
+                            if (k == e) continue;
+                            if (neg(vt[k])) sg = -sg;
+                            if (fabs(vt[k]) < mn) mn = fabs(vt[k]);
+                        }
+                        double w = weights[(int64_t)t * n_types + (edge_type ? edge_type[e] : 0)];
+                        cout[e] = w * (sg * mn);
+                    }
+                }
+            }
+            const double* cT = c2v + (int64_t)T * E;
+            for (int32_t v = 0; v < n; ++v) {
+                double a = Lch[v];
+                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a += cT[cv.edge[k]];
+                Lp[v] = a;
+                if (post_out) post_out[(int64_t)f * n + v] = a;
+                double z = -(1.0 - 2.0 * (b[v] & 1)) * a;           /* softplus(z) */
+                double sp = z > 0 ? z + log1p(exp(-z)) : log1p(exp(z));
+                loss_loc += sp * inv_count;
+                double sig = z >= 0 ? 1.0 / (1.0 + exp(-z)) : exp(z) / (1.0 + exp(z));
+                gL[v] = -(1.0 - 2.0 * (b[v] & 1)) * sig * inv_count;
+            }
+            /* reverse: L_post(T) -> c2v(T) */
+            for (int32_t v = 0; v < n; ++v)
+                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) g_c2v[cv.edge[k]] = gL[v];
+            double* gch = dllr ? dllr + (int64_t)f * n : NULL;
+            if (gch) for (int32_t v = 0; v < n; ++v) gch[v] = gL[v];
+            for (int32_t t = T - 1; t >= 0; --t) {
+                const double* vt = v2c + (int64_t)t * E;
+                for (int64_t e = 0; e < E; ++e) g_v2c[e] = 0.0;
+                /* through c2v(t+1) = w * sg_e * min_{k != e} |v2c_k| */
+                for (int32_t c = 0; c < m; ++c) {
+                    const double ssign = (s && (s[c] & 1)) ? -1.0 : 1.0;
+                    for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+                        double sg = ssign, mn = INFINITY;
+                        int32_t arg = -1;
+                        for (int32_t k = row_ptr[c]; k < row_ptr[c + 1]; ++k) {
+                            if (k == e) continue;
+                            if (neg(vt[k])) sg = -sg;
+                            if (fabs(vt[k]) < mn) { mn = fabs(vt[k]); arg = k; }
+                        }
+                        int32_t ty = edge_type ? edge_type[e] : 0;
+                        double w = weights[(int64_t)t * n_types + ty];
+                        dw_loc[(int64_t)t * n_types + ty] += g_c2v[e] * sg * mn;
+                        if (arg >= 0) {
+                            double dabs = neg(vt[arg]) ? -1.0 : 1.0;
+                            g_v2c[arg] += g_c2v[e] * w * sg * dabs;
+                        }
+                    }
+                }
+                /* through v2c(t)_e = L_ch + sum_{k != e} c2v(t)_k */
+                for (int64_t e = 0; e < E; ++e) g_c2v[e] = 0.0;
+                for (int32_t v = 0; v < n; ++v)
+                    for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) {
+                        double g = g_v2c[cv.edge[k]];
+                        if (gch) gch[v] += g;
+                        for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
+                            if (k2 != k) g_c2v[cv.edge[k2]] += g;
+                    }
+                /* c2v(0) = 0 is a constant: nothing flows further at t = 0 */
+            }
+            loss_frame[f] = loss_loc;
+        }
+        free(c2v); free(v2c); free(g_c2v); free(g_v2c); free(Lp); free(gL);
+    }
+    double loss_total = 0.0;
+    for (int64_t i = 0; i < (int64_t)T * n_types; ++i) dw[i] = 0.0;
+    for (int32_t f = 0; f < F; ++f) {
+        loss_total += loss_frame[f];
+        for (int64_t i = 0; i < (int64_t)T * n_types; ++i) dw[i] += dw_frame[(int64_t)f * T * n_types + i];
+    }
+    if (loss_out) *loss_out = loss_total;
+    free(dw_frame); free(loss_frame);
+    free_colview(&cv);
+    return 0;
+}
