@@ -36,7 +36,7 @@ def _load():
         i32 = C.c_int32
         d = C.c_double
         lib.orc_syndrome.argtypes = [i32, i32, P, P, i32, P, P, P, P]
-        lib.orc_decode.argtypes = [i32, i32, P, P, P, i32, i32, P, P, i32, i32, i32, i32,
+        lib.orc_decode.argtypes = [i32, i32, P, P, P, i32, i32, P, P, i32, i32, i32, i32, i32,
                                    d, P, d, P, P, P, P, P, P, P]
         lib.orc_nms_unrolled.argtypes = [i32, i32, P, P, P, i32, i32, P, P, P, i32, P, P, P, P, P]
         lib.orc_round_half.argtypes = [d]
@@ -74,10 +74,10 @@ def syndrome(code, bits, s_ref=None):
 
 
 def decode(code, llr, syndrome=None, *, algo=SP, max_iter=50, early_stop=True,
-           store_half=False, alpha=0.75, weights=None, clamp=50.0, trace=False):
-    """Flooding BP over frames llr [F, n] (fp64).  Returns a dict with bits,
-    post, iters, ok and, with ``trace``, post_trace/scale_trace [F, T+1, n] and
-    unsat_trace [F, T+1]."""
+           store_half=False, alpha=0.75, weights=None, clamp=50.0, trace=False, prec32=False):
+    """Flooding BP over frames llr [F, n] (fp64, or every step rounded to
+    binary32 with ``prec32``).  Returns a dict with bits, post, iters, ok and,
+    with ``trace``, post_trace/scale_trace [F, T+1, n] and unsat_trace [F, T+1]."""
     lib = _load()
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     F, n = llr.shape
@@ -97,7 +97,7 @@ def decode(code, llr, syndrome=None, *, algo=SP, max_iter=50, early_stop=True,
         ut = np.full((F, max_iter + 1), -1, dtype=np.int32)
     rc = lib.orc_decode(code.n, code.m, _p(rp), _p(ci), _p(et), code.n_types, F, _p(llr), _p(syn),
                         int(algo), int(max_iter), int(bool(early_stop)), int(bool(store_half)),
-                        float(alpha), _p(w), float(clamp),
+                        int(bool(prec32)), float(alpha), _p(w), float(clamp),
                         _p(out["bits"]), _p(out["post"]), _p(out["iters"]), _p(out["ok"]),
                         _p(tr), _p(sc), _p(ut))
     if rc:

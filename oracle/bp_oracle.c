@@ -101,15 +101,21 @@ static colview make_colview(int32_t n, int32_t m, const int32_t* row_ptr, const 
 
 static void free_colview(colview* cv) { free(cv->ptr); free(cv->edge); }
 
-/* Number of checks whose parity over the hard decisions differs from s. */
+/* Number of checks whose parity over the hard decisions differs from s.  A
+ * check touching a NaN posterior counts as unsatisfied, so that a frame fed a
+ * NaN LLR can never be reported as decoded. */
 static int32_t count_unsat(int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
                            const double* L, const uint8_t* s)
 {
     int32_t u = 0;
     for (int32_t c = 0; c < m; ++c) {
         int p = s ? (s[c] & 1) : 0;
-        for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) p ^= neg(L[col_idx[e]]);
-        u += p;
+        int nan = 0;
+        for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+            p ^= neg(L[col_idx[e]]);
+            nan |= isnan(L[col_idx[e]]) ? 1 : 0;
+        }
+        u += p | nan;
     }
     return u;
 }
@@ -134,11 +140,21 @@ static int32_t count_unsat(int32_t m, const int32_t* row_ptr, const int32_t* col
  * Optional traces ([F][T+1][n] / [F][T+1]): L_post(t), the scale
  * |L_ch| + sum |c2v| of each posterior sum, and the unsatisfied-check count;
  * entries after a frame's stop are left untouched.
+ *
+ * prec32 != 0 takes every step in binary32 instead: each result of an add,
+ * subtract, multiply or phi is rounded to the nearest float (computing in
+ * double and rounding once is exact for these operations since 53 >= 2*24+2),
+ * the posterior is accumulated from L_ch in ascending check order, and the
+ * extrinsic message is formed as L_post - c2v, which equals the sum above in
+ * exact arithmetic.  This is the precision in which a binary32 decoder takes
+ * its rounding-to-binary16 and minimum-selection decisions.
  */
+static inline double rnd(int prec32, double x) { return prec32 ? (double)(float)x : x; }
+
 int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
                const uint8_t* edge_type, int32_t n_types,
                int32_t F, const double* llr, const uint8_t* syn,
-               int32_t algo, int32_t T, int32_t early_stop, int32_t store_half,
+               int32_t algo, int32_t T, int32_t early_stop, int32_t store_half, int32_t prec32,
                double alpha, const double* weights, double clamp,
                uint8_t* bits, double* post, int32_t* iters, uint8_t* ok,
                double* trace, double* trace_scale, int32_t* trace_unsat)
@@ -158,7 +174,7 @@ int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_
         double* v2c = (double*)malloc((size_t)(E > 0 ? E : 1) * sizeof(double));
         double* Lp = (double*)malloc((size_t)n * sizeof(double));
         double* mag = (double*)malloc((size_t)(maxdeg > 0 ? maxdeg : 1) * sizeof(double));
-        for (int32_t v = 0; v < n; ++v) Lp[v] = Lch[v];
+        for (int32_t v = 0; v < n; ++v) Lp[v] = rnd(prec32, Lch[v]);
 
         int32_t t = 0;
         for (;;) {
@@ -183,9 +199,14 @@ int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_
             /* variable-to-check: extrinsic sums */
             for (int32_t v = 0; v < n; ++v) {
                 for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) {
-                    double a = Lch[v];
-                    for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
-                        if (k2 != k) a += c2v[cv.edge[k2]];
+                    double a;
+                    if (prec32) {
+                        a = rnd(1, Lp[v] - c2v[cv.edge[k]]);
+                    } else {
+                        a = Lch[v];
+                        for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
+                            if (k2 != k) a += c2v[cv.edge[k2]];
+                    }
                     v2c[cv.edge[k]] = a;
                 }
             }
@@ -210,14 +231,14 @@ int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_
                     if (algo == ORC_SP) {
                         double acc = 0.0;
                         for (int32_t k = e0; k < e1; ++k)
-                            if (k != e) acc += phi(fabs(mag[k - e0]));
-                        out = sg * phi(acc);
+                            if (k != e) acc = rnd(prec32, acc + rnd(prec32, phi(fabs(mag[k - e0]))));
+                        out = sg * rnd(prec32, phi(acc));
                     } else {
                         double mn = INFINITY;
                         for (int32_t k = e0; k < e1; ++k)
                             if (k != e && fabs(mag[k - e0]) < mn) mn = fabs(mag[k - e0]);
                         double w = weights ? weights[(int64_t)t * n_types + (edge_type ? edge_type[e] : 0)] : alpha;
-                        out = w * (sg * mn);
+                        out = rnd(prec32, rnd(prec32, w) * (sg * mn));
                     }
                     c2v[e] = store_half ? orc_round_half(out) : out;
                 }
@@ -225,8 +246,8 @@ int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_
 
             /* posteriors */
             for (int32_t v = 0; v < n; ++v) {
-                double a = Lch[v];
-                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a += c2v[cv.edge[k]];
+                double a = rnd(prec32, Lch[v]);
+                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a = rnd(prec32, a + c2v[cv.edge[k]]);
                 Lp[v] = a;
             }
             ++t;

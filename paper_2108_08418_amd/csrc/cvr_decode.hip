@@ -1,0 +1,552 @@
+// Batched flooding belief-propagation decoding of sub-blocks (Sec. III-A,
+// Sec. III-C) and syndrome checks (Sec. II Step 5).
+//
+// State kept between the two half-iterations of frame f:
+//   c2v  [msg_off .. msg_off + E)  check-to-variable messages (store dtype)
+//   Lpost[vn_off .. vn_off + n)    posteriors of the last finished iteration
+// The variable-to-check message is never stored: the check pass forms it as
+// Lpost[v] - c2v[e] from the two arrays above (for t = 0, c2v = 0).
+//
+// Iteration t (t = 0..T) of one frame is
+//   check pass:    count checks unsatisfied by the decisions of Lpost(t) and,
+//                  if t < T, compute c2v(t+1) from Lpost(t) and c2v(t);
+//   variable pass: if the count is 0 (early stop) or t == T the frame ends
+//                  at t; else Lpost(t+1) = Lch + sum_e c2v(t+1).
+// Every pass reads a per-frame `active` flag, so finished frames cost one
+// flag read per tile.  Two layouts share this schedule:
+//   generic  -- explicit CSR; messages in CSR order; one thread per check row
+//               / variable, gathers through col_idx / col_edge;
+//   QC       -- quasi-cyclic codes; messages block-major ([block][k]), so both
+//               passes touch consecutive addresses per wavefront and need no
+//               index arrays (the block tables are wave-uniform).
+// Both sum in the same order, so they give bit-identical results.
+#include "cvr_internal.h"
+
+namespace cvr {
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers
+// ---------------------------------------------------------------------------
+// phi(x) = -ln tanh(x/2) = ln(1 + 2/(e^x - 1)); phi(0) = inf, phi(inf) = 0.
+__device__ __forceinline__ float phi(float x) { return log1pf(2.0f / expm1f(x)); }
+__device__ __forceinline__ double phi(double x) { return log1p(2.0 / expm1(x)); }
+
+template <typename S> struct StoreT;
+template <> struct StoreT<double> {
+    __device__ static double put(double v) { return v; }
+    __device__ static double get(double s) { return s; }
+};
+template <> struct StoreT<float> {
+    template <typename M> __device__ static float put(M v) { return float(v); }
+    __device__ static float get(float s) { return s; }
+};
+template <> struct StoreT<__half> {
+    // round to nearest even, saturating at the largest finite half (NaN kept)
+    __device__ static __half put(float v)
+    {
+        v = v > 65504.0f ? 65504.0f : (v < -65504.0f ? -65504.0f : v);
+        return __float2half_rn(v);
+    }
+    __device__ static float get(__half s) { return __half2float(s); }
+};
+
+template <typename M> __device__ __forceinline__ M mabs(M v) { return v < M(0) ? -v : v; }
+
+// Check-node rule on d <= MAXD incoming v2c values x[] (sign flags in negm).
+// Writes the outgoing messages through `emit(k, value)`.
+template <typename M, int ALGO, int MAXD, typename W, typename Emit>
+__device__ __forceinline__ void check_rule(const M (&x)[MAXD], int d, int syn, M clampv, W weight, Emit emit)
+{
+    uint32_t negm = 0;
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k)
+        if (k < d && x[k] < M(0)) negm |= 1u << k;
+    const uint32_t tot = uint32_t(__popc(negm) & 1) ^ uint32_t(syn);
+    if (ALGO == CVR_SP) {
+        M a[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            M v = mabs(x[k]);
+            v = v > clampv ? clampv : v;
+            a[k] = (k < d) ? phi(v) : M(0);
+        }
+        // exclusive sums by prefix + suffix (no total-minus-self cancellation)
+        M suf[MAXD];
+        M acc = M(0);
+#pragma unroll
+        for (int k = MAXD - 1; k >= 0; --k) {
+            suf[k] = acc;
+            if (k < d) acc += a[k];
+        }
+        acc = M(0);
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+                const M mag = phi(acc + suf[k]);
+                const bool neg = (tot ^ ((negm >> k) & 1u)) != 0;
+                emit(k, neg ? -mag : mag);
+                acc += a[k];
+            }
+        }
+    } else {
+        M m1 = M(INFINITY), m2 = M(INFINITY);
+        int i1 = -1;
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+                const M v = mabs(x[k]);
+                if (v < m1) {
+                    m2 = m1;
+                    m1 = v;
+                    i1 = k;
+                } else if (v < m2) {
+                    m2 = v;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+                const M mag = (k == i1) ? m2 : m1;
+                const bool neg = (tot ^ ((negm >> k) & 1u)) != 0;
+                const M w = weight(k);
+                emit(k, w * (neg ? -mag : mag));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+struct DecArgs {
+    const DevCode* codes;
+    const DevFrame* frames;
+    const Tile* tiles;
+    const void* llr;          // math dtype
+    const uint8_t* syn;       // may be NULL
+    void* c2v;                // store dtype
+    void* post;               // math dtype
+    void* trace;              // math dtype or NULL
+    uint8_t* bits;
+    int32_t* iters;
+    uint8_t* ok;
+    int32_t* active;          // [F]
+    int32_t* unsat;           // [F][2]
+    const float* weights;     // [T][n_types] or NULL
+    int64_t total_n;
+    float alpha;
+    float clamp;
+    int32_t t;
+    int32_t T;
+    int32_t early_stop;
+    int32_t n_types;
+};
+
+__device__ __forceinline__ void add_unsat(int32_t* slot, int pred)
+{
+    const int cnt = __syncthreads_count(pred);
+    if (threadIdx.x == 0 && cnt) atomicAdd(slot, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// generic (explicit CSR) passes
+// ---------------------------------------------------------------------------
+template <typename M, typename S, int ALGO, int MAXD>
+__global__ __launch_bounds__(kTile) void k_check_generic(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int r = tl.a + int(threadIdx.x);
+    const M* Lp = static_cast<const M*>(a.post) + fr.vn_off;
+    S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    int bad = 0;
+    if (int(threadIdx.x) < count) {
+        const int e0 = cd.row_ptr[r];
+        const int d = cd.row_ptr[r + 1] - e0;
+        const int syn = a.syn ? (a.syn[fr.chk_off + r] & 1) : 0;
+        int par = syn;
+        bool nan = false;
+        M x[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            x[k] = M(0);
+            if (k < d) {
+                const M lp = Lp[cd.col_idx[e0 + k]];
+                par ^= (lp < M(0)) ? 1 : 0;
+                nan |= (lp != lp);
+                x[k] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(msg[e0 + k]));
+            }
+        }
+        bad = par | (nan ? 1 : 0);
+        if (a.t < a.T) {
+            const float* wt = a.weights ? a.weights + int64_t(a.t) * a.n_types : nullptr;
+            auto weight = [&](int k) -> M {
+                return wt ? M(wt[cd.edge_type[e0 + k]]) : M(a.alpha);
+            };
+            auto emit = [&](int k, M v) { msg[e0 + k] = StoreT<S>::put(v); };
+            check_rule<M, ALGO, MAXD>(x, d, syn, M(a.clamp), weight, emit);
+        }
+    }
+    add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
+}
+
+// Ends finished frames; returns true when this tile's frame must not update.
+__device__ __forceinline__ bool frame_stops(const DecArgs& a, const Tile& tl)
+{
+    const int u = a.unsat[2 * tl.frame + (a.t & 1)];
+    const bool stop = (a.early_stop && u == 0) || a.t >= a.T;
+    if ((tl.count & kFirstTile) && threadIdx.x == 0) {
+        if (stop) {
+            a.iters[tl.frame] = a.t;
+            a.ok[tl.frame] = uint8_t(u == 0);
+            a.active[tl.frame] = 0;
+        } else {
+            a.unsat[2 * tl.frame + ((a.t + 1) & 1)] = 0;
+        }
+    }
+    return stop;
+}
+
+template <typename M, typename S>
+__global__ __launch_bounds__(kTile) void k_var_generic(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    if (frame_stops(a, tl)) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int v = tl.a + int(threadIdx.x);
+    if (int(threadIdx.x) >= count) return;
+    const S* msg = static_cast<const S*>(a.c2v) + fr.msg_off;
+    M acc = static_cast<const M*>(a.llr)[fr.vn_off + v];
+    for (int k = cd.col_ptr[v]; k < cd.col_ptr[v + 1]; ++k) acc += M(StoreT<S>::get(msg[cd.col_edge[k]]));
+    static_cast<M*>(a.post)[fr.vn_off + v] = acc;
+    if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// quasi-cyclic passes: tile = (frame, block row / column, first k / u)
+// ---------------------------------------------------------------------------
+template <typename M, typename S, int ALGO, int MAXD>
+__global__ __launch_bounds__(kTile) void k_check_qc(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int i = tl.a;
+    const int k = tl.b + int(threadIdx.x);
+    const int Z = cd.Z;
+    const int q0 = cd.qrow_ptr[i];
+    const int d = cd.qrow_ptr[i + 1] - q0;
+    const M* Lp = static_cast<const M*>(a.post) + fr.vn_off;
+    S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    int bad = 0;
+    if (int(threadIdx.x) < count) {
+        const int syn = a.syn ? (a.syn[fr.chk_off + int64_t(i) * Z + k] & 1) : 0;
+        int par = syn;
+        bool nan = false;
+        M x[MAXD];
+#pragma unroll
+        for (int q = 0; q < MAXD; ++q) {
+            x[q] = M(0);
+            if (q < d) {
+                const QcBlock blk = cd.qrow[q0 + q];
+                int u = k + blk.shift;
+                u = u >= Z ? u - Z : u;
+                const M lp = Lp[int64_t(blk.other) * Z + u];
+                par ^= (lp < M(0)) ? 1 : 0;
+                nan |= (lp != lp);
+                x[q] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(msg[int64_t(blk.blk) * Z + k]));
+            }
+        }
+        bad = par | (nan ? 1 : 0);
+        if (a.t < a.T) {
+            const float* wt = a.weights ? a.weights + int64_t(a.t) * a.n_types : nullptr;
+            auto weight = [&](int q) -> M { return wt ? M(wt[cd.qrow[q0 + q].type]) : M(a.alpha); };
+            auto emit = [&](int q, M v) { msg[int64_t(cd.qrow[q0 + q].blk) * Z + k] = StoreT<S>::put(v); };
+            check_rule<M, ALGO, MAXD>(x, d, syn, M(a.clamp), weight, emit);
+        }
+    }
+    add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
+}
+
+template <typename M, typename S>
+__global__ __launch_bounds__(kTile) void k_var_qc(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    if (frame_stops(a, tl)) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    if (int(threadIdx.x) >= count) return;
+    const int j = tl.a;
+    const int u = tl.b + int(threadIdx.x);
+    const int Z = cd.Z;
+    const S* msg = static_cast<const S*>(a.c2v) + fr.msg_off;
+    const int64_t v = int64_t(j) * Z + u;
+    M acc = static_cast<const M*>(a.llr)[fr.vn_off + v];
+    for (int q = cd.qcol_ptr[j]; q < cd.qcol_ptr[j + 1]; ++q) {      // block rows ascending
+        const QcBlock blk = cd.qcol[q];
+        int k = u - blk.shift;
+        k = k < 0 ? k + Z : k;
+        acc += M(StoreT<S>::get(msg[int64_t(blk.blk) * Z + k]));
+    }
+    static_cast<M*>(a.post)[fr.vn_off + v] = acc;
+    if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// set-up and output passes (over the generic variable tiles)
+// ---------------------------------------------------------------------------
+template <typename M>
+__global__ __launch_bounds__(kTile) void k_dec_init(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    const DevFrame fr = a.frames[tl.frame];
+    const int count = tl.count & 0x7fffffff;
+    if ((tl.count & kFirstTile) && threadIdx.x == 0) {
+        a.active[tl.frame] = 1;
+        a.unsat[2 * tl.frame] = 0;
+        a.unsat[2 * tl.frame + 1] = 0;
+        a.iters[tl.frame] = 0;
+        a.ok[tl.frame] = 0;
+    }
+    if (int(threadIdx.x) >= count) return;
+    const int64_t v = fr.vn_off + tl.a + int(threadIdx.x);
+    const M l = static_cast<const M*>(a.llr)[v];
+    static_cast<M*>(a.post)[v] = l;
+    if (a.trace) static_cast<M*>(a.trace)[v] = l;
+}
+
+template <typename M>
+__global__ __launch_bounds__(kTile) void k_dec_final(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    const DevFrame fr = a.frames[tl.frame];
+    const int count = tl.count & 0x7fffffff;
+    if (int(threadIdx.x) >= count) return;
+    const int64_t v = fr.vn_off + tl.a + int(threadIdx.x);
+    a.bits[v] = static_cast<const M*>(a.post)[v] < M(0) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// syndrome check over F frames of one code
+// ---------------------------------------------------------------------------
+struct SynArgs {
+    DevCode code;
+    const uint8_t* bits;
+    const uint8_t* ref;
+    uint8_t* out;
+    int32_t* n_unsat;
+    int32_t F;
+};
+
+__global__ __launch_bounds__(256) void k_zero_i32(int32_t* p, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_syndrome(SynArgs a)
+{
+    const int f = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const DevCode& cd = a.code;
+    int bad = 0;
+    if (r < cd.m) {
+        const uint8_t* b = a.bits + int64_t(f) * cd.n;
+        int par = 0;
+        for (int e = cd.row_ptr[r]; e < cd.row_ptr[r + 1]; ++e) par ^= b[cd.col_idx[e]] & 1;
+        const int ref = a.ref ? (a.ref[int64_t(f) * cd.m + r] & 1) : 0;
+        if (a.out) a.out[int64_t(f) * cd.m + r] = uint8_t(par);
+        bad = par != ref;
+    }
+    if (a.n_unsat) add_unsat(&a.n_unsat[f], bad);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static size_t msize(int32_t p) { return p == CVR_F64 ? 8 : (p == CVR_F32 ? 4 : 2); }
+
+struct WsLayout {
+    size_t c2v, post, active, unsat, total;
+};
+
+static WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
+{
+    WsLayout w{};
+    size_t off = 0;
+    w.c2v = off;
+    off = align256(off + size_t(b->total_E) * msize(p->store));
+    w.post = off;
+    off = align256(off + size_t(b->total_n) * msize(p->math));
+    w.active = off;
+    off = align256(off + size_t(b->F) * 4);
+    w.unsat = off;
+    off = align256(off + size_t(b->F) * 8);
+    w.total = off;
+    return w;
+}
+
+static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
+{
+    if (!b) return fail(CVR_EINVAL, "decode: NULL batch");
+    if (!p) return fail(CVR_EINVAL, "decode: NULL params");
+    if (p->algo != CVR_SP && p->algo != CVR_NMS) return fail(CVR_EINVAL, "decode: bad algo");
+    if (p->max_iter < 0 || p->max_iter > 100000) return fail(CVR_EINVAL, "decode: max_iter out of range");
+    if (p->math != CVR_F32 && p->math != CVR_F64) return fail(CVR_EINVAL, "decode: math must be F32 or F64");
+    if (p->store != CVR_F64 && p->store != CVR_F32 && p->store != CVR_F16) return fail(CVR_EINVAL, "decode: bad store");
+    if (p->store == CVR_F64 && p->math != CVR_F64) return fail(CVR_EINVAL, "decode: F64 storage needs F64 math");
+    if (p->math == CVR_F64 && p->store != CVR_F64)
+        return fail(CVR_EUNSUPPORTED, "decode: F64 math is implemented with F64 storage only");
+    if (p->algo == CVR_SP && !(p->msg_clamp > 0.0f)) return fail(CVR_EINVAL, "decode: msg_clamp must be > 0");
+    return CVR_OK;
+}
+
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_decode(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc)
+{
+    const int64_t nvt = b->n_vn_tiles;
+    a.tiles = b->d_vn_tiles;
+    {
+        ProfScope prof(CVR_PROF_DEC_SETUP, s);
+        hipLaunchKernelGGL(k_dec_init<M>, dim3(nvt), dim3(kTile), 0, s, a);
+    }
+    if (cvr_status st = check_launch("decode init")) return st;
+    for (int t = 0; t <= a.T; ++t) {
+        a.t = t;
+        if (qc) {
+            a.tiles = b->d_qcn_tiles;
+            {
+                ProfScope prof(CVR_PROF_CHECK, s);
+                hipLaunchKernelGGL((k_check_qc<M, S, ALGO, MAXD>), dim3(b->n_qcn_tiles), dim3(kTile), 0, s, a);
+            }
+            a.tiles = b->d_qvn_tiles;
+            {
+                ProfScope prof(CVR_PROF_VAR, s);
+                hipLaunchKernelGGL((k_var_qc<M, S>), dim3(b->n_qvn_tiles), dim3(kTile), 0, s, a);
+            }
+        } else {
+            a.tiles = b->d_cn_tiles;
+            {
+                ProfScope prof(CVR_PROF_CHECK, s);
+                hipLaunchKernelGGL((k_check_generic<M, S, ALGO, MAXD>), dim3(b->n_cn_tiles), dim3(kTile), 0, s, a);
+            }
+            a.tiles = b->d_vn_tiles;
+            {
+                ProfScope prof(CVR_PROF_VAR, s);
+                hipLaunchKernelGGL((k_var_generic<M, S>), dim3(nvt), dim3(kTile), 0, s, a);
+            }
+        }
+        if (cvr_status st = check_launch("decode iteration")) return st;
+    }
+    a.tiles = b->d_vn_tiles;
+    {
+        ProfScope prof(CVR_PROF_DEC_SETUP, s);
+        hipLaunchKernelGGL(k_dec_final<M>, dim3(nvt), dim3(kTile), 0, s, a);
+    }
+    return check_launch("decode final");
+}
+
+template <typename M, typename S, int ALGO>
+static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc)
+{
+    if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
+    if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
+    return run_decode<M, S, ALGO, 32>(b, a, s, qc);
+}
+
+template <typename M, typename S>
+static cvr_status dispatch_algo(const cvr_batch_s* b, int algo, DecArgs a, hipStream_t s, bool qc)
+{
+    if (algo == CVR_SP) return dispatch_deg<M, S, CVR_SP>(b, a, s, qc);
+    return dispatch_deg<M, S, CVR_NMS>(b, a, s, qc);
+}
+
+}  // namespace cvr
+
+using namespace cvr;
+
+extern "C" cvr_status cvr_decode_workspace_size(cvr_batch_t batch, const cvr_decode_params* params, size_t* bytes)
+{
+    if (cvr_status st = check_params(batch, params)) return st;
+    if (!bytes) return fail(CVR_EINVAL, "cvr_decode_workspace_size: bytes is NULL");
+    *bytes = layout(batch, params).total;
+    return CVR_OK;
+}
+
+extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_params* params, const void* llr,
+                                        const uint8_t* syndrome, uint8_t* bits_out, void* llr_post_out,
+                                        int32_t* iters_out, uint8_t* ok_out, void* workspace, size_t ws_bytes,
+                                        void* stream)
+{
+    if (cvr_status st = check_params(batch, params)) return st;
+    if (batch->F == 0) return CVR_OK;
+    if (!llr || !bits_out || !iters_out || !ok_out) return fail(CVR_EINVAL, "ldpc_decode_batch: NULL input/output");
+    const WsLayout w = layout(batch, params);
+    if (!workspace || ws_bytes < w.total) return fail(CVR_ENOMEM, "ldpc_decode_batch: workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(CVR_EINVAL, "ldpc_decode_batch: workspace not 256-byte aligned");
+    if (params->weights && batch->max_types > kMaxTypes) return fail(CVR_EINVAL, "ldpc_decode_batch: too many edge types");
+    char* ws = static_cast<char*>(workspace);
+    DecArgs a{};
+    a.codes = batch->d_codes;
+    a.frames = batch->d_frames;
+    a.llr = llr;
+    a.syn = syndrome;
+    a.c2v = ws + w.c2v;
+    a.post = llr_post_out ? llr_post_out : static_cast<void*>(ws + w.post);
+    a.trace = params->trace;
+    a.bits = bits_out;
+    a.iters = iters_out;
+    a.ok = ok_out;
+    a.active = reinterpret_cast<int32_t*>(ws + w.active);
+    a.unsat = reinterpret_cast<int32_t*>(ws + w.unsat);
+    a.weights = params->weights;
+    a.total_n = batch->total_n;
+    a.alpha = params->alpha;
+    a.clamp = params->msg_clamp;
+    a.T = params->max_iter;
+    a.early_stop = params->early_stop ? 1 : 0;
+    a.n_types = batch->max_types;
+    const hipStream_t s = hipStream_t(stream);
+    const bool qc = batch->all_qc;
+    if (params->math == CVR_F64) return dispatch_algo<double, double>(batch, params->algo, a, s, qc);
+    if (params->store == CVR_F32) return dispatch_algo<float, float>(batch, params->algo, a, s, qc);
+    return dispatch_algo<float, __half>(batch, params->algo, a, s, qc);
+}
+
+extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,
+                                     uint8_t* syndrome_out, int32_t* n_unsat, void* stream)
+{
+    if (!code) return fail(CVR_EINVAL, "syndrome_check: NULL code");
+    if (F < 0) return fail(CVR_EINVAL, "syndrome_check: F < 0");
+    if (F == 0) return CVR_OK;
+    if (F > 65535) return fail(CVR_EINVAL, "syndrome_check: F > 65535");
+    if (!bits) return fail(CVR_EINVAL, "syndrome_check: bits is NULL");
+    const hipStream_t s = hipStream_t(stream);
+    ProfScope prof(CVR_PROF_SYNDROME, s);
+    if (n_unsat) {
+        hipLaunchKernelGGL(k_zero_i32, dim3((F + 255) / 256), dim3(256), 0, s, n_unsat, int64_t(F));
+        if (cvr_status st = check_launch("syndrome_check zero")) return st;
+    }
+    SynArgs a{};
+    a.code = code->dev;
+    a.bits = bits;
+    a.ref = syndrome;
+    a.out = syndrome_out;
+    a.n_unsat = n_unsat;
+    a.F = F;
+    hipLaunchKernelGGL(k_syndrome, dim3((code->dev.m + 255) / 256, F), dim3(256), 0, s, a);
+    return check_launch("syndrome_check");
+}

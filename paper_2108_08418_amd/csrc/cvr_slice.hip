@@ -1,0 +1,210 @@
+// Bob's quantiser/slicer and Alice's slice LLRs (Sec. III-B steps 1, 2 and 4).
+//
+// Both kernels are streaming passes over the quadratures: one fp64 load per
+// sample plus m_bits slice bytes (quantiser) or the known slice bytes and one
+// output (LLR).  The thresholds travel by value in the kernel arguments.
+#include "cvr_internal.h"
+
+#include <cmath>
+
+namespace cvr {
+
+constexpr int kMaxThr = 255;
+
+struct QuantArgs {
+    const double* y;
+    uint8_t* slices;
+    int64_t n;
+    int32_t m_bits;
+    int32_t nthr;
+    int32_t gray;
+    int32_t vec;           // 1: n % 4 == 0 and y/slices aligned for the 4-wide path
+    double t[kMaxThr];
+};
+
+struct LlrArgs {
+    const double* x;
+    const uint8_t* slices;
+    void* out;
+    int64_t n;
+    double sigma;
+    int32_t m_bits;
+    int32_t nthr;
+    int32_t gray;
+    int32_t j;
+    uint32_t known;
+    int32_t out_f64;
+    double t[kMaxThr];
+};
+
+__device__ __forceinline__ int interval_label(const QuantArgs& a, double y)
+{
+    int k = 0;
+    for (int q = 0; q < a.nthr; ++q) k += (a.t[q] <= y) ? 1 : 0;   // #{i : t_i <= y}
+    return a.gray ? (k ^ (k >> 1)) : k;
+}
+
+// Four consecutive samples per thread: two 16-byte loads of y and one 4-byte
+// store per slice row.
+__global__ __launch_bounds__(256) void k_quantize(QuantArgs a)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x * 4;
+    for (int64_t i0 = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4; i0 < a.n; i0 += stride) {
+        if (a.vec) {
+            const double4 yv = *reinterpret_cast<const double4*>(a.y + i0);
+            const int g0 = interval_label(a, yv.x), g1 = interval_label(a, yv.y);
+            const int g2 = interval_label(a, yv.z), g3 = interval_label(a, yv.w);
+            for (int j = 0; j < a.m_bits; ++j) {
+                uint32_t w = uint32_t((g0 >> j) & 1) | (uint32_t((g1 >> j) & 1) << 8) |
+                             (uint32_t((g2 >> j) & 1) << 16) | (uint32_t((g3 >> j) & 1) << 24);
+                *reinterpret_cast<uint32_t*>(a.slices + int64_t(j) * a.n + i0) = w;
+            }
+        } else {
+            for (int64_t i = i0; i < i0 + 4 && i < a.n; ++i) {
+                const int g = interval_label(a, a.y[i]);
+                for (int j = 0; j < a.m_bits; ++j) a.slices[int64_t(j) * a.n + i] = uint8_t((g >> j) & 1);
+            }
+        }
+    }
+}
+
+// ln Phi(z), Phi the standard normal CDF.  Right of zero via log1p of the
+// upper tail; moderately left via erfc; far left via the scaled complementary
+// error function erfcx(u) = exp(u^2) erfc(u), so that ln Phi stays finite.
+__device__ __forceinline__ double ln_phi(double z)
+{
+    if (z > 0.0) return log1p(-0.5 * erfc(z * M_SQRT1_2));
+    if (z > -5.0) return log(0.5 * erfc(-z * M_SQRT1_2));
+    return log(0.5 * erfcx(-z * M_SQRT1_2)) - 0.5 * z * z;
+}
+
+// ln(e^a - e^b) for b <= a.
+__device__ __forceinline__ double log_diff(double a, double b)
+{
+    return a + log(-expm1(b - a));
+}
+
+// ln Pr(lo <= Z < hi), Z standard normal, lo < hi.
+__device__ __forceinline__ double ln_interval(double lo, double hi)
+{
+    if (lo >= 0.0) return log_diff(ln_phi(-lo), ln_phi(-hi));      // both in the upper tail
+    if (hi <= 0.0) return log_diff(ln_phi(hi), ln_phi(lo));        // both in the lower tail
+    const double out = 0.5 * erfc(-lo * M_SQRT1_2) + 0.5 * erfc(hi * M_SQRT1_2);
+    return log1p(-out);                                            // straddles the mean
+}
+
+__device__ __forceinline__ void lse_push(double& mx, double& s, double v)
+{
+    if (v == -INFINITY) return;
+    if (v > mx) {
+        s = s * exp(mx - v) + 1.0;
+        mx = v;
+    } else {
+        s += exp(v - mx);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int K = 1 << a.m_bits;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const double x = a.x[i];
+        uint32_t kb = 0;
+        for (int q = 0; q < a.m_bits; ++q)
+            if ((a.known >> q) & 1u) kb |= uint32_t(a.slices[int64_t(q) * a.n + i] & 1) << q;
+        double m0 = -INFINITY, s0 = 0.0, m1 = -INFINITY, s1 = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const uint32_t g = a.gray ? uint32_t(k ^ (k >> 1)) : uint32_t(k);
+            if ((g & a.known) != kb) continue;            // disagrees with a known slice bit
+            const double lo = (k == 0) ? -INFINITY : (a.t[k - 1] - x) / a.sigma;
+            const double hi = (k == K - 1) ? INFINITY : (a.t[k] - x) / a.sigma;
+            const double lp = ln_interval(lo, hi);
+            if ((g >> a.j) & 1u) lse_push(m1, s1, lp);
+            else lse_push(m0, s0, lp);
+        }
+        const double L = (m0 + log(s0)) - (m1 + log(s1));
+        if (a.out_f64) static_cast<double*>(a.out)[i] = L;
+        else static_cast<float*>(a.out)[i] = float(L);
+    }
+}
+
+static int grid_for(int64_t items, int per_block)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return int(g);
+}
+
+static cvr_status check_thresholds(const char* fn, const double* t, int32_t m_bits)
+{
+    if (m_bits < 1 || m_bits > 8) return fail(CVR_EINVAL, std::string(fn) + ": m_bits must be in [1, 8]");
+    if (!t) return fail(CVR_EINVAL, std::string(fn) + ": thresholds is NULL");
+    const int nthr = (1 << m_bits) - 1;
+    for (int q = 0; q < nthr; ++q) {
+        if (!std::isfinite(t[q])) return fail(CVR_EINVAL, std::string(fn) + ": non-finite threshold");
+        if (q > 0 && !(t[q] > t[q - 1])) return fail(CVR_EINVAL, std::string(fn) + ": thresholds not strictly ascending");
+    }
+    return CVR_OK;
+}
+
+}  // namespace cvr
+
+using namespace cvr;
+
+extern "C" cvr_status slice_quantize(const double* y, int64_t n, const double* thresholds, int32_t m_bits,
+                                     int32_t labelling, uint8_t* slices, void* stream)
+{
+    if (n < 0) return fail(CVR_EINVAL, "slice_quantize: n < 0");
+    if (labelling != CVR_GRAY && labelling != CVR_BINARY) return fail(CVR_EINVAL, "slice_quantize: bad labelling");
+    if (cvr_status st = check_thresholds("slice_quantize", thresholds, m_bits)) return st;
+    if (n == 0) return CVR_OK;
+    if (!y || !slices) return fail(CVR_EINVAL, "slice_quantize: NULL y or slices");
+    QuantArgs a{};
+    a.y = y;
+    a.slices = slices;
+    a.n = n;
+    a.m_bits = m_bits;
+    a.nthr = (1 << m_bits) - 1;
+    a.gray = labelling == CVR_GRAY;
+    for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
+    a.vec = (n % 4 == 0) && (reinterpret_cast<uintptr_t>(y) % 32 == 0) &&
+            (reinterpret_cast<uintptr_t>(slices) % 4 == 0);
+    ProfScope prof(CVR_PROF_QUANTIZE, hipStream_t(stream));
+    hipLaunchKernelGGL(k_quantize, dim3(grid_for((n + 3) / 4, 256)), dim3(256), 0, hipStream_t(stream), a);
+    return check_launch("slice_quantize");
+}
+
+extern "C" cvr_status slice_llr(const double* x, int64_t n, double sigma_n, const double* thresholds, int32_t m_bits,
+                                int32_t labelling, int32_t j, uint32_t known_mask, const uint8_t* slices,
+                                int32_t out_dtype, void* llr_out, void* stream)
+{
+    if (n < 0) return fail(CVR_EINVAL, "slice_llr: n < 0");
+    if (labelling != CVR_GRAY && labelling != CVR_BINARY) return fail(CVR_EINVAL, "slice_llr: bad labelling");
+    if (cvr_status st = check_thresholds("slice_llr", thresholds, m_bits)) return st;
+    if (!(sigma_n > 0.0) || !std::isfinite(sigma_n)) return fail(CVR_EINVAL, "slice_llr: sigma_n must be finite and > 0");
+    if (j < 0 || j >= m_bits) return fail(CVR_EINVAL, "slice_llr: j out of range");
+    if ((known_mask >> j) & 1u) return fail(CVR_EINVAL, "slice_llr: slice j is already in known_mask");
+    if (known_mask >> m_bits) return fail(CVR_EINVAL, "slice_llr: known_mask has bits >= m_bits");
+    if (out_dtype != CVR_F32 && out_dtype != CVR_F64) return fail(CVR_EINVAL, "slice_llr: out_dtype must be F32 or F64");
+    if (n == 0) return CVR_OK;
+    if (!x || !llr_out) return fail(CVR_EINVAL, "slice_llr: NULL x or llr_out");
+    if (known_mask && !slices) return fail(CVR_EINVAL, "slice_llr: known_mask set but slices is NULL");
+    LlrArgs a{};
+    a.x = x;
+    a.slices = slices;
+    a.out = llr_out;
+    a.n = n;
+    a.sigma = sigma_n;
+    a.m_bits = m_bits;
+    a.nthr = (1 << m_bits) - 1;
+    a.gray = labelling == CVR_GRAY;
+    a.j = j;
+    a.known = known_mask;
+    a.out_f64 = out_dtype == CVR_F64;
+    for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
+    ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
+    hipLaunchKernelGGL(k_slice_llr, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    return check_launch("slice_llr");
+}

@@ -320,3 +320,48 @@ def test_unrolled_nms_gradient_matches_central_differences():
     lm = llr.copy(); lm[1, v] -= h
     fd = (oracle.nms_unrolled(code, lp, s, bits, w)["loss"] - oracle.nms_unrolled(code, lm, s, bits, w)["loss"]) / (2 * h)
     assert abs(fd - g["dllr"][1, v]) <= 1e-6 * max(abs(fd), 1e-8)
+
+
+# --------------------------------------------------------------------------
+# binary32 mode of the oracle
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("algo", [oracle.SP, oracle.NMS])
+def test_prec32_values_are_floats_and_close_to_fp64(algo):
+    code = I.lambda_half_rate_spec(2048).to_csr()
+    rng = np.random.default_rng(21)
+    bits = rng.integers(0, 2, (3, code.n)).astype(np.uint8)
+    llr = I.bpsk_llr(bits, 0.6, 22)
+    s, _ = oracle.syndrome(code, bits)
+    a = oracle.decode(code, llr, s, algo=algo, alpha=0.8, max_iter=1, early_stop=False, trace=True)
+    b = oracle.decode(code, llr, s, algo=algo, alpha=0.8, max_iter=1, early_stop=False, trace=True, prec32=True)
+    # every posterior of the binary32 run is a float
+    np.testing.assert_array_equal(b["post"], b["post"].astype(np.float32).astype(np.float64))
+    # one iteration: the two agree to a few binary32 roundings of the sum
+    err = np.abs(a["post"] - b["post"]) / a["scale_trace"][:, 1]
+    assert err.max() < 16 * 2.0 ** -24
+
+
+def test_prec32_min_sum_hand_computed_row():
+    H = np.ones((1, 3), np.uint8)
+    code = _csr_from_dense(H)
+    L = np.array([0.1, -0.3, 2.0])
+    r = oracle.decode(code, L[None, :], None, algo=oracle.NMS, max_iter=1, early_stop=False,
+                      alpha=0.8, prec32=True)
+    f = np.float32
+    w = f(0.8)
+    Lf = L.astype(np.float32)
+    # v0: others (-0.3, 2.0): sign -, min 0.3;  v1: others (0.1, 2.0): +, 0.1;  v2: (0.1, -0.3): -, 0.1
+    c2v = np.array([-(w * f(0.3)), w * f(0.1), -(w * f(0.1))], dtype=np.float32)
+    expect = (Lf + c2v).astype(np.float64)
+    np.testing.assert_array_equal(r["post"][0], expect)
+
+
+def test_prec32_half_store_is_rounding_of_the_float_message():
+    H = np.ones((1, 2), np.uint8)
+    code = _csr_from_dense(H)
+    L = np.array([[1.0, 1.0 + 3 * 2.0 ** -12]])     # 0.75 * that lies between halves
+    r = oracle.decode(code, L, None, algo=oracle.NMS, alpha=0.75, max_iter=1, early_stop=False,
+                      prec32=True, store_half=True)
+    msg = np.float32(0.75) * np.float32(L[0, 1])
+    assert r["post"][0, 0] == np.float32(np.float32(1.0) + np.float32(np.float16(msg)))
