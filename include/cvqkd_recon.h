@@ -173,7 +173,15 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *  weights   device fp32 [max_iter][n_types] or NULL.
  *  trace     device [max_iter + 1][total_n] of the math dtype, or NULL: the
  *            posteriors after every iteration (row 0 = channel LLRs); rows past
- *            a frame's stop are not written for that frame.                  */
+ *            a frame's stop are not written for that frame.
+ *  schedule  how the flooding iterations are launched (results are identical):
+ *            CVR_SCHED_PASSES: two kernel launches per iteration over all
+ *            frames (any code); CVR_SCHED_PERSISTENT: one persistent launch in
+ *            which each workgroup iterates whole frames to their stop (QC codes
+ *            with <= 2048 circulants and <= 512 block rows/columns, else
+ *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible.     */
+enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2 };
+
 typedef struct {
     int32_t algo;
     int32_t max_iter;          /* >= 0 */
@@ -182,6 +190,7 @@ typedef struct {
     int32_t store;
     float alpha;
     float msg_clamp;           /* > 0; SP only */
+    int32_t schedule;
     const float* weights;
     void* trace;
 } cvr_decode_params;
@@ -216,7 +225,8 @@ enum {
     CVR_PROF_CHECK = 3,        /* decoder check-node pass (one per iteration)     */
     CVR_PROF_VAR = 4,          /* decoder variable-node pass (one per iteration)  */
     CVR_PROF_DEC_SETUP = 5,    /* decoder set-up and output passes                */
-    CVR_PROF_OTHER = 6
+    CVR_PROF_FRAMES = 6,       /* persistent decoder (whole decode in one launch) */
+    CVR_PROF_OTHER = 7
 };
 
 /* on != 0: every later launch of the library is bracketed by two HIP events on

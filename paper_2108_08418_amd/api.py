@@ -19,6 +19,7 @@ from ._lib import DecodeParams, Frame, check, load
 GRAY, BINARY = 0, 1
 SP, NMS = 0, 1
 F64, F32, F16 = 0, 1, 2
+SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT = 0, 1, 2
 
 _TORCH_OF = {F64: torch.float64, F32: torch.float32}
 
@@ -146,11 +147,13 @@ class Params:
     alpha: float = 0.75
     msg_clamp: float = 50.0
     weights: torch.Tensor | None = None   # device fp32 [max_iter, n_types]
+    schedule: int = SCHED_AUTO
 
     def c_struct(self, trace: torch.Tensor | None = None) -> DecodeParams:
         p = DecodeParams()
         p.algo, p.max_iter, p.early_stop = int(self.algo), int(self.max_iter), int(bool(self.early_stop))
         p.math, p.store, p.alpha, p.msg_clamp = int(self.math), int(self.store), float(self.alpha), float(self.msg_clamp)
+        p.schedule = int(self.schedule)
         if self.weights is not None:
             if self.weights.dtype != torch.float32:
                 raise ValueError("weights must be float32")
@@ -265,7 +268,7 @@ def version() -> int:
 # ---------------------------------------------------------------------------
 # launch timing
 # ---------------------------------------------------------------------------
-PROF_QUANTIZE, PROF_LLR, PROF_SYNDROME, PROF_CHECK, PROF_VAR, PROF_DEC_SETUP, PROF_OTHER = range(7)
+PROF_QUANTIZE, PROF_LLR, PROF_SYNDROME, PROF_CHECK, PROF_VAR, PROF_DEC_SETUP, PROF_FRAMES, PROF_OTHER = range(8)
 
 
 def profile_enable(on: bool = True) -> None:

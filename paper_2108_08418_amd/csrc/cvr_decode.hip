@@ -22,13 +22,38 @@
 // Both sum in the same order, so they give bit-identical results.
 #include "cvr_internal.h"
 
+#include <algorithm>
+
 namespace cvr {
 
 // ---------------------------------------------------------------------------
 // arithmetic helpers
 // ---------------------------------------------------------------------------
-// phi(x) = -ln tanh(x/2) = ln(1 + 2/(e^x - 1)); phi(0) = inf, phi(inf) = 0.
-__device__ __forceinline__ float phi(float x) { return log1pf(2.0f / expm1f(x)); }
+// phi(x) = -ln tanh(x/2) = 2 atanh(e^-x) = ln((1 + e^-x) / (1 - e^-x)), x >= 0;
+// phi(0) = inf, phi(inf) = 0, and phi(phi(x)) = x.
+// binary32: one hardware exponential, then either the odd series of 2 atanh(u)
+// (u = e^-x < 1/4, truncation < 5e-9 relative) or one hardware logarithm of
+// (1 + u) / (1 - u), with 1 - u from its Taylor series below x = 1/8 where the
+// subtraction would cancel.  Relative error stays near 2e-6.
+__device__ __forceinline__ float phi(float x)
+{
+    const float u = __expf(-x);
+    if (u < 0.25f) {
+        const float u2 = u * u;
+        float p = 1.0f / 11.0f;
+        p = p * u2 + 1.0f / 9.0f;
+        p = p * u2 + 1.0f / 7.0f;
+        p = p * u2 + 1.0f / 5.0f;
+        p = p * u2 + 1.0f / 3.0f;
+        p = p * u2 + 1.0f;
+        return 2.0f * u * p;
+    }
+    const float omu = (x < 0.125f)
+        ? x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))))
+        : 1.0f - u;
+    return __logf(__fdividef(1.0f + u, omu));
+}
+// binary64: the library's correctly rounded-ish expm1 / log1p.
 __device__ __forceinline__ double phi(double x) { return log1p(2.0 / expm1(x)); }
 
 template <typename S> struct StoreT;
@@ -304,6 +329,136 @@ __global__ __launch_bounds__(kTile) void k_var_qc(DecArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// persistent frame-per-workgroup decoder for quasi-cyclic codes
+// ---------------------------------------------------------------------------
+// Each workgroup takes whole frames from an atomic queue and runs all of a
+// frame's iterations itself: the two half-iterations are separated by
+// __syncthreads only, so frames stop independently, no grid-wide barrier or
+// per-iteration launch exists, and a frame's state is touched by one CU only
+// (it stays in that XCD's L2 / the Infinity Cache while the frame is decoded).
+// The protograph tables of the current code are cached in LDS.
+constexpr int kFrameThreads = 1024;
+constexpr int kMaxLdsBlocks = 2048;
+constexpr int kMaxLdsDim = 512;
+
+struct LdsCode {
+    int32_t rptr[kMaxLdsDim + 1];
+    int32_t cptr[kMaxLdsDim + 1];
+    int2 row[kMaxLdsBlocks];   // x = shift, y = block column | type << 20 (block id = position)
+    int2 col[kMaxLdsBlocks];   // x = shift, y = block id
+};
+
+template <typename M, typename S, int ALGO, int MAXD>
+__global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F)
+{
+    __shared__ LdsCode sc;
+    __shared__ int32_t s_frame;
+    __shared__ int32_t s_unsat[2];
+    const int tid = int(threadIdx.x);
+    int cur = -1;
+    for (;;) {
+        if (tid == 0) s_frame = atomicAdd(queue, 1);
+        __syncthreads();
+        const int f = s_frame;
+        if (f >= F) break;
+        const DevFrame fr = a.frames[f];
+        const DevCode& cd = a.codes[fr.code];
+        if (fr.code != cur) {
+            for (int q = tid; q <= cd.mb; q += kFrameThreads) sc.rptr[q] = cd.qrow_ptr[q];
+            for (int q = tid; q <= cd.nb; q += kFrameThreads) sc.cptr[q] = cd.qcol_ptr[q];
+            for (int q = tid; q < cd.NB; q += kFrameThreads) {
+                const QcBlock br = cd.qrow[q];
+                sc.row[q] = make_int2(br.shift, br.other | (br.type << 20));
+                const QcBlock bc = cd.qcol[q];
+                sc.col[q] = make_int2(bc.shift, bc.blk);
+            }
+            cur = fr.code;
+        }
+        const int Z = cd.Z;
+        const int m = cd.mb * Z, n = cd.nb * Z;
+        const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
+        M* Lp = static_cast<M*>(a.post) + fr.vn_off;
+        const M* Lc = static_cast<const M*>(a.llr) + fr.vn_off;
+        S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+        const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
+        M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
+        for (int v = tid; v < n; v += kFrameThreads) {
+            const M l = Lc[v];
+            Lp[v] = l;
+            if (tr) tr[v] = l;
+        }
+        if (tid == 0) {
+            s_unsat[0] = 0;
+            s_unsat[1] = 0;
+        }
+        __syncthreads();
+        for (int t = 0;; ++t) {
+            // check pass: syndrome test of Lpost(t) and c2v(t+1)
+            int bad = 0;
+            const float* wt = a.weights ? a.weights + int64_t(t) * a.n_types : nullptr;
+            for (int r = tid; r < m; r += kFrameThreads) {
+                const int i = zsh >= 0 ? (r >> zsh) : r / Z;
+                const int k = r - i * Z;
+                const int q0 = sc.rptr[i];
+                const int d = sc.rptr[i + 1] - q0;
+                const int sbit = syn ? (syn[r] & 1) : 0;
+                int par = sbit;
+                bool nan = false;
+                M x[MAXD];
+#pragma unroll
+                for (int q = 0; q < MAXD; ++q) {
+                    x[q] = M(0);
+                    if (q < d) {
+                        const int2 e = sc.row[q0 + q];
+                        int uu = k + e.x;
+                        uu = uu >= Z ? uu - Z : uu;
+                        const M lp = Lp[(e.y & 0xfffff) * Z + uu];
+                        par ^= (lp < M(0)) ? 1 : 0;
+                        nan |= (lp != lp);
+                        x[q] = (t == 0) ? lp : lp - M(StoreT<S>::get(msg[(q0 + q) * Z + k]));
+                    }
+                }
+                bad += par | (nan ? 1 : 0);
+                if (t < a.T) {
+                    auto weight = [&](int q) -> M { return wt ? M(wt[sc.row[q0 + q].y >> 20]) : M(a.alpha); };
+                    auto emit = [&](int q, M v) { msg[(q0 + q) * Z + k] = StoreT<S>::put(v); };
+                    check_rule<M, ALGO, MAXD>(x, d, sbit, M(a.clamp), weight, emit);
+                }
+            }
+            if (bad) atomicAdd(&s_unsat[t & 1], bad);
+            __syncthreads();
+            const int u = s_unsat[t & 1];
+            if ((a.early_stop && u == 0) || t >= a.T) {
+                if (tid == 0) {
+                    a.iters[f] = t;
+                    a.ok[f] = uint8_t(u == 0);
+                }
+                break;
+            }
+            if (tid == 0) s_unsat[(t + 1) & 1] = 0;
+            // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1), block rows ascending
+            for (int v = tid; v < n; v += kFrameThreads) {
+                const int j = zsh >= 0 ? (v >> zsh) : v / Z;
+                const int uu = v - j * Z;
+                const int q0 = sc.cptr[j];
+                const int dv = sc.cptr[j + 1] - q0;
+                M acc = Lc[v];
+                for (int q = 0; q < dv; ++q) {
+                    const int2 e = sc.col[q0 + q];
+                    int k = uu - e.x;
+                    k = k < 0 ? k + Z : k;
+                    acc += M(StoreT<S>::get(msg[e.y * Z + k]));
+                }
+                Lp[v] = acc;
+                if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
+            }
+            __syncthreads();
+        }
+        for (int v = tid; v < n; v += kFrameThreads) a.bits[fr.vn_off + v] = Lp[v] < M(0) ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // set-up and output passes (over the generic variable tiles)
 // ---------------------------------------------------------------------------
 template <typename M>
@@ -380,7 +535,7 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 static size_t msize(int32_t p) { return p == CVR_F64 ? 8 : (p == CVR_F32 ? 4 : 2); }
 
 struct WsLayout {
-    size_t c2v, post, active, unsat, total;
+    size_t c2v, post, active, unsat, queue, total;
 };
 
 static WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
@@ -395,6 +550,8 @@ static WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
     off = align256(off + size_t(b->F) * 4);
     w.unsat = off;
     off = align256(off + size_t(b->F) * 8);
+    w.queue = off;
+    off = align256(off + 4);
     w.total = off;
     return w;
 }
@@ -411,6 +568,7 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
     if (p->math == CVR_F64 && p->store != CVR_F64)
         return fail(CVR_EUNSUPPORTED, "decode: F64 math is implemented with F64 storage only");
     if (p->algo == CVR_SP && !(p->msg_clamp > 0.0f)) return fail(CVR_EINVAL, "decode: msg_clamp must be > 0");
+    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_PERSISTENT) return fail(CVR_EINVAL, "decode: bad schedule");
     return CVR_OK;
 }
 
@@ -459,19 +617,66 @@ static cvr_status run_decode(const cvr_batch_s* b, DecArgs a, hipStream_t s, boo
     return check_launch("decode final");
 }
 
-template <typename M, typename S, int ALGO>
-static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc)
+static int device_cus()
 {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, queue, int64_t(1));
+    if (cvr_status st = check_launch("decode queue reset")) return st;
+    static int per_cu = 0;      // resident workgroups per CU of this instantiation
+    if (per_cu == 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_frames_qc<M, S, ALGO, MAXD>, kFrameThreads, 0) != hipSuccess || v < 1)
+            v = 1;
+        per_cu = v;
+    }
+    const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
+    ProfScope prof(CVR_PROF_FRAMES, s);
+    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD>), dim3(grid), dim3(kFrameThreads), 0, s, a, queue, b->F);
+    return check_launch("decode (persistent)");
+}
+
+template <typename M, typename S, int ALGO>
+static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue)
+{
+    if (frames) {
+        if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s);
+        if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s);
+        return run_frames<M, S, ALGO, 32>(b, a, queue, s);
+    }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
     return run_decode<M, S, ALGO, 32>(b, a, s, qc);
 }
 
 template <typename M, typename S>
-static cvr_status dispatch_algo(const cvr_batch_s* b, int algo, DecArgs a, hipStream_t s, bool qc)
+static cvr_status dispatch_algo(const cvr_batch_s* b, int algo, DecArgs a, hipStream_t s, bool qc, bool frames,
+                                int32_t* queue)
 {
-    if (algo == CVR_SP) return dispatch_deg<M, S, CVR_SP>(b, a, s, qc);
-    return dispatch_deg<M, S, CVR_NMS>(b, a, s, qc);
+    if (algo == CVR_SP) return dispatch_deg<M, S, CVR_SP>(b, a, s, qc, frames, queue);
+    return dispatch_deg<M, S, CVR_NMS>(b, a, s, qc, frames, queue);
+}
+
+// The persistent path needs a quasi-cyclic batch whose protograph tables fit in LDS.
+static bool frames_fit(const cvr_batch_s* b)
+{
+    if (!b->all_qc) return false;
+    for (const cvr_code_t c : b->codes)
+        if (c->dev.NB > kMaxLdsBlocks || c->dev.mb > kMaxLdsDim || c->dev.nb > kMaxLdsDim || c->dev.Z >= (1 << 20))
+            return false;
+    return true;
 }
 
 }  // namespace cvr
@@ -521,9 +726,19 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
     a.n_types = batch->max_types;
     const hipStream_t s = hipStream_t(stream);
     const bool qc = batch->all_qc;
-    if (params->math == CVR_F64) return dispatch_algo<double, double>(batch, params->algo, a, s, qc);
-    if (params->store == CVR_F32) return dispatch_algo<float, float>(batch, params->algo, a, s, qc);
-    return dispatch_algo<float, __half>(batch, params->algo, a, s, qc);
+    bool frames = false;
+    if (params->schedule == CVR_SCHED_PERSISTENT) {
+        if (!frames_fit(batch))
+            return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the persistent schedule needs QC codes with <= 2048 "
+                                          "circulants and <= 512 block rows/columns");
+        frames = true;
+    } else if (params->schedule == CVR_SCHED_AUTO) {
+        frames = frames_fit(batch);
+    }
+    int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
+    if (params->math == CVR_F64) return dispatch_algo<double, double>(batch, params->algo, a, s, qc, frames, queue);
+    if (params->store == CVR_F32) return dispatch_algo<float, float>(batch, params->algo, a, s, qc, frames, queue);
+    return dispatch_algo<float, __half>(batch, params->algo, a, s, qc, frames, queue);
 }
 
 extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,

@@ -28,7 +28,7 @@ cvr_status check_launch(const char* what);
 
 // Opt-in launch timing (cvr_profile_enable): brackets the launches made in its
 // scope with HIP events on stream s.
-constexpr int kProfKinds = 8;
+constexpr int kProfKinds = 8;   // CVR_PROF_* kinds
 class ProfScope {
 public:
     ProfScope(int kind, hipStream_t s);

@@ -285,23 +285,52 @@ def _lambda_columns(nb: int):
     return col_deg, col_type
 
 
+def _chain_base_matrix(col_deg: np.ndarray, mb: int, rng: np.random.Generator) -> np.ndarray:
+    """Binary protograph whose degree-2 columns form one path through the rows
+    (so no cycle runs through degree-2 columns only: such cycles lift to
+    low-weight codewords), the other columns filling the least-loaded rows.
+    Row order and tie-breaking are seeded."""
+    nb = len(col_deg)
+    base = np.zeros((mb, nb), dtype=np.uint8)
+    rows = rng.permutation(mb)
+    d2 = np.nonzero(col_deg == 2)[0]
+    if len(d2) >= mb:
+        raise ValueError("too many degree-2 columns for an acyclic chain")
+    for k, c in enumerate(d2):
+        base[rows[k], c] = 1
+        base[rows[k + 1], c] = 1
+    for c in np.nonzero(col_deg != 2)[0]:
+        load = base.sum(1) + rng.random(mb) * 0.5
+        base[np.argsort(load, kind="stable")[: col_deg[c]], c] = 1
+    return base
+
+
+def _lambda_qc_code(nb: int, mb: int, Z: int, seed: int, name: str) -> QcCode:
+    col_deg, col_type = _lambda_columns(nb)
+    rng = np.random.default_rng(seed)
+    p = rng.permutation(nb)
+    col_deg, col_type = col_deg[p], col_type[p]
+    base = _chain_base_matrix(col_deg, mb, rng)
+    shift = _assign_shifts(base, Z, rng)
+    btype = np.where(shift >= 0, col_type[None, :], 0).astype(np.uint8)
+    return QcCode(nb, mb, Z, shift.astype(np.int32), btype, 3, name=name)
+
+
 def slice_code_spec(slice_j: int, n: int, seed: int = 2108) -> QcCode:
     """Seeded QC code for coded slice ``slice_j`` (2 or 3) of the 16-level,
     4-slice setup at SNR 3: lambda(x) = 0.25x + 0.3x^2 + 0.45x^7 over nb = 128
-    block columns.  Rates follow the selection loop of Sec. V-B: start 10 %
-    below the slice capacity and step down by 0.05 while the code fails its
-    frame-error test.  Slice 3 (C = 0.5469) keeps 0.9 C -> mb = 65,
-    R = 0.4921875; slice 2 (C = 0.3153) needs two steps, 0.9 C - 0.10 ->
-    mb = 104, R = 0.1875.  Column permutation and circulant shifts are seeded."""
+    block columns, degree-2 columns chained (see ``_chain_base_matrix``).
+
+    Rates follow the selection loop of Sec. V-B: start 10 % below the slice
+    capacity and step down by 0.05 while the code fails its frame-error test.
+    Slice 2 (C = 0.3153): 0.284 and 0.234 fail, 0.184 passes -> mb = 104,
+    R = 0.1875.  Slice 3 (C = 0.5469): 0.492 fails, 0.442 passes -> mb = 71,
+    R = 0.4453125.  Column permutation, row order and shifts are seeded."""
     nb = 128
-    mb = {2: 104, 3: 65}[slice_j]
+    mb = {2: 104, 3: 71}[slice_j]
     if n % nb:
         raise ValueError("n must be a multiple of 128")
-    col_deg, col_type = _lambda_columns(nb)
-    rng = np.random.default_rng(seed * 7 + slice_j)
-    p = rng.permutation(nb)
-    return qc_protograph_code(nb, mb, n // nb, col_deg[p], seed * 131 + slice_j + 17 * (n // nb),
-                              col_type[p], 3, name=f"slice{slice_j}-qc n{n}")
+    return _lambda_qc_code(nb, mb, n // nb, seed * 131 + slice_j * 7 + 17 * (n // nb), f"slice{slice_j}-qc n{n}")
 
 
 def lambda_half_rate_spec(n: int, seed: int = 1650) -> QcCode:
@@ -309,11 +338,7 @@ def lambda_half_rate_spec(n: int, seed: int = 1650) -> QcCode:
     nb, mb = 128, 64
     if n % nb:
         raise ValueError("n must be a multiple of 128")
-    col_deg, col_type = _lambda_columns(nb)
-    rng = np.random.default_rng(seed)
-    p = rng.permutation(nb)
-    return qc_protograph_code(nb, mb, n // nb, col_deg[p], seed + n // nb, col_type[p], 3,
-                              name=f"lambda-r1/2-qc n{n}")
+    return _lambda_qc_code(nb, mb, n // nb, seed + n // nb, f"lambda-r1/2-qc n{n}")
 
 
 def met_rate_tenth_spec(n: int, seed: int = 16) -> QcCode:

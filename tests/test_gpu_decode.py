@@ -107,16 +107,29 @@ def test_slice_stage_sp_fp32_qc(j):
     np.testing.assert_array_equal(s_chk, syn[ok])
 
 
-def test_qc_and_generic_paths_are_bit_identical():
-    print("[decode qc vs generic]", flush=True)
+def test_layouts_and_schedules_are_bit_identical():
+    """Explicit CSR per-pass, QC per-pass and QC persistent decoding sum in the
+    same order and must agree bit for bit."""
+    print("[decode layouts/schedules]", flush=True)
     n, F = 16384, 6
     qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=99)
-    for p in (api.Params(algo=api.SP, max_iter=40, math=api.F32, store=api.F32),
-              api.Params(algo=api.NMS, max_iter=40, math=api.F32, store=api.F16, alpha=0.8)):
-        a = _decode_gpu(api.Code.from_qc(qc), F, L, syn, p)
-        b = _decode_gpu(api.Code.from_csr(csr), F, L, syn, p)
-        for k in ("bits", "post", "iters", "ok"):
-            np.testing.assert_array_equal(a[k], b[k])
+    for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8),
+                 dict(algo=api.NMS, store=api.F32, alpha=0.7)):
+        runs = []
+        for code, sched in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT), (api.Code.from_qc(qc), api.SCHED_PASSES),
+                            (api.Code.from_csr(csr), api.SCHED_PASSES)):
+            p = api.Params(max_iter=40, math=api.F32, schedule=sched, **base)
+            runs.append(_decode_gpu(code, F, L, syn, p, trace=True))
+        for r in runs[1:]:
+            for k in ("bits", "post", "iters", "ok", "trace"):
+                np.testing.assert_array_equal(np.nan_to_num(runs[0][k], nan=1e30), np.nan_to_num(r[k], nan=1e30))
+
+
+def test_persistent_schedule_rejects_explicit_codes():
+    csr = inputs.regular_code(1024, 3, 6, seed=1)
+    p = api.Params(algo=api.SP, max_iter=5, math=api.F32, store=api.F32, schedule=api.SCHED_PERSISTENT)
+    with pytest.raises(api._lib.CvrError, match="CVR_EUNSUPPORTED"):
+        _decode_gpu(api.Code.from_csr(csr), 2, np.zeros((2, 1024)), None, p)
 
 
 @pytest.mark.parametrize("store", [api.F32, api.F16])
