@@ -50,10 +50,40 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent"])
+    ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
+    ap.add_argument("--rows", type=int, default=0, help="check rows per thread per step (0 = default)")
     ap.add_argument("--cpu-frames", type=int, default=16, help="sub-blocks per stage in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2108)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def csrc_hash() -> str:
+    import hashlib
+    from pathlib import Path
+    h = hashlib.sha256()
+    for p in sorted((Path(ROOT) / "paper_2108_08418_amd" / "csrc").glob("*")):
+        if p.suffix in (".hip", ".h"):
+            h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel_name: str):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded under
+    profiles/ for this kernel instantiation, or None when no record exists or
+    the kernel sources changed since the counters were taken."""
+    from pathlib import Path
+    sha = csrc_hash()
+    for p in sorted((Path(ROOT) / "profiles").glob("*_hbm_traffic.md")):
+        text = p.read_text()
+        if "```json" not in text:
+            continue
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if rec.get("source_sha") == sha and rec.get("kernel", "").startswith(kernel_name):
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], p.name
+    return None, None
 
 
 def frame_decode_bytes(iters, n, m, E, s_msg):
@@ -96,6 +126,15 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes}))
+        return
     wl = WORKLOADS[args.workload]
     N, n = wl["N"], wl["n"]
     F = N // n
@@ -115,7 +154,7 @@ def main():
     store = api.F32 if args.decoder == "sp" else api.F16
     sched = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT}[args.schedule]
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        schedule=sched)
+                        schedule=sched, wg_threads=args.wg, rows_per_step=args.rows)
     ws_bytes = max(api.decode_workspace_size(batches[j], params) for j in (2, 3))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     bob = torch.empty((M_BITS, N), dtype=torch.uint8, device=dev)
@@ -176,11 +215,17 @@ def main():
     var_ms, var_n = prof["var"]
     per_ms, per_n = prof["decode_persistent"]
     dom = max(("check", "var", "slice_llr", "decode_persistent"), key=lambda k: prof[k][0])
+    traffic = traffic_src = None
     if per_ms > 0:
-        roof_kernel = "persistent frame-per-workgroup decoder (k_frames_qc)"
+        wg = args.wg or 512
+        rows = args.rows or 1
+        mt = "float, float" if store == api.F32 else "float, __half"
+        inst = f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, {rows}>"
+        roof_kernel = inst
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
         iter_gbs = achieved
+        traffic, traffic_src = recorded_traffic(inst)
     else:
         roof_kernel = "decoder check-node pass (k_check_qc)"
         achieved = (args.steps * chk_bytes) / (chk_ms * 1e-3) / 1e9 if chk_ms > 0 else None
@@ -204,7 +249,8 @@ def main():
             "workload": args.workload, "pairs": N, "sub_block": n, "sub_blocks_per_slice": F,
             "slices": "16 equiprobable Gray intervals; slices 0-1 disclosed, 2 (R=0.1875) and 3 (R=0.4922) decoded",
             "decoder": ("sum-product" if algo == api.SP else f"normalized min-sum alpha={args.alpha}"),
-            "max_iter": args.max_iter, "schedule": args.schedule, "parallelism": "single GPU",
+            "max_iter": args.max_iter, "schedule": args.schedule, "wg_threads": args.wg, "rows_per_step": args.rows,
+            "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
@@ -213,7 +259,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_source": traffic_src,
+            "traffic_over_algorithmic": (traffic / (launch_bytes / launches)) if (traffic and launches) else None,
             "avg_launch_us": 1e3 * launch_ms / launches if launches else None,
             "algorithmic_bytes_per_launch": launch_bytes / launches if launches else None,
         },

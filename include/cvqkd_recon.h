@@ -179,7 +179,10 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            frames (any code); CVR_SCHED_PERSISTENT: one persistent launch in
  *            which each workgroup iterates whole frames to their stop (QC codes
  *            with <= 2048 circulants and <= 512 block rows/columns, else
- *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible.     */
+ *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible.
+ *  wg_threads, rows_per_step  tuning knobs of the persistent decoder that do
+ *            not change results: workgroup size 256, 512 or 1024 (0 = 512) and
+ *            check rows per thread per step, 1 or 2 (0 = 1).                  */
 enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2 };
 
 typedef struct {
@@ -191,6 +194,8 @@ typedef struct {
     float alpha;
     float msg_clamp;           /* > 0; SP only */
     int32_t schedule;
+    int32_t wg_threads;
+    int32_t rows_per_step;
     const float* weights;
     void* trace;
 } cvr_decode_params;

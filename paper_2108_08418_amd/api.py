@@ -148,12 +148,16 @@ class Params:
     msg_clamp: float = 50.0
     weights: torch.Tensor | None = None   # device fp32 [max_iter, n_types]
     schedule: int = SCHED_AUTO
+    wg_threads: int = 0
+    rows_per_step: int = 0
 
     def c_struct(self, trace: torch.Tensor | None = None) -> DecodeParams:
         p = DecodeParams()
         p.algo, p.max_iter, p.early_stop = int(self.algo), int(self.max_iter), int(bool(self.early_stop))
         p.math, p.store, p.alpha, p.msg_clamp = int(self.math), int(self.store), float(self.alpha), float(self.msg_clamp)
         p.schedule = int(self.schedule)
+        p.wg_threads = int(self.wg_threads)
+        p.rows_per_step = int(self.rows_per_step)
         if self.weights is not None:
             if self.weights.dtype != torch.float32:
                 raise ValueError("weights must be float32")

@@ -12,17 +12,8 @@ CSRC = PKG / "csrc"
 LIB = PKG / "libcvqkd_recon.so"
 ARCH = os.environ.get("CVR_OFFLOAD_ARCH", "gfx950")
 
-HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}",
-    "-O3",
-    "-std=c++17",
-    "-fPIC",
-    "-shared",
-    # keep the compiler from forming packed fp32 (v_pk_*_f32) instructions
-    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall",
-    "-Wno-unused-result",
-]
+# "-Xclang -target-feature -Xclang -packed-fp32-ops" keeps the compiler from
+# forming packed fp32 (v_pk_*_f32) instructions.
 
 
 def sources():
@@ -30,9 +21,27 @@ def sources():
 
 
 def build(verbose: bool = False) -> Path:
+    """Compiles every csrc/*.hip to an object in parallel, then links the library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = PKG / "_build"
+    objdir.mkdir(exist_ok=True)
+    common = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-Wall", "-Wno-unused-result", f"-I{ROOT / 'include'}", f"-I{CSRC}"]
+    procs = []
+    objs = []
+    for src in sources():
+        obj = objdir / (Path(src).stem + ".o")
+        objs.append(str(obj))
+        cmd = [hipcc, *common, "-c", src, "-o", str(obj)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd)))
+    for src, p in procs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, f"hipcc {src}")
     tmp = LIB.with_suffix(f".so.tmp{os.getpid()}")
-    cmd = [hipcc, *HIPCC_FLAGS, f"-I{ROOT / 'include'}", f"-I{CSRC}", *sources(), "-o", str(tmp)]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,0 +1,9 @@
+// Decoder instantiation: math double, message storage double, rule CVR_SP.
+#include "cvr_decode_impl.h"
+
+namespace cvr {
+CVR_DECL_DISPATCH(decode_f64_sp)
+{
+    return dispatch_deg<double, double, CVR_SP>(b, a, s, qc, frames, queue, wg, rows);
+}
+}  // namespace cvr

@@ -1,0 +1,650 @@
+// Batched flooding belief-propagation decoding of sub-blocks (Sec. III-A,
+// Sec. III-C) and syndrome checks (Sec. II Step 5).
+//
+// State kept between the two half-iterations of frame f:
+//   c2v  [msg_off .. msg_off + E)  check-to-variable messages (store dtype)
+//   Lpost[vn_off .. vn_off + n)    posteriors of the last finished iteration
+// The variable-to-check message is never stored: the check pass forms it as
+// Lpost[v] - c2v[e] from the two arrays above (for t = 0, c2v = 0).
+//
+// Iteration t (t = 0..T) of one frame is
+//   check pass:    count checks unsatisfied by the decisions of Lpost(t) and,
+//                  if t < T, compute c2v(t+1) from Lpost(t) and c2v(t);
+//   variable pass: if the count is 0 (early stop) or t == T the frame ends
+//                  at t; else Lpost(t+1) = Lch + sum_e c2v(t+1).
+// Every pass reads a per-frame `active` flag, so finished frames cost one
+// flag read per tile.  Two layouts share this schedule:
+//   generic  -- explicit CSR; messages in CSR order; one thread per check row
+//               / variable, gathers through col_idx / col_edge;
+//   QC       -- quasi-cyclic codes; messages block-major ([block][k]), so both
+//               passes touch consecutive addresses per wavefront and need no
+//               index arrays (the block tables are wave-uniform).
+// Both sum in the same order, so they give bit-identical results.
+#pragma once
+#include "cvr_internal.h"
+
+#include <algorithm>
+
+namespace cvr {
+
+// ---------------------------------------------------------------------------
+// arithmetic helpers
+// ---------------------------------------------------------------------------
+// phi(x) = -ln tanh(x/2) = 2 atanh(e^-x) = ln((1 + e^-x) / (1 - e^-x)), x >= 0;
+// phi(0) = inf, phi(inf) = 0, and phi(phi(x)) = x.
+// binary32: one hardware exponential, then either the odd series of 2 atanh(u)
+// (u = e^-x < 1/4, truncation < 5e-9 relative) or one hardware logarithm of
+// (1 + u) / (1 - u), with 1 - u from its Taylor series below x = 1/8 where the
+// subtraction would cancel.  Relative error stays near 2e-6.
+__device__ __forceinline__ float phi(float x)
+{
+    const float u = __expf(-x);
+    if (u < 0.25f) {
+        const float u2 = u * u;
+        float p = 1.0f / 11.0f;
+        p = p * u2 + 1.0f / 9.0f;
+        p = p * u2 + 1.0f / 7.0f;
+        p = p * u2 + 1.0f / 5.0f;
+        p = p * u2 + 1.0f / 3.0f;
+        p = p * u2 + 1.0f;
+        return 2.0f * u * p;
+    }
+    const float omu = (x < 0.125f)
+        ? x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))))
+        : 1.0f - u;
+    return __logf(__fdividef(1.0f + u, omu));
+}
+// binary64: the library's correctly rounded-ish expm1 / log1p.
+__device__ __forceinline__ double phi(double x) { return log1p(2.0 / expm1(x)); }
+
+template <typename S> struct StoreT;
+template <> struct StoreT<double> {
+    __device__ static double put(double v) { return v; }
+    __device__ static double get(double s) { return s; }
+};
+template <> struct StoreT<float> {
+    template <typename M> __device__ static float put(M v) { return float(v); }
+    __device__ static float get(float s) { return s; }
+};
+template <> struct StoreT<__half> {
+    // round to nearest even, saturating at the largest finite half (NaN kept)
+    __device__ static __half put(float v)
+    {
+        v = v > 65504.0f ? 65504.0f : (v < -65504.0f ? -65504.0f : v);
+        return __float2half_rn(v);
+    }
+    __device__ static float get(__half s) { return __half2float(s); }
+};
+
+template <typename M> __device__ __forceinline__ M mabs(M v) { return v < M(0) ? -v : v; }
+
+// Check-node rule on d <= MAXD incoming v2c values x[] (sign flags in negm).
+// Writes the outgoing messages through `emit(k, value)`.
+template <typename M, int ALGO, int MAXD, typename W, typename Emit>
+__device__ __forceinline__ void check_rule(const M (&x)[MAXD], int d, int syn, M clampv, W weight, Emit emit)
+{
+    uint32_t negm = 0;
+#pragma unroll
+    for (int k = 0; k < MAXD; ++k)
+        if (k < d && x[k] < M(0)) negm |= 1u << k;
+    const uint32_t tot = uint32_t(__popc(negm) & 1) ^ uint32_t(syn);
+    if (ALGO == CVR_SP) {
+        M a[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            M v = mabs(x[k]);
+            v = v > clampv ? clampv : v;
+            a[k] = (k < d) ? phi(v) : M(0);
+        }
+        // exclusive sums by prefix + suffix (no total-minus-self cancellation)
+        M suf[MAXD];
+        M acc = M(0);
+#pragma unroll
+        for (int k = MAXD - 1; k >= 0; --k) {
+            suf[k] = acc;
+            if (k < d) acc += a[k];
+        }
+        acc = M(0);
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+                const M mag = phi(acc + suf[k]);
+                const bool neg = (tot ^ ((negm >> k) & 1u)) != 0;
+                emit(k, neg ? -mag : mag);
+                acc += a[k];
+            }
+        }
+    } else {
+        M m1 = M(INFINITY), m2 = M(INFINITY);
+        int i1 = -1;
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+                const M v = mabs(x[k]);
+                if (v < m1) {
+                    m2 = m1;
+                    m1 = v;
+                    i1 = k;
+                } else if (v < m2) {
+                    m2 = v;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            if (k < d) {
+                const M mag = (k == i1) ? m2 : m1;
+                const bool neg = (tot ^ ((negm >> k) & 1u)) != 0;
+                const M w = weight(k);
+                emit(k, w * (neg ? -mag : mag));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+struct DecArgs {
+    const DevCode* codes;
+    const DevFrame* frames;
+    const Tile* tiles;
+    const void* llr;          // math dtype
+    const uint8_t* syn;       // may be NULL
+    void* c2v;                // store dtype
+    void* post;               // math dtype
+    void* trace;              // math dtype or NULL
+    uint8_t* bits;
+    int32_t* iters;
+    uint8_t* ok;
+    int32_t* active;          // [F]
+    int32_t* unsat;           // [F][2]
+    const float* weights;     // [T][n_types] or NULL
+    int64_t total_n;
+    float alpha;
+    float clamp;
+    int32_t t;
+    int32_t T;
+    int32_t early_stop;
+    int32_t n_types;
+};
+
+__device__ __forceinline__ void add_unsat(int32_t* slot, int pred)
+{
+    const int cnt = __syncthreads_count(pred);
+    if (threadIdx.x == 0 && cnt) atomicAdd(slot, cnt);
+}
+
+// ---------------------------------------------------------------------------
+// generic (explicit CSR) passes
+// ---------------------------------------------------------------------------
+template <typename M, typename S, int ALGO, int MAXD>
+__global__ __launch_bounds__(kTile) void k_check_generic(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int r = tl.a + int(threadIdx.x);
+    const M* Lp = static_cast<const M*>(a.post) + fr.vn_off;
+    S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    int bad = 0;
+    if (int(threadIdx.x) < count) {
+        const int e0 = cd.row_ptr[r];
+        const int d = cd.row_ptr[r + 1] - e0;
+        const int syn = a.syn ? (a.syn[fr.chk_off + r] & 1) : 0;
+        int par = syn;
+        bool nan = false;
+        M x[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            x[k] = M(0);
+            if (k < d) {
+                const M lp = Lp[cd.col_idx[e0 + k]];
+                par ^= (lp < M(0)) ? 1 : 0;
+                nan |= (lp != lp);
+                x[k] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(msg[e0 + k]));
+            }
+        }
+        bad = par | (nan ? 1 : 0);
+        if (a.t < a.T) {
+            const float* wt = a.weights ? a.weights + int64_t(a.t) * a.n_types : nullptr;
+            auto weight = [&](int k) -> M {
+                return wt ? M(wt[cd.edge_type[e0 + k]]) : M(a.alpha);
+            };
+            auto emit = [&](int k, M v) { msg[e0 + k] = StoreT<S>::put(v); };
+            check_rule<M, ALGO, MAXD>(x, d, syn, M(a.clamp), weight, emit);
+        }
+    }
+    add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
+}
+
+// Ends finished frames; returns true when this tile's frame must not update.
+__device__ __forceinline__ bool frame_stops(const DecArgs& a, const Tile& tl)
+{
+    const int u = a.unsat[2 * tl.frame + (a.t & 1)];
+    const bool stop = (a.early_stop && u == 0) || a.t >= a.T;
+    if ((tl.count & kFirstTile) && threadIdx.x == 0) {
+        if (stop) {
+            a.iters[tl.frame] = a.t;
+            a.ok[tl.frame] = uint8_t(u == 0);
+            a.active[tl.frame] = 0;
+        } else {
+            a.unsat[2 * tl.frame + ((a.t + 1) & 1)] = 0;
+        }
+    }
+    return stop;
+}
+
+template <typename M, typename S>
+__global__ __launch_bounds__(kTile) void k_var_generic(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    if (frame_stops(a, tl)) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int v = tl.a + int(threadIdx.x);
+    if (int(threadIdx.x) >= count) return;
+    const S* msg = static_cast<const S*>(a.c2v) + fr.msg_off;
+    M acc = static_cast<const M*>(a.llr)[fr.vn_off + v];
+    for (int k = cd.col_ptr[v]; k < cd.col_ptr[v + 1]; ++k) acc += M(StoreT<S>::get(msg[cd.col_edge[k]]));
+    static_cast<M*>(a.post)[fr.vn_off + v] = acc;
+    if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// quasi-cyclic passes: tile = (frame, block row / column, first k / u)
+// ---------------------------------------------------------------------------
+template <typename M, typename S, int ALGO, int MAXD>
+__global__ __launch_bounds__(kTile) void k_check_qc(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int i = tl.a;
+    const int k = tl.b + int(threadIdx.x);
+    const int Z = cd.Z;
+    const int q0 = cd.qrow_ptr[i];
+    const int d = cd.qrow_ptr[i + 1] - q0;
+    const M* Lp = static_cast<const M*>(a.post) + fr.vn_off;
+    S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    int bad = 0;
+    if (int(threadIdx.x) < count) {
+        const int syn = a.syn ? (a.syn[fr.chk_off + int64_t(i) * Z + k] & 1) : 0;
+        int par = syn;
+        bool nan = false;
+        M x[MAXD];
+#pragma unroll
+        for (int q = 0; q < MAXD; ++q) {
+            x[q] = M(0);
+            if (q < d) {
+                const QcBlock blk = cd.qrow[q0 + q];
+                int u = k + blk.shift;
+                u = u >= Z ? u - Z : u;
+                const M lp = Lp[int64_t(blk.other) * Z + u];
+                par ^= (lp < M(0)) ? 1 : 0;
+                nan |= (lp != lp);
+                x[q] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(msg[int64_t(blk.blk) * Z + k]));
+            }
+        }
+        bad = par | (nan ? 1 : 0);
+        if (a.t < a.T) {
+            const float* wt = a.weights ? a.weights + int64_t(a.t) * a.n_types : nullptr;
+            auto weight = [&](int q) -> M { return wt ? M(wt[cd.qrow[q0 + q].type]) : M(a.alpha); };
+            auto emit = [&](int q, M v) { msg[int64_t(cd.qrow[q0 + q].blk) * Z + k] = StoreT<S>::put(v); };
+            check_rule<M, ALGO, MAXD>(x, d, syn, M(a.clamp), weight, emit);
+        }
+    }
+    add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
+}
+
+template <typename M, typename S>
+__global__ __launch_bounds__(kTile) void k_var_qc(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    if (!a.active[tl.frame]) return;
+    if (frame_stops(a, tl)) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    if (int(threadIdx.x) >= count) return;
+    const int j = tl.a;
+    const int u = tl.b + int(threadIdx.x);
+    const int Z = cd.Z;
+    const S* msg = static_cast<const S*>(a.c2v) + fr.msg_off;
+    const int64_t v = int64_t(j) * Z + u;
+    M acc = static_cast<const M*>(a.llr)[fr.vn_off + v];
+    for (int q = cd.qcol_ptr[j]; q < cd.qcol_ptr[j + 1]; ++q) {      // block rows ascending
+        const QcBlock blk = cd.qcol[q];
+        int k = u - blk.shift;
+        k = k < 0 ? k + Z : k;
+        acc += M(StoreT<S>::get(msg[int64_t(blk.blk) * Z + k]));
+    }
+    static_cast<M*>(a.post)[fr.vn_off + v] = acc;
+    if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// persistent frame-per-workgroup decoder for quasi-cyclic codes
+// ---------------------------------------------------------------------------
+// Each workgroup takes whole frames from an atomic queue and runs all of a
+// frame's iterations itself: the two half-iterations are separated by
+// __syncthreads only, so frames stop independently, no grid-wide barrier or
+// per-iteration launch exists, and a frame's state is touched by one CU only
+// (it stays in that XCD's L2 / the Infinity Cache while the frame is decoded).
+// The protograph tables of the current code are cached in LDS.
+constexpr int kMaxLdsBlocks = 2048;
+constexpr int kMaxLdsDim = 512;
+
+struct LdsCode {
+    int32_t rptr[kMaxLdsDim + 1];
+    int32_t cptr[kMaxLdsDim + 1];
+    int2 row[kMaxLdsBlocks];   // x = shift, y = block column | type << 20 (block id = position)
+    int2 col[kMaxLdsBlocks];   // x = shift, y = block id
+};
+
+template <typename M, typename S, int ALGO, int MAXD, int kFrameThreads, int ROWS>
+__global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F)
+{
+    __shared__ LdsCode sc;
+    __shared__ int32_t s_frame;
+    __shared__ int32_t s_unsat[2];
+    const int tid = int(threadIdx.x);
+    int cur = -1;
+    for (;;) {
+        if (tid == 0) s_frame = atomicAdd(queue, 1);
+        __syncthreads();
+        const int f = s_frame;
+        if (f >= F) break;
+        const DevFrame fr = a.frames[f];
+        const DevCode& cd = a.codes[fr.code];
+        if (fr.code != cur) {
+            for (int q = tid; q <= cd.mb; q += kFrameThreads) sc.rptr[q] = cd.qrow_ptr[q];
+            for (int q = tid; q <= cd.nb; q += kFrameThreads) sc.cptr[q] = cd.qcol_ptr[q];
+            for (int q = tid; q < cd.NB; q += kFrameThreads) {
+                const QcBlock br = cd.qrow[q];
+                sc.row[q] = make_int2(br.shift, br.other | (br.type << 20));
+                const QcBlock bc = cd.qcol[q];
+                sc.col[q] = make_int2(bc.shift, bc.blk);
+            }
+            cur = fr.code;
+        }
+        const int Z = cd.Z;
+        const int m = cd.mb * Z, n = cd.nb * Z;
+        const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
+        M* Lp = static_cast<M*>(a.post) + fr.vn_off;
+        const M* Lc = static_cast<const M*>(a.llr) + fr.vn_off;
+        S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+        const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
+        M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
+        for (int v = tid; v < n; v += kFrameThreads) {
+            const M l = Lc[v];
+            Lp[v] = l;
+            if (tr) tr[v] = l;
+        }
+        if (tid == 0) {
+            s_unsat[0] = 0;
+            s_unsat[1] = 0;
+        }
+        __syncthreads();
+        for (int t = 0;; ++t) {
+            // check pass: syndrome test of Lpost(t) and c2v(t+1); ROWS rows per
+            // thread per step so that their loads are in flight together
+            int bad = 0;
+            const float* wt = a.weights ? a.weights + int64_t(t) * a.n_types : nullptr;
+            for (int r0 = tid; r0 < m; r0 += ROWS * kFrameThreads) {
+                M x[ROWS][MAXD];
+                int q0[ROWS], d[ROWS], kk[ROWS], sbit[ROWS], par[ROWS];
+                bool nan[ROWS];
+#pragma unroll
+                for (int h = 0; h < ROWS; ++h) {
+                    const int r = r0 + h * kFrameThreads;
+                    const bool live = r < m;
+                    const int rr = live ? r : r0;
+                    const int i = zsh >= 0 ? (rr >> zsh) : rr / Z;
+                    kk[h] = rr - i * Z;
+                    q0[h] = sc.rptr[i];
+                    d[h] = live ? sc.rptr[i + 1] - q0[h] : 0;
+                    sbit[h] = (syn && live) ? (syn[rr] & 1) : 0;
+                    par[h] = sbit[h];
+                    nan[h] = false;
+                }
+#pragma unroll
+                for (int h = 0; h < ROWS; ++h) {
+#pragma unroll
+                    for (int q = 0; q < MAXD; ++q) {
+                        x[h][q] = M(0);
+                        if (q < d[h]) {
+                            const int2 e = sc.row[q0[h] + q];
+                            int uu = kk[h] + e.x;
+                            uu = uu >= Z ? uu - Z : uu;
+                            const M lp = Lp[(e.y & 0xfffff) * Z + uu];
+                            par[h] ^= (lp < M(0)) ? 1 : 0;
+                            nan[h] |= (lp != lp);
+                            x[h][q] = (t == 0) ? lp : lp - M(StoreT<S>::get(msg[(q0[h] + q) * Z + kk[h]]));
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < ROWS; ++h) {
+                    if (d[h] == 0) continue;
+                    bad += par[h] | (nan[h] ? 1 : 0);
+                    if (t < a.T) {
+                        const int qb = q0[h], kh = kk[h];
+                        auto weight = [&](int q) -> M { return wt ? M(wt[sc.row[qb + q].y >> 20]) : M(a.alpha); };
+                        auto emit = [&](int q, M v) { msg[(qb + q) * Z + kh] = StoreT<S>::put(v); };
+                        check_rule<M, ALGO, MAXD>(x[h], d[h], sbit[h], M(a.clamp), weight, emit);
+                    }
+                }
+            }
+            if (bad) atomicAdd(&s_unsat[t & 1], bad);
+            __syncthreads();
+            const int u = s_unsat[t & 1];
+            if ((a.early_stop && u == 0) || t >= a.T) {
+                if (tid == 0) {
+                    a.iters[f] = t;
+                    a.ok[f] = uint8_t(u == 0);
+                }
+                break;
+            }
+            if (tid == 0) s_unsat[(t + 1) & 1] = 0;
+            // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows
+            // ascending; the messages are loaded 8 at a time, then summed in order
+            for (int v = tid; v < n; v += kFrameThreads) {
+                const int j = zsh >= 0 ? (v >> zsh) : v / Z;
+                const int uu = v - j * Z;
+                const int qa = sc.cptr[j];
+                const int dv = sc.cptr[j + 1] - qa;
+                M acc = Lc[v];
+                for (int q8 = 0; q8 < dv; q8 += 8) {
+                    M c[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        c[q] = M(0);
+                        if (q8 + q < dv) {
+                            const int2 e = sc.col[qa + q8 + q];
+                            int k = uu - e.x;
+                            k = k < 0 ? k + Z : k;
+                            c[q] = M(StoreT<S>::get(msg[e.y * Z + k]));
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q8 + q < dv) acc += c[q];
+                }
+                Lp[v] = acc;
+                if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
+            }
+            __syncthreads();
+        }
+        for (int v = tid; v < n; v += kFrameThreads) a.bits[fr.vn_off + v] = Lp[v] < M(0) ? 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up and output passes (over the generic variable tiles)
+// ---------------------------------------------------------------------------
+template <typename M>
+__global__ __launch_bounds__(kTile) void k_dec_init(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    const DevFrame fr = a.frames[tl.frame];
+    const int count = tl.count & 0x7fffffff;
+    if ((tl.count & kFirstTile) && threadIdx.x == 0) {
+        a.active[tl.frame] = 1;
+        a.unsat[2 * tl.frame] = 0;
+        a.unsat[2 * tl.frame + 1] = 0;
+        a.iters[tl.frame] = 0;
+        a.ok[tl.frame] = 0;
+    }
+    if (int(threadIdx.x) >= count) return;
+    const int64_t v = fr.vn_off + tl.a + int(threadIdx.x);
+    const M l = static_cast<const M*>(a.llr)[v];
+    static_cast<M*>(a.post)[v] = l;
+    if (a.trace) static_cast<M*>(a.trace)[v] = l;
+}
+
+template <typename M>
+__global__ __launch_bounds__(kTile) void k_dec_final(DecArgs a)
+{
+    const Tile tl = a.tiles[blockIdx.x];
+    const DevFrame fr = a.frames[tl.frame];
+    const int count = tl.count & 0x7fffffff;
+    if (int(threadIdx.x) >= count) return;
+    const int64_t v = fr.vn_off + tl.a + int(threadIdx.x);
+    a.bits[v] = static_cast<const M*>(a.post)[v] < M(0) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// host side (templated launch sequences, instantiated per precision/rule TU)
+__global__ __launch_bounds__(256) static void k_zero_i32(int32_t* p, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_decode(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc)
+{
+    const int64_t nvt = b->n_vn_tiles;
+    a.tiles = b->d_vn_tiles;
+    {
+        ProfScope prof(CVR_PROF_DEC_SETUP, s);
+        hipLaunchKernelGGL(k_dec_init<M>, dim3(nvt), dim3(kTile), 0, s, a);
+    }
+    if (cvr_status st = check_launch("decode init")) return st;
+    for (int t = 0; t <= a.T; ++t) {
+        a.t = t;
+        if (qc) {
+            a.tiles = b->d_qcn_tiles;
+            {
+                ProfScope prof(CVR_PROF_CHECK, s);
+                hipLaunchKernelGGL((k_check_qc<M, S, ALGO, MAXD>), dim3(b->n_qcn_tiles), dim3(kTile), 0, s, a);
+            }
+            a.tiles = b->d_qvn_tiles;
+            {
+                ProfScope prof(CVR_PROF_VAR, s);
+                hipLaunchKernelGGL((k_var_qc<M, S>), dim3(b->n_qvn_tiles), dim3(kTile), 0, s, a);
+            }
+        } else {
+            a.tiles = b->d_cn_tiles;
+            {
+                ProfScope prof(CVR_PROF_CHECK, s);
+                hipLaunchKernelGGL((k_check_generic<M, S, ALGO, MAXD>), dim3(b->n_cn_tiles), dim3(kTile), 0, s, a);
+            }
+            a.tiles = b->d_vn_tiles;
+            {
+                ProfScope prof(CVR_PROF_VAR, s);
+                hipLaunchKernelGGL((k_var_generic<M, S>), dim3(nvt), dim3(kTile), 0, s, a);
+            }
+        }
+        if (cvr_status st = check_launch("decode iteration")) return st;
+    }
+    a.tiles = b->d_vn_tiles;
+    {
+        ProfScope prof(CVR_PROF_DEC_SETUP, s);
+        hipLaunchKernelGGL(k_dec_final<M>, dim3(nvt), dim3(kTile), 0, s, a);
+    }
+    return check_launch("decode final");
+}
+
+static inline int device_cus()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS>
+static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s)
+{
+    static int per_cu = 0;      // resident workgroups per CU of this instantiation
+    if (per_cu == 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_frames_qc<M, S, ALGO, MAXD, NT, ROWS>, NT, 0) != hipSuccess ||
+            v < 1)
+            v = 1;
+        per_cu = v;
+    }
+    const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
+    ProfScope prof(CVR_PROF_FRAMES, s);
+    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD, NT, ROWS>), dim3(grid), dim3(NT), 0, s, a, queue, b->F);
+    return check_launch("decode (persistent)");
+}
+
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int wg, int rows)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, queue, int64_t(1));
+    if (cvr_status st = check_launch("decode queue reset")) return st;
+    if (rows == 2) {
+        if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 2>(b, a, queue, s);
+        if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 2>(b, a, queue, s);
+        return launch_frames<M, S, ALGO, MAXD, 512, 2>(b, a, queue, s);
+    }
+    if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 1>(b, a, queue, s);
+    if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 1>(b, a, queue, s);
+    return launch_frames<M, S, ALGO, MAXD, 512, 1>(b, a, queue, s);
+}
+
+template <typename M, typename S, int ALGO>
+static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue,
+                               int wg, int rows)
+{
+    if (frames) {
+        if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, wg, rows);
+        if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, wg, rows);
+        return run_frames<M, S, ALGO, 32>(b, a, queue, s, wg, rows);
+    }
+    if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
+    if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
+    return run_decode<M, S, ALGO, 32>(b, a, s, qc);
+}
+
+
+}  // namespace cvr
+
+namespace cvr {
+// One instantiation per (math, store, rule); each lives in its own translation unit.
+#define CVR_DECL_DISPATCH(NAME)                                                                      \
+    cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue, \
+                    int wg, int rows)
+CVR_DECL_DISPATCH(decode_f64_sp);
+CVR_DECL_DISPATCH(decode_f64_nms);
+CVR_DECL_DISPATCH(decode_f32_sp);
+CVR_DECL_DISPATCH(decode_f32_nms);
+CVR_DECL_DISPATCH(decode_f16_sp);
+CVR_DECL_DISPATCH(decode_f16_nms);
+}  // namespace cvr

@@ -68,29 +68,32 @@ __global__ __launch_bounds__(256) void k_quantize(QuantArgs a)
     }
 }
 
-// ln Phi(z), Phi the standard normal CDF.  Right of zero via log1p of the
-// upper tail; moderately left via erfc; far left via the scaled complementary
-// error function erfcx(u) = exp(u^2) erfc(u), so that ln Phi stays finite.
-__device__ __forceinline__ double ln_phi(double z)
+// ln Q(z) for z >= 0 (z may be +inf), Q(z) = 1 - Phi(z) the normal upper tail,
+// through the scaled complementary error function erfcx(w) = exp(w^2) erfc(w):
+// ln Q(z) = ln(erfcx(z / sqrt 2) / 2) - z^2 / 2, finite far into the tail.
+__device__ __forceinline__ double ln_q(double z)
 {
-    if (z > 0.0) return log1p(-0.5 * erfc(z * M_SQRT1_2));
-    if (z > -5.0) return log(0.5 * erfc(-z * M_SQRT1_2));
-    return log(0.5 * erfcx(-z * M_SQRT1_2)) - 0.5 * z * z;
+    if (z == INFINITY) return -INFINITY;
+    const double w = z * M_SQRT1_2;
+    return log(0.5 * erfcx(w)) - w * w;
 }
 
-// ln(e^a - e^b) for b <= a.
-__device__ __forceinline__ double log_diff(double a, double b)
-{
-    return a + log(-expm1(b - a));
-}
-
-// ln Pr(lo <= Z < hi), Z standard normal, lo < hi.
+// ln Pr(lo <= Z < hi) for a standard normal Z and lo < hi (either may be
+// infinite).  A lower-tail interval is mirrored onto the upper tail (same
+// probability), so only two cases remain: both ends above the mean, where
+// P = Q(lo) - Q(hi) = Q(lo) (1 - Q(hi)/Q(lo)), and an interval containing the
+// mean, where P = 1 - Q(-lo) - Q(hi).  Both need ln Q at |lo| and hi only.
 __device__ __forceinline__ double ln_interval(double lo, double hi)
 {
-    if (lo >= 0.0) return log_diff(ln_phi(-lo), ln_phi(-hi));      // both in the upper tail
-    if (hi <= 0.0) return log_diff(ln_phi(hi), ln_phi(lo));        // both in the lower tail
-    const double out = 0.5 * erfc(-lo * M_SQRT1_2) + 0.5 * erfc(hi * M_SQRT1_2);
-    return log1p(-out);                                            // straddles the mean
+    if (hi <= 0.0) {
+        const double t = lo;
+        lo = -hi;
+        hi = -t;
+    }
+    const double A = ln_q(fabs(lo));
+    const double B = ln_q(hi);
+    if (lo >= 0.0) return A + log(-expm1(B - A));
+    return log1p(-(exp(A) + exp(B)));
 }
 
 __device__ __forceinline__ void lse_push(double& mx, double& s, double v)
@@ -104,22 +107,40 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double v)
     }
 }
 
+// One thread per sample.  Only the 2^(m - |known|) labels that agree with the
+// sample's known slice bits are visited (a uniform trip count: the free bit
+// positions are the same for every sample), so wavefronts do not diverge over
+// interval membership.  Interval bounds come from an LDS copy of the
+// thresholds with t_0 = -inf and t_{2^m} = +inf.
 __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
 {
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    __shared__ double bnd[kMaxThr + 2];
     const int K = 1 << a.m_bits;
+    for (int q = threadIdx.x; q <= K; q += blockDim.x)
+        bnd[q] = (q == 0) ? -INFINITY : (q == K ? INFINITY : a.t[q - 1]);
+    __syncthreads();
+    const uint32_t freemask = uint32_t(K - 1) & ~a.known;
+    const int nfree = __popc(freemask);
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += stride) {
         const double x = a.x[i];
         uint32_t kb = 0;
         for (int q = 0; q < a.m_bits; ++q)
             if ((a.known >> q) & 1u) kb |= uint32_t(a.slices[int64_t(q) * a.n + i] & 1) << q;
         double m0 = -INFINITY, s0 = 0.0, m1 = -INFINITY, s1 = 0.0;
-        for (int k = 0; k < K; ++k) {
-            const uint32_t g = a.gray ? uint32_t(k ^ (k >> 1)) : uint32_t(k);
-            if ((g & a.known) != kb) continue;            // disagrees with a known slice bit
-            const double lo = (k == 0) ? -INFINITY : (a.t[k - 1] - x) / a.sigma;
-            const double hi = (k == K - 1) ? INFINITY : (a.t[k] - x) / a.sigma;
-            const double lp = ln_interval(lo, hi);
+        for (int c = 0; c < (1 << nfree); ++c) {
+            // deposit the bits of c into the free label positions
+            uint32_t g = kb, fm = freemask;
+            for (int b = 0; b < nfree; ++b) {
+                const uint32_t low = fm & (~fm + 1u);
+                if ((c >> b) & 1) g |= low;
+                fm &= fm - 1u;
+            }
+            // interval index of label g
+            uint32_t k = g;
+            if (a.gray)
+                for (uint32_t sh = 1; sh < 8; sh <<= 1) k ^= k >> sh;
+            const double lp = ln_interval((bnd[k] - x) / a.sigma, (bnd[k + 1] - x) / a.sigma);
             if ((g >> a.j) & 1u) lse_push(m1, s1, lp);
             else lse_push(m0, s0, lp);
         }
