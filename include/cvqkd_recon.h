@@ -220,6 +220,39 @@ cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_params* params,
                              void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------- */
+/* Differentiable unrolled normalized min-sum (learning per-iteration,        */
+/* per-edge-type scales)                                                      */
+/* ------------------------------------------------------------------------- */
+/* T iterations of binary32 min-sum with weights w[t][type] (no early stop,
+ * fp32 messages) on a QC batch (as the persistent schedule requires, at most
+ * 4 edge types, every check of degree >= 2).  The forward posteriors equal
+ * those of ldpc_decode_batch(CVR_NMS, F32/F32, weights, early_stop = 0).
+ * The messages c2v(t) at t = 0, K, 2K, ... (K = ckpt_every) are checkpointed;
+ * the backward pass recomputes each K-iteration segment from its checkpoint
+ * and runs the adjoint through it: derivatives flow through the minimum to
+ * its lowest-index minimiser, |x| has derivative sign(x) (sign(0) = +1) and
+ * sign products are constant.  The weight gradient is reduced in a fixed
+ * order (bit-identical across runs on one device).
+ *
+ * nms_unrolled_sizes: ckpt_floats = floats of the checkpoint buffer; bytes of
+ *   the forward and backward workspaces (any output pointer may be NULL).
+ * nms_unrolled_fwd: weights device fp32 [T][n_types]; llr device fp32
+ *   [total_n]; syndrome device uint8 [total_m] or NULL; llr_post_out device
+ *   fp32 [total_n] = L_post(T); ckpt device fp32 [ckpt_floats] (written).
+ * nms_unrolled_bwd: ckpt as written by the forward with the same arguments;
+ *   dloss_dpost device fp32 [total_n]; dweights device fp32 [T][n_types]
+ *   (overwritten); dllr device fp32 [total_n] or NULL (overwritten).        */
+cvr_status nms_unrolled_sizes(cvr_batch_t batch, int32_t T, int32_t ckpt_every, size_t* ckpt_floats,
+                              size_t* fwd_workspace, size_t* bwd_workspace);
+cvr_status nms_unrolled_fwd(cvr_batch_t batch, int32_t T, int32_t ckpt_every, const float* weights,
+                            const float* llr, const uint8_t* syndrome, float* llr_post_out, float* ckpt,
+                            void* workspace, size_t ws_bytes, void* stream);
+cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckpt_every, const float* weights,
+                            const float* llr, const uint8_t* syndrome, const float* ckpt,
+                            const float* dloss_dpost, float* dweights, float* dllr, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- */
 /* Launch timing                                                              */
 /* ------------------------------------------------------------------------- */
 /* Kernel kinds reported by cvr_profile_read. */

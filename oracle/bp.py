@@ -38,7 +38,7 @@ def _load():
         lib.orc_syndrome.argtypes = [i32, i32, P, P, i32, P, P, P, P]
         lib.orc_decode.argtypes = [i32, i32, P, P, P, i32, i32, P, P, i32, i32, i32, i32, i32,
                                    d, P, d, P, P, P, P, P, P, P]
-        lib.orc_nms_unrolled.argtypes = [i32, i32, P, P, P, i32, i32, P, P, P, i32, P, P, P, P, P]
+        lib.orc_nms_unrolled.argtypes = [i32, i32, P, P, P, i32, i32, P, P, P, i32, P, i32, P, P, P, P]
         lib.orc_round_half.argtypes = [d]
         lib.orc_round_half.restype = d
         _lib = lib
@@ -107,9 +107,9 @@ def decode(code, llr, syndrome=None, *, algo=SP, max_iter=50, early_stop=True,
     return out
 
 
-def nms_unrolled(code, llr, syndrome, truth, weights, want_dllr=False):
+def nms_unrolled(code, llr, syndrome, truth, weights, want_dllr=False, prec32=False):
     """Unrolled normalized min-sum: loss, final posteriors, d loss / d weights
-    [T, n_types] (and d loss / d llr)."""
+    [T, n_types] (and d loss / d llr).  ``prec32``: binary32 forward pass."""
     lib = _load()
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
     F, n = llr.shape
@@ -123,7 +123,7 @@ def nms_unrolled(code, llr, syndrome, truth, weights, want_dllr=False):
     dw = np.zeros_like(w)
     dl = np.zeros((F, n)) if want_dllr else None
     rc = lib.orc_nms_unrolled(code.n, code.m, _p(rp), _p(ci), _p(et), code.n_types, F, _p(llr),
-                              _p(syn), _p(tb), T, _p(w), _p(loss), _p(post), _p(dw), _p(dl))
+                              _p(syn), _p(tb), T, _p(w), int(bool(prec32)), _p(loss), _p(post), _p(dw), _p(dl))
     if rc:
         raise ValueError("oracle nms_unrolled rejected its arguments")
     res = dict(loss=float(loss[0]), post=post, dw=dw)

@@ -272,11 +272,14 @@ int orc_decode(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_
  * The derivative of |x| is taken as sign(x) with sign(0) = +1; the derivative
  * of the minimum over k != e goes to its lowest-index minimiser; sign products
  * are piecewise constant.  All intermediate messages are kept (a full tape).
+ * prec32 != 0 runs the forward pass in binary32 as orc_decode does (so the
+ * minimum and sign decisions are those of a binary32 decoder); the reverse
+ * pass stays in double.
  */
 int orc_nms_unrolled(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
                      const uint8_t* edge_type, int32_t n_types,
                      int32_t F, const double* llr, const uint8_t* syn, const uint8_t* truth,
-                     int32_t T, const double* weights,
+                     int32_t T, const double* weights, int32_t prec32,
                      double* loss_out, double* post_out, double* dw, double* dllr)
 {
     if (n <= 0 || m < 0 || F < 0 || T < 1) return -1;
@@ -310,13 +313,22 @@ int orc_nms_unrolled(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t
                 const double* cin = c2v + (int64_t)t * E;
                 double* vt = v2c + (int64_t)t * E;
                 double* cout = c2v + (int64_t)(t + 1) * E;
-                for (int32_t v = 0; v < n; ++v)
+                for (int32_t v = 0; v < n; ++v) {
+                    double lp = rnd(1, Lch[v]);
+                    if (prec32)
+                        for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) lp = rnd(1, lp + cin[cv.edge[k]]);
                     for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) {
-                        double a = Lch[v];
-                        for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
-                            if (k2 != k) a += cin[cv.edge[k2]];
+                        double a;
+                        if (prec32) {
+                            a = rnd(1, lp - cin[cv.edge[k]]);
+                        } else {
+                            a = Lch[v];
+                            for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
+                                if (k2 != k) a += cin[cv.edge[k2]];
+                        }
                         vt[cv.edge[k]] = a;
                     }
+                }
                 for (int32_t c = 0; c < m; ++c) {
                     const double ssign = (s && (s[c] & 1)) ? -1.0 : 1.0;
                     for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
@@ -327,14 +339,14 @@ int orc_nms_unrolled(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t
                             if (fabs(vt[k]) < mn) mn = fabs(vt[k]);
                         }
                         double w = weights[(int64_t)t * n_types + (edge_type ? edge_type[e] : 0)];
-                        cout[e] = w * (sg * mn);
+                        cout[e] = rnd(prec32, rnd(prec32, w) * (sg * mn));
                     }
                 }
             }
             const double* cT = c2v + (int64_t)T * E;
             for (int32_t v = 0; v < n; ++v) {
-                double a = Lch[v];
-                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a += cT[cv.edge[k]];
+                double a = rnd(prec32, Lch[v]);
+                for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a = rnd(prec32, a + cT[cv.edge[k]]);
                 Lp[v] = a;
                 if (post_out) post_out[(int64_t)f * n + v] = a;
                 double z = -(1.0 - 2.0 * (b[v] & 1)) * a;           /* softplus(z) */
@@ -363,7 +375,7 @@ int orc_nms_unrolled(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t
                             if (fabs(vt[k]) < mn) { mn = fabs(vt[k]); arg = k; }
                         }
                         int32_t ty = edge_type ? edge_type[e] : 0;
-                        double w = weights[(int64_t)t * n_types + ty];
+                        double w = rnd(prec32, weights[(int64_t)t * n_types + ty]);
                         dw_loc[(int64_t)t * n_types + ty] += g_c2v[e] * sg * mn;
                         if (arg >= 0) {
                             double dabs = neg(vt[arg]) ? -1.0 : 1.0;

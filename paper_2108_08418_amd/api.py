@@ -285,3 +285,69 @@ def profile_read(kind: int, reset: bool = False) -> tuple[float, int]:
     cnt = C.c_int64()
     check(load().cvr_profile_read(int(kind), C.byref(ms), C.byref(cnt), int(bool(reset))), "cvr_profile_read")
     return ms.value, cnt.value
+
+
+# ---------------------------------------------------------------------------
+# differentiable unrolled min-sum
+# ---------------------------------------------------------------------------
+def nms_unrolled_sizes(batch: Batch, T: int, ckpt_every: int) -> tuple[int, int, int]:
+    """(checkpoint floats, forward workspace bytes, backward workspace bytes)."""
+    ck, fw, bw = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    check(load().nms_unrolled_sizes(batch.handle, int(T), int(ckpt_every), C.byref(ck), C.byref(fw), C.byref(bw)),
+          "nms_unrolled_sizes")
+    return ck.value, fw.value, bw.value
+
+
+def nms_unrolled_fwd(batch: Batch, T: int, ckpt_every: int, weights: torch.Tensor, llr: torch.Tensor,
+                     syndrome: torch.Tensor | None = None, stream=None):
+    """Posteriors after T weighted min-sum iterations and the checkpoints."""
+    ck, fw, _ = nms_unrolled_sizes(batch, T, ckpt_every)
+    dev = llr.device
+    post = torch.empty(batch.total_n, dtype=torch.float32, device=dev)
+    ckpt = torch.empty(max(ck, 1), dtype=torch.float32, device=dev)
+    ws = torch.empty(max(fw, 256), dtype=torch.uint8, device=dev)
+    for name, t in (("weights", weights), ("llr", llr)):
+        if t.dtype != torch.float32:
+            raise ValueError(f"{name} must be float32")
+    check(load().nms_unrolled_fwd(batch.handle, int(T), int(ckpt_every), _ptr(weights.contiguous()), _ptr(llr),
+                                  _ptr(syndrome), _ptr(post), _ptr(ckpt), _ptr(ws), ws.numel(), _stream(stream)),
+          "nms_unrolled_fwd")
+    return post, ckpt
+
+
+def nms_unrolled_bwd(batch: Batch, T: int, ckpt_every: int, weights: torch.Tensor, llr: torch.Tensor,
+                     syndrome: torch.Tensor | None, ckpt: torch.Tensor, dloss_dpost: torch.Tensor,
+                     want_dllr: bool = False, stream=None):
+    """(d loss / d weights [T, n_types], d loss / d llr or None)."""
+    _, _, bw = nms_unrolled_sizes(batch, T, ckpt_every)
+    dev = llr.device
+    dw = torch.empty_like(weights, dtype=torch.float32).contiguous()
+    dl = torch.empty(batch.total_n, dtype=torch.float32, device=dev) if want_dllr else None
+    ws = torch.empty(max(bw, 256), dtype=torch.uint8, device=dev)
+    check(load().nms_unrolled_bwd(batch.handle, int(T), int(ckpt_every), _ptr(weights.contiguous()), _ptr(llr),
+                                  _ptr(syndrome), _ptr(ckpt), _ptr(dloss_dpost.contiguous()), _ptr(dw), _ptr(dl),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "nms_unrolled_bwd")
+    return dw, dl
+
+
+class NMSUnrolled(torch.autograd.Function):
+    """L_post(T) of T-iteration weighted min-sum as a differentiable function of
+    the weights [T, n_types] (and of the channel LLRs).  Backward is the
+    library's adjoint kernel with checkpointed recomputation."""
+
+    @staticmethod
+    def forward(ctx, weights, llr, syndrome, batch, T, ckpt_every):
+        w = weights.detach().contiguous()
+        l = llr.detach().contiguous()
+        post, ckpt = nms_unrolled_fwd(batch, T, ckpt_every, w, l, syndrome)
+        ctx.save_for_backward(w, l, ckpt)
+        ctx.syndrome = syndrome
+        ctx.batch, ctx.T, ctx.K = batch, T, ckpt_every
+        return post
+
+    @staticmethod
+    def backward(ctx, grad_post):
+        w, l, ckpt = ctx.saved_tensors
+        dw, dl = nms_unrolled_bwd(ctx.batch, ctx.T, ctx.K, w, l, ctx.syndrome, ckpt, grad_post,
+                                  want_dllr=ctx.needs_input_grad[1])
+        return dw, dl, None, None, None, None

@@ -58,15 +58,19 @@ static cvr_status finish_code(cvr_code_s* h, int32_t n, int32_t m, const std::ve
     std::vector<int32_t> fill(col_ptr.begin(), col_ptr.end() - 1);
     for (int32_t c = 0; c < m; ++c)
         for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) col_edge[fill[col_idx[e]]++] = int32_t(e);
-    int32_t max_col = 0, max_row = 0;
+    int32_t max_col = 0, max_row = 0, min_row = INT32_MAX;
     for (int32_t v = 0; v < n; ++v) max_col = std::max(max_col, col_ptr[v + 1] - col_ptr[v]);
-    for (int32_t c = 0; c < m; ++c) max_row = std::max(max_row, row_ptr[c + 1] - row_ptr[c]);
+    for (int32_t c = 0; c < m; ++c) {
+        max_row = std::max(max_row, row_ptr[c + 1] - row_ptr[c]);
+        min_row = std::min(min_row, row_ptr[c + 1] - row_ptr[c]);
+    }
 
     DevCode& d = h->dev;
     d.n = n;
     d.m = m;
     d.E = E;
     d.max_row_deg = max_row;
+    d.min_row_deg = min_row;
     d.max_col_deg = max_col;
     d.n_types = n_types;
     h->E = E;

@@ -53,32 +53,6 @@ __global__ __launch_bounds__(256) void k_syndrome(SynArgs a)
     if (a.n_unsat) add_unsat(&a.n_unsat[f], bad);
 }
 
-static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
-
-static size_t msize(int32_t p) { return p == CVR_F64 ? 8 : (p == CVR_F32 ? 4 : 2); }
-
-struct WsLayout {
-    size_t c2v, post, active, unsat, queue, total;
-};
-
-static WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
-{
-    WsLayout w{};
-    size_t off = 0;
-    w.c2v = off;
-    off = align256(off + size_t(b->total_E) * msize(p->store));
-    w.post = off;
-    off = align256(off + size_t(b->total_n) * msize(p->math));
-    w.active = off;
-    off = align256(off + size_t(b->F) * 4);
-    w.unsat = off;
-    off = align256(off + size_t(b->F) * 8);
-    w.queue = off;
-    off = align256(off + 4);
-    w.total = off;
-    return w;
-}
-
 static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
 {
     if (!b) return fail(CVR_EINVAL, "decode: NULL batch");
@@ -96,16 +70,6 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
         return fail(CVR_EINVAL, "decode: wg_threads must be 0, 256, 512 or 1024");
     if (p->rows_per_step < 0 || p->rows_per_step > 2) return fail(CVR_EINVAL, "decode: rows_per_step must be 0, 1 or 2");
     return CVR_OK;
-}
-
-// The persistent path needs a quasi-cyclic batch whose protograph tables fit in LDS.
-static bool frames_fit(const cvr_batch_s* b)
-{
-    if (!b->all_qc) return false;
-    for (const cvr_code_t c : b->codes)
-        if (c->dev.NB > kMaxLdsBlocks || c->dev.mb > kMaxLdsDim || c->dev.nb > kMaxLdsDim || c->dev.Z >= (1 << 20))
-            return false;
-    return true;
 }
 
 }  // namespace cvr

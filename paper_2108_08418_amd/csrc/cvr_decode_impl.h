@@ -167,6 +167,9 @@ struct DecArgs {
     int32_t T;
     int32_t early_stop;
     int32_t n_types;
+    float* ckpt;              // [ceil(T / ckpt_every)][ckpt_stride] c2v(t) at t = 0, K, 2K, ... or NULL
+    int64_t ckpt_stride;
+    int32_t ckpt_every;
 };
 
 __device__ __forceinline__ void add_unsat(int32_t* slot, int pred)
@@ -393,6 +396,13 @@ __global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t*
         }
         __syncthreads();
         for (int t = 0;; ++t) {
+            if (a.ckpt && t < a.T && t % a.ckpt_every == 0) {
+                // checkpoint c2v(t) (all zero at t = 0) before the check pass overwrites it
+                float* ck = a.ckpt + int64_t(t / a.ckpt_every) * a.ckpt_stride + fr.msg_off;
+                const int ef = cd.NB * Z;
+                for (int e = tid; e < ef; e += kFrameThreads) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(msg[e]));
+                __syncthreads();
+            }
             // check pass: syndrome test of Lpost(t) and c2v(t+1); ROWS rows per
             // thread per step so that their loads are in flight together
             int bad = 0;
@@ -637,6 +647,43 @@ static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, b
 }  // namespace cvr
 
 namespace cvr {
+static inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static inline size_t msize(int32_t p) { return p == CVR_F64 ? 8 : (p == CVR_F32 ? 4 : 2); }
+
+struct WsLayout {
+    size_t c2v, post, active, unsat, queue, total;
+};
+
+static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
+{
+    WsLayout w{};
+    size_t off = 0;
+    w.c2v = off;
+    off = align256(off + size_t(b->total_E) * msize(p->store));
+    w.post = off;
+    off = align256(off + size_t(b->total_n) * msize(p->math));
+    w.active = off;
+    off = align256(off + size_t(b->F) * 4);
+    w.unsat = off;
+    off = align256(off + size_t(b->F) * 8);
+    w.queue = off;
+    off = align256(off + 4);
+    w.total = off;
+    return w;
+}
+
+// The persistent path needs a quasi-cyclic batch whose protograph tables fit in LDS.
+static inline bool frames_fit(const cvr_batch_s* b)
+{
+    if (!b->all_qc) return false;
+    for (const cvr_code_t c : b->codes)
+        if (c->dev.NB > kMaxLdsBlocks || c->dev.mb > kMaxLdsDim || c->dev.nb > kMaxLdsDim || c->dev.Z >= (1 << 20))
+            return false;
+    return true;
+}
+
+
 // One instantiation per (math, store, rule); each lives in its own translation unit.
 #define CVR_DECL_DISPATCH(NAME)                                                                      \
     cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue, \

@@ -60,6 +60,7 @@ struct DevCode {
     int32_t n, m;
     int64_t E;
     int32_t max_row_deg, max_col_deg, n_types, is_qc;
+    int32_t min_row_deg, pad0;
     int32_t nb, mb, Z, NB;
     // CSR (always present): row c -> edges row_ptr[c]..row_ptr[c+1]-1
     const int32_t* row_ptr;

@@ -365,3 +365,18 @@ def test_prec32_half_store_is_rounding_of_the_float_message():
                       prec32=True, store_half=True)
     msg = np.float32(0.75) * np.float32(L[0, 1])
     assert r["post"][0, 0] == np.float32(np.float32(1.0) + np.float32(np.float16(msg)))
+
+
+def test_unrolled_prec32_forward_matches_binary32_decoder_and_gradient_is_close():
+    code = I.irregular_code(256, 128, I.LAMBDA_NODE_FRACTIONS, seed=3)
+    rng = np.random.default_rng(31)
+    F, T = 3, 10
+    bits = rng.integers(0, 2, (F, 256)).astype(np.uint8)
+    llr = I.bpsk_llr(bits, 0.6, 32)
+    s, _ = oracle.syndrome(code, bits)
+    w = rng.uniform(0.6, 0.9, (T, code.n_types))
+    u32 = oracle.nms_unrolled(code, llr, s, bits, w, prec32=True)
+    d32 = oracle.decode(code, llr, s, algo=oracle.NMS, weights=w, max_iter=T, early_stop=False, prec32=True)
+    np.testing.assert_array_equal(u32["post"], d32["post"])
+    u64 = oracle.nms_unrolled(code, llr, s, bits, w)
+    np.testing.assert_allclose(u32["dw"], u64["dw"], rtol=1e-4, atol=1e-9)
