@@ -306,12 +306,15 @@ def _chain_base_matrix(col_deg: np.ndarray, mb: int, rng: np.random.Generator) -
 
 
 def _lambda_qc_code(nb: int, mb: int, Z: int, seed: int, name: str) -> QcCode:
+    """The protograph depends on ``seed`` only, so that every lifting size Z
+    shares it (and per-edge-type decoder weights carry over between sub-block
+    lengths); the circulant shifts depend on (seed, Z)."""
     col_deg, col_type = _lambda_columns(nb)
     rng = np.random.default_rng(seed)
     p = rng.permutation(nb)
     col_deg, col_type = col_deg[p], col_type[p]
     base = _chain_base_matrix(col_deg, mb, rng)
-    shift = _assign_shifts(base, Z, rng)
+    shift = _assign_shifts(base, Z, np.random.default_rng([seed, Z]))
     btype = np.where(shift >= 0, col_type[None, :], 0).astype(np.uint8)
     return QcCode(nb, mb, Z, shift.astype(np.int32), btype, 3, name=name)
 
@@ -330,7 +333,7 @@ def slice_code_spec(slice_j: int, n: int, seed: int = 2108) -> QcCode:
     mb = {2: 104, 3: 71}[slice_j]
     if n % nb:
         raise ValueError("n must be a multiple of 128")
-    return _lambda_qc_code(nb, mb, n // nb, seed * 131 + slice_j * 7 + 17 * (n // nb), f"slice{slice_j}-qc n{n}")
+    return _lambda_qc_code(nb, mb, n // nb, seed * 131 + slice_j * 7, f"slice{slice_j}-qc n{n}")
 
 
 def lambda_half_rate_spec(n: int, seed: int = 1650) -> QcCode:
@@ -338,7 +341,7 @@ def lambda_half_rate_spec(n: int, seed: int = 1650) -> QcCode:
     nb, mb = 128, 64
     if n % nb:
         raise ValueError("n must be a multiple of 128")
-    return _lambda_qc_code(nb, mb, n // nb, seed + n // nb, f"lambda-r1/2-qc n{n}")
+    return _lambda_qc_code(nb, mb, n // nb, seed, f"lambda-r1/2-qc n{n}")
 
 
 def met_rate_tenth_spec(n: int, seed: int = 16) -> QcCode:

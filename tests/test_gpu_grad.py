@@ -50,8 +50,10 @@ def test_gradient_matches_oracle(n, F, T, K):
     lg = _g(llr.reshape(-1)).requires_grad_(True)
     post = api.NMSUnrolled.apply(wg, lg, _g(syn.reshape(-1)), batch, T, K)
     target = _g(bits.reshape(-1).astype(np.float32))
-    # BCE of P(bit = 1) = sigmoid(-L) against the true bits, mean over all bits
-    loss = torch.nn.functional.binary_cross_entropy_with_logits(-post, target)
+    # BCE of P(bit = 1) = sigmoid(-L) against the true bits, mean over all bits,
+    # written as softplus(-(1 - 2b) L) so that its derivative stays accurate
+    # for confidently decoded bits
+    loss = torch.nn.functional.softplus(-(1 - 2 * target) * post).mean()
     loss.backward()
     torch.cuda.synchronize()
     ref = oracle.nms_unrolled(csr, llr.astype(np.float64), syn, bits, w.astype(np.float64), want_dllr=True, prec32=True)
@@ -79,7 +81,8 @@ def test_checkpoint_interval_does_not_change_results():
     for K in (1, 3, 5, 12):
         wg = _g(w).requires_grad_(True)
         post = api.NMSUnrolled.apply(wg, _g(llr.reshape(-1)), _g(syn.reshape(-1)), batch, 12, K)
-        loss = torch.nn.functional.binary_cross_entropy_with_logits(-post, _g(bits.reshape(-1).astype(np.float32)))
+        tb = _g(bits.reshape(-1).astype(np.float32))
+        loss = torch.nn.functional.softplus(-(1 - 2 * tb) * post).mean()
         loss.backward()
         outs.append((post.detach().cpu().numpy(), wg.grad.cpu().numpy()))
     for p, gw in outs[1:]:
