@@ -34,6 +34,11 @@ WORKLOADS = {
     "recon-2^27-nR2^14": dict(N=1 << 27, n=1 << 14),
     "recon-2^27-nR2^18": dict(N=1 << 27, n=1 << 18),
     "recon-2^27-nR2^20": dict(N=1 << 27, n=1 << 20),
+    # 4096 sub-blocks of mixed length (2176 x 4096, 1024 x 16384, 640 x 65536,
+    # 256 x 262144; seeded order) of a low-rate multi-edge-type code, BPSK at
+    # SNR 0.16, decoded in one persistent launch
+    "ragged-4096-frames": dict(kind="ragged", sizes=(4096, 16384, 65536, 262144), counts=(2176, 1024, 640, 256),
+                               snr=0.16),
 }
 SNR = 3.0
 M_BITS = 4
@@ -49,12 +54,16 @@ def parse():
     ap.add_argument("--decoder", default="sp", choices=["sp", "nms"])
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--alpha", type=float, default=0.75)
+    ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
+                    "(weights/<prefix>_slice<j>.json per coded slice); sets max-iter to their T")
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent"])
     ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
     ap.add_argument("--rows", type=int, default=0, help="check rows per thread per step (0 = default)")
     ap.add_argument("--cpu-frames", type=int, default=16, help="sub-blocks per stage in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2108)
+    ap.add_argument("--graph", action="store_true", help="replay the decode from a captured HIP graph")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (untimed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -136,6 +145,8 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes}))
         return
     wl = WORKLOADS[args.workload]
+    if wl.get("kind") == "ragged":
+        return ragged(args, wl, dev)
     N, n = wl["N"], wl["n"]
     F = N // n
     sig = math.sqrt(1.0 / SNR)
@@ -155,7 +166,18 @@ def main():
     sched = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT}[args.schedule]
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
                         schedule=sched, wg_threads=args.wg, rows_per_step=args.rows)
-    ws_bytes = max(api.decode_workspace_size(batches[j], params) for j in (2, 3))
+    stage_params = {2: params, 3: params}
+    if args.weights:
+        if algo != api.NMS:
+            raise SystemExit("--weights needs --decoder nms")
+        from dataclasses import replace
+
+        from paper_2108_08418_amd.train import load_weights
+        stage_params = {}
+        for j in (2, 3):
+            w = load_weights(f"{args.weights}_slice{j}")
+            stage_params[j] = replace(params, max_iter=int(w.shape[0]), weights=torch.from_numpy(w).to(dev))
+    ws_bytes = max(api.decode_workspace_size(batches[j], stage_params[j]) for j in (2, 3))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     bob = torch.empty((M_BITS, N), dtype=torch.uint8, device=dev)
     alice = torch.empty((M_BITS, N), dtype=torch.uint8, device=dev)
@@ -172,10 +194,21 @@ def main():
             api.syndrome_check(codes[j], bob[j], want_unsat=False, out_syndrome=syn[j])
         alice[0:2].copy_(bob[0:2])                                                     # disclosed slices
         api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)                     # Alice: slice 2
-        api.ldpc_decode_batch(batches[2], params, llr, syn[2], workspace=ws, out=outs[2])
+        api.ldpc_decode_batch(batches[2], stage_params[2], llr, syn[2], workspace=ws, out=outs[2])
         api.slice_llr(x, sig, th, M_BITS, 3, 0b111, alice, out=llr)                    # Alice: slice 3
-        api.ldpc_decode_batch(batches[3], params, llr, syn[3], workspace=ws, out=outs[3])
+        api.ldpc_decode_batch(batches[3], stage_params[3], llr, syn[3], workspace=ws, out=outs[3])
 
+    tuned = None
+    if not args.no_tune and args.wg == 0 and args.rows == 0 and args.schedule != "passes":
+        # pick the launch shape on this workload's own slice-2 decode (untimed)
+        step()
+        from paper_2108_08418_amd.tune import tune_decode
+        (wgt, rwt), tim = tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2])
+        for pp in {id(v): v for v in (params, *stage_params.values())}.values():
+            pp.wg_threads, pp.rows_per_step = wgt, rwt
+        args.wg, args.rows = wgt, rwt
+        tuned = {f"{k[0]}x{k[1]}": round(v, 3) for k, v in tim.items()}
+        print(f"# tuned: wg={args.wg} rows={args.rows} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -206,7 +239,7 @@ def main():
     dec_bytes = 0.0
     edge_updates = 0
     for j in (2, 3):
-        cb, ib = stage_bytes(iters[j], args.max_iter, n, codes[j].m, codes[j].n_edges, s_msg)
+        cb, ib = stage_bytes(iters[j], stage_params[j].max_iter, n, codes[j].m, codes[j].n_edges, s_msg)
         chk_bytes += cb
         iter_bytes += ib
         dec_bytes += frame_decode_bytes(iters[j], n, codes[j].m, codes[j].n_edges, s_msg)
@@ -248,8 +281,10 @@ def main():
         "config": {
             "workload": args.workload, "pairs": N, "sub_block": n, "sub_blocks_per_slice": F,
             "slices": "16 equiprobable Gray intervals; slices 0-1 disclosed, 2 (R=0.1875) and 3 (R=0.4922) decoded",
-            "decoder": ("sum-product" if algo == api.SP else f"normalized min-sum alpha={args.alpha}"),
-            "max_iter": args.max_iter, "schedule": args.schedule, "wg_threads": args.wg, "rows_per_step": args.rows,
+            "decoder": ("sum-product" if algo == api.SP else
+                        (f"learned normalized min-sum ({args.weights})" if args.weights else
+                         f"normalized min-sum alpha={args.alpha}")),
+            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "rows_per_step": args.rows,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -273,6 +308,7 @@ def main():
             "decode_ms_per_step": (per_ms + chk_ms + var_ms) / args.steps,
         },
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
+        "autotune_ms_per_decode": tuned,
         "dominant_kernel": dom,
         "fer": {str(j): float(1.0 - ok[j].mean()) for j in (2, 3)},
         "mean_iters": {str(j): float(iters[j].mean()) for j in (2, 3)},
@@ -281,11 +317,130 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args, x_np, y_np, qcs, th, sig, n)
+        result["cpu_baseline"] = cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params)
     print(json.dumps(result))
 
 
-def cpu_baseline(args, x_np, y_np, qcs, th, sig, n):
+def ragged(args, wl, dev):
+    """Uneven batch: every sub-block of the batch in one decode call."""
+    import torch
+
+    import oracle
+    from paper_2108_08418_amd import api, inputs
+
+    sizes, counts = wl["sizes"], wl["counts"]
+    rng = np.random.default_rng(args.seed)
+    order = rng.permutation(np.repeat(np.arange(len(sizes)), counts))
+    qcs = [inputs.met_low_rate_spec(n) for n in sizes]
+    codes = [api.Code.from_qc(q) for q in qcs]
+    frames, vo, co = [], 0, 0
+    for c in order:
+        frames.append((int(c), vo, co))
+        vo += sizes[c]
+        co += qcs[c].m
+    batch = api.Batch(codes, frames)
+    total_n, total_m, F = batch.total_n, batch.total_m, batch.F
+    print(f"# workload {args.workload}: F={F} total_n={total_n}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    bits = inputs.random_bits(total_n, seed=args.seed + 1)
+    sigma2 = 1.0 / wl["snr"]
+    llr_np = inputs.bpsk_llr(bits, sigma2, seed=args.seed + 2).astype(np.float32)
+    bits_g = torch.from_numpy(bits).to(dev)
+    llr = torch.from_numpy(llr_np).to(dev)
+    syn = torch.empty(total_m, dtype=torch.uint8, device=dev)
+    # Bob's syndromes, one syndrome_check per code over that code's frames (input synthesis)
+    for c, q in enumerate(qcs):
+        idx = [i for i, f in enumerate(frames) if f[0] == c]
+        vidx = torch.cat([torch.arange(frames[i][1], frames[i][1] + q.n, device=dev) for i in idx])
+        cidx = torch.cat([torch.arange(frames[i][2], frames[i][2] + q.m, device=dev) for i in idx])
+        s_c, _ = api.syndrome_check(codes[c], bits_g[vidx].contiguous(), want_unsat=False)
+        syn[cidx] = s_c.view(-1)
+    algo = api.SP if args.decoder == "sp" else api.NMS
+    store = api.F32 if args.decoder == "sp" else api.F16
+    params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
+                        wg_threads=args.wg, rows_per_step=args.rows)
+    ws = api.alloc_workspace(batch, params, dev)
+    out = dict(bits=torch.empty(total_n, dtype=torch.uint8, device=dev), post=None,
+               iters=torch.empty(F, dtype=torch.int32, device=dev), ok=torch.empty(F, dtype=torch.uint8, device=dev))
+    torch.cuda.synchronize()
+    print(f"# inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def step():
+        api.ldpc_decode_batch(batch, params, llr, syn, workspace=ws, out=out)
+
+    tuned = None
+    if not args.no_tune and args.wg == 0 and args.rows == 0:
+        from paper_2108_08418_amd.tune import tune_decode
+        (params.wg_threads, params.rows_per_step), tim = tune_decode(batch, params, llr, syn, ws, out)
+        args.wg, args.rows = params.wg_threads, params.rows_per_step
+        tuned = {f"{k[0]}x{k[1]}": round(v, 3) for k, v in tim.items()}
+        print(f"# tuned: wg={args.wg} rows={args.rows} {tuned}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        with torch.cuda.graph(graph):
+            step()
+    torch.cuda.synchronize()
+    api.profile_enable(not args.graph)
+    for k in range(8):
+        api.profile_read(k, reset=True)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay() if graph is not None else step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    api.profile_enable(False)
+    per_ms, per_n = api.profile_read(6, reset=True)
+    iters = out["iters"].cpu().numpy()
+    ok = out["ok"].cpu().numpy()
+    err = (out["bits"] != bits_g).cpu().numpy()
+    s_msg = 4 if store == api.F32 else 2
+    dec_bytes = 0.0
+    fer = {}
+    for c, q in enumerate(qcs):
+        sel = order == c
+        dec_bytes += frame_decode_bytes(iters[sel], q.n, q.m, q.n_edges, s_msg)
+        fer[str(sizes[c])] = float(1.0 - ok[sel].mean())
+    achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9 if per_ms > 0 else None
+    if achieved is None:                  # graph replay: whole step timed by the host clock
+        achieved = (args.steps * dec_bytes) / t_total / 1e9
+    wg, rows = args.wg or 512, args.rows or 1
+    mt = "float, float" if store == api.F32 else "float, __half"
+    inst = f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, {rows}>"
+    traffic, traffic_src = recorded_traffic(inst)
+    value = total_n / (t_total / args.steps)
+    result = {
+        "metric": "decoded bits/s of a batch of uneven sub-blocks (one persistent launch)",
+        "value": value, "unit": "bits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_total / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if store == api.F32 else "f32 math / f16 messages",
+        "data": "synthetic: seeded random words and BPSK/AWGN at SNR 0.16, seeded MET QC codes",
+        "config": {"workload": args.workload, "frames": F, "total_bits": total_n,
+                   "sizes": list(sizes), "counts": list(counts), "code_rate": 0.0625,
+                   "decoder": ("sum-product" if algo == api.SP else f"normalized min-sum alpha={args.alpha}"),
+                   "max_iter": args.max_iter, "graph": bool(args.graph), "wg_threads": wg, "rows_per_step": rows,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": inst, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                     "traffic_source": traffic_src,
+                     "avg_launch_us": 1e3 * per_ms / per_n if per_n else None,
+                     "algorithmic_bytes_per_launch": dec_bytes},
+        "fer": fer,
+        "mean_iters": float(iters.mean()),
+        "bit_errors": int(err.sum()),
+        "autotune_ms_per_decode": tuned,
+    }
+    print(json.dumps(result))
+
+
+def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
     """The fp64 oracle on a bounded sample of the same workload (the first
     ``cpu_frames`` sub-blocks of both coded slices), all host threads."""
     import oracle
@@ -301,8 +456,10 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n):
     A[0:2] = S[0:2]
     for j in (2, 3):
         L = oracle.slice_llr(xs, sig, th, M_BITS, oracle.GRAY, j, (1 << j) - 1, A)
-        r = oracle.decode(csr[j], L.reshape(Fs, n), syn[j], algo=algo, max_iter=args.max_iter,
-                          alpha=args.alpha, store_half=(algo == oracle.NMS))
+        sp = stage_params[j]
+        w = None if sp.weights is None else sp.weights.cpu().numpy().astype(np.float64)
+        r = oracle.decode(csr[j], L.reshape(Fs, n), syn[j], algo=algo, max_iter=sp.max_iter,
+                          alpha=args.alpha, weights=w, store_half=(algo == oracle.NMS))
         A[j] = r["bits"].reshape(-1)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

@@ -263,3 +263,74 @@ def test_repeat_runs_are_bit_identical():
     b = _decode_gpu(code, 4, L, syn, p)
     for k in ("bits", "post", "iters", "ok"):
         np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_graph_capture_replays_match_eager():
+    """The decode (queue reset + persistent kernel, no memset) captured in a HIP
+    graph: every replay, with unrelated eager work in between, equals eager."""
+    print("[decode graph]", flush=True)
+    qc, csr, L, syn, _ = _slice_stage(2, 16384, 8, seed=21)
+    code = api.Code.from_qc(qc)
+    batch = api.Batch.uniform(code, 8)
+    p = api.Params(algo=api.NMS, max_iter=60, math=api.F32, store=api.F16, alpha=0.75)
+    llr = _g(L.reshape(-1).astype(np.float32))
+    sg = _g(syn.reshape(-1))
+    ref = api.ldpc_decode_batch(batch, p, llr, sg)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    ws = api.alloc_workspace(batch, p)
+    out = {k: torch.empty_like(v) for k, v in ref.items()}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        api.ldpc_decode_batch(batch, p, llr, sg, workspace=ws, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        api.ldpc_decode_batch(batch, p, llr, sg, workspace=ws, out=out)
+    other = api.Params(algo=api.SP, max_iter=10, math=api.F32, store=api.F32)
+    for rep in range(3):
+        for v in out.values():
+            v.fill_(0x55 if v.dtype == torch.uint8 else 7)
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(out[k], ref[k]), (rep, k)
+        api.ldpc_decode_batch(batch, other, llr, sg)     # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_ragged_low_rate_met_batch_sampled_against_oracle():
+    """A scaled-down uneven batch of the low-rate MET code (sizes 4096 ...
+    65536) at SNR 0.16, NMS with binary16 messages: sampled frames of each
+    size decode bit-exactly as the binary32 oracle."""
+    print("[decode ragged MET]", flush=True)
+    sizes, counts = (4096, 16384, 65536), (24, 8, 3)
+    rng = np.random.default_rng(4)
+    order = rng.permutation(np.repeat(np.arange(3), counts))
+    qcs = [inputs.met_low_rate_spec(n) for n in sizes]
+    codes = [api.Code.from_qc(q) for q in qcs]
+    frames, vo, co = [], 0, 0
+    for c in order:
+        frames.append((int(c), vo, co))
+        vo += sizes[c]
+        co += qcs[c].m
+    bits = inputs.random_bits(vo, seed=5)
+    llr = inputs.bpsk_llr(bits, 1 / 0.16, seed=6).astype(np.float32)
+    syn = np.zeros(co, np.uint8)
+    for (c, v0, c0) in frames:
+        syn[c0:c0 + qcs[c].m] = oracle.syndrome(qcs[c].to_csr(), bits[v0:v0 + sizes[c]][None, :])[0][0]
+    batch = api.Batch(codes, frames)
+    p = api.Params(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75)
+    out = api.ldpc_decode_batch(batch, p, _g(llr), _g(syn))
+    torch.cuda.synchronize()
+    picks = [int(np.nonzero(order == c)[0][0]) for c in range(3)] + [len(frames) - 1]
+    for i in picks:
+        c, v0, c0 = frames[i]
+        n = sizes[c]
+        ref = oracle.decode(qcs[c].to_csr(), llr[v0:v0 + n][None, :].astype(np.float64), syn[c0:c0 + qcs[c].m][None, :],
+                            algo=oracle.NMS, alpha=float(np.float32(0.75)), max_iter=100, store_half=True, prec32=True)
+        assert int(out["iters"][i]) == int(ref["iters"][0])
+        assert int(out["ok"][i]) == int(ref["ok"][0])
+        np.testing.assert_array_equal(out["bits"][v0:v0 + n].cpu().numpy(), ref["bits"][0])
+        np.testing.assert_array_equal(out["post"][v0:v0 + n].cpu().numpy().astype(np.float64), ref["post"][0])
