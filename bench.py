@@ -31,6 +31,7 @@ WORKLOADS = {
     # 2^20 pairs, 16 sub-blocks of 65536
     "recon-2^20-nR2^16": dict(N=1 << 20, n=1 << 16),
     # other sweep points
+    "recon-2^27-nR2^12": dict(N=1 << 27, n=1 << 12),
     "recon-2^27-nR2^14": dict(N=1 << 27, n=1 << 14),
     "recon-2^27-nR2^18": dict(N=1 << 27, n=1 << 18),
     "recon-2^27-nR2^20": dict(N=1 << 27, n=1 << 20),
@@ -63,6 +64,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2108)
     ap.add_argument("--graph", action="store_true", help="replay the decode from a captured HIP graph")
+    ap.add_argument("--sweep", action="store_true",
+                    help="block-size sweep: every recon-2^27 workload with SP and with learned min-sum "
+                         "(--weights, default 'learned'); prints one JSON line per point")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (untimed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (HBM counter calibration) and exit")
@@ -144,9 +148,28 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes}))
         return
+    if args.sweep:
+        import copy
+        for name in sorted(k for k in WORKLOADS if k.startswith("recon-2^27")):
+            for dec, wts in (("sp", ""), ("nms", args.weights or "learned")):
+                a = copy.copy(args)
+                a.workload, a.decoder, a.weights, a.no_cpu_baseline = name, dec, wts, True
+                a.wg = a.rows = 0
+                res = recon(a, WORKLOADS[name], dev)
+                print(json.dumps(res), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     if wl.get("kind") == "ragged":
         return ragged(args, wl, dev)
+    print(json.dumps(recon(args, wl, dev)))
+
+
+def recon(args, wl, dev):
+    """The slice-reconciliation step on N pairs in sub-blocks of n; returns the result dict."""
+    import torch
+
+    from paper_2108_08418_amd import api, inputs
+
     N, n = wl["N"], wl["n"]
     F = N // n
     sig = math.sqrt(1.0 / SNR)
@@ -318,7 +341,7 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params)
-    print(json.dumps(result))
+    return result
 
 
 def ragged(args, wl, dev):

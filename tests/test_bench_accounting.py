@@ -1,0 +1,32 @@
+"""CPU checks of bench.py's algorithmic-byte accounting (the roofline numerator)."""
+import numpy as np
+
+import bench
+
+
+def test_frame_decode_bytes_counts_every_iteration_once():
+    n, m, E, s = 1024, 512, 3072, 4
+    it = np.array([0, 1, 7])
+    # per frame: t*(2 s E + 12 n) + (t+1) m + 13 n
+    expect = sum(t * (2 * s * E + 12 * n) + (t + 1) * m + 13 * n for t in it)
+    assert bench.frame_decode_bytes(it, n, m, E, s) == expect
+
+
+def test_per_edge_iteration_figure_matches_design_value():
+    # lambda(x) code: mean variable degree 3.5703; fp32 messages -> 2*4 + 12/3.57 = 11.4 B
+    # per edge-iteration for the message + posterior traffic (the 15.4 B figure adds the
+    # 4 B index of explicit codes); n large so that set-up terms vanish
+    n = 1 << 16
+    E = int(round(3.5703125 * n))
+    per = (bench.frame_decode_bytes(np.array([1000]), n, 0, E, 4) - 13 * n) / (1000 * E)
+    assert abs(per - (8 + 12 / 3.5703125)) < 1e-6
+
+
+def test_stage_bytes_check_pass_split():
+    n, m, E, s, T = 100, 50, 300, 4, 10
+    it = np.array([3, 10])
+    chk, full = bench.stage_bytes(it, T, n, m, E, s)
+    # frame stopping at 3: 4 tests, updates at t=0..3 (read at t=1..3); at T=10: 11 tests, updates t=0..9
+    expect = (4 * (4 * n + m) + (4 + 3) * s * E) + (11 * (4 * n + m) + (10 + 9) * s * E)
+    assert chk == expect
+    assert full == (3 + 10) * (2 * s * E + 12 * n)
