@@ -225,6 +225,7 @@ def recon(args, wl, dev):
     if not args.no_tune and args.wg == 0 and args.rows == 0 and args.schedule != "passes":
         # pick the launch shape on this workload's own slice-2 decode (untimed)
         step()
+        api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
         from paper_2108_08418_amd.tune import tune_decode
         (wgt, rwt), tim = tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2])
         for pp in {id(v): v for v in (params, *stage_params.values())}.values():

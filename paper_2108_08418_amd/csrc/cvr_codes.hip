@@ -266,6 +266,7 @@ static void free_batch(cvr_batch_s* b)
 {
     (void)hipFree(b->d_codes);
     (void)hipFree(b->d_frames);
+    (void)hipFree(b->d_order);
     (void)hipFree(b->d_cn_tiles);
     (void)hipFree(b->d_vn_tiles);
     (void)hipFree(b->d_qcn_tiles);
@@ -357,7 +358,15 @@ extern "C" cvr_status cvr_batch_create(const cvr_code_t* codes, int32_t n_codes,
                     qvn.push_back(Tile{f, j, u, std::min(kTile, d.Z - u) | (j == 0 && u == 0 ? kFirstTile : 0)});
         }
     }
+    // the persistent decoder hands frames out largest first (longest-processing-
+    // time order), so a few long frames do not trail at the end of a launch
+    std::vector<int32_t> order(static_cast<size_t>(F));
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return dc[b->frames_host[x].code].E > dc[b->frames_host[y].code].E;
+    });
     cvr_status st = CVR_OK;
+    if (!st) st = upload_vec(order, &b->d_order);
     if (!st) st = upload_vec(dc, &b->d_codes);
     if (!st) st = upload_vec(b->frames_host, &b->d_frames);
     if (!st) st = upload_vec(cn, &b->d_cn_tiles);

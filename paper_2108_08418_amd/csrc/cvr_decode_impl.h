@@ -352,7 +352,7 @@ struct LdsCode {
 };
 
 template <typename M, typename S, int ALGO, int MAXD, int kFrameThreads, int ROWS>
-__global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F)
+__global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F, const int32_t* order)
 {
     __shared__ LdsCode sc;
     __shared__ int32_t s_frame;
@@ -360,7 +360,10 @@ __global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t*
     const int tid = int(threadIdx.x);
     int cur = -1;
     for (;;) {
-        if (tid == 0) s_frame = atomicAdd(queue, 1);
+        if (tid == 0) {
+            const int slot = atomicAdd(queue, 1);
+            s_frame = slot < F ? order[slot] : F;
+        }
         __syncthreads();
         const int f = s_frame;
         if (f >= F) break;
@@ -610,7 +613,7 @@ static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue,
     }
     const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
     ProfScope prof(CVR_PROF_FRAMES, s);
-    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD, NT, ROWS>), dim3(grid), dim3(NT), 0, s, a, queue, b->F);
+    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD, NT, ROWS>), dim3(grid), dim3(NT), 0, s, a, queue, b->F, b->d_order);
     return check_launch("decode (persistent)");
 }
 

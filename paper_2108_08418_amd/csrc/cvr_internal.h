@@ -116,6 +116,7 @@ struct cvr_batch_s {
     std::vector<cvr::DevFrame> frames_host;
     cvr::DevCode* d_codes = nullptr;
     cvr::DevFrame* d_frames = nullptr;
+    int32_t* d_order = nullptr;           // processing order of the persistent decoder: largest frames first
     cvr::Tile* d_cn_tiles = nullptr;     // generic rows
     cvr::Tile* d_vn_tiles = nullptr;     // generic variables
     cvr::Tile* d_qcn_tiles = nullptr;    // QC rows (within a block row)
