@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
-                    "(weights/<prefix>_slice<j>.json per coded slice); sets max-iter to their T")
+                    "(weights/<prefix>_slice<j>.json per coded slice); iterations past their T reuse "
+                    "the last learned row up to --max-iter")
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent"])
     ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
     ap.add_argument("--rows", type=int, default=0, help="check rows per thread per step (0 = default)")
@@ -198,7 +199,7 @@ def recon(args, wl, dev):
         from paper_2108_08418_amd.train import load_weights
         stage_params = {}
         for j in (2, 3):
-            w = load_weights(f"{args.weights}_slice{j}")
+            w = load_weights(f"{args.weights}_slice{j}", extend_to=args.max_iter)
             stage_params[j] = replace(params, max_iter=int(w.shape[0]), weights=torch.from_numpy(w).to(dev))
     ws_bytes = max(api.decode_workspace_size(batches[j], stage_params[j]) for j in (2, 3))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)

@@ -99,10 +99,14 @@ def save(path, name, weights, meta):
                                     weights=np.asarray(weights, dtype=float).round(7).tolist(), **meta), indent=1))
 
 
-def load_weights(name: str) -> np.ndarray:
-    """Weights [T, n_types] stored under ``weights/<name>.json``."""
+def load_weights(name: str, extend_to: int | None = None) -> np.ndarray:
+    """Weights [T, n_types] stored under ``weights/<name>.json``; with
+    ``extend_to`` > T the last learned row is held for the extra iterations."""
     d = json.loads((WEIGHTS_DIR / f"{name}.json").read_text())
-    return np.asarray(d["weights"], dtype=np.float32)
+    w = np.asarray(d["weights"], dtype=np.float32)
+    if extend_to is not None and extend_to > w.shape[0]:
+        w = np.concatenate([w, np.repeat(w[-1:], extend_to - w.shape[0], axis=0)])
+    return w
 
 
 def main():
