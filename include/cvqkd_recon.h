@@ -180,9 +180,13 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            which each workgroup iterates whole frames to their stop (QC codes
  *            with <= 2048 circulants and <= 512 block rows/columns, else
  *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible.
- *  wg_threads, rows_per_step  tuning knobs of the persistent decoder that do
- *            not change results: workgroup size 256, 512 or 1024 (0 = 512) and
- *            check rows per thread per step, 1 or 2 (0 = 1).                  */
+ *  wg_threads, rows_per_step, min_waves  tuning knobs of the persistent
+ *            decoder that do not change results: workgroup size 256, 512 or
+ *            1024 (0 = 512); check rows per thread per step, 1 or 2 (0 = 1);
+ *            min_waves 8 compiles for 8 resident waves per SIMD (workgroup
+ *            512 or 1024, one row per step), 0 lets the compiler choose.
+ *            Batches with a check row of more than 8 edges run 256 or 512
+ *            threads (1024 -> 512), one row per step, min_waves ignored.      */
 enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2 };
 
 typedef struct {
@@ -196,6 +200,7 @@ typedef struct {
     int32_t schedule;
     int32_t wg_threads;
     int32_t rows_per_step;
+    int32_t min_waves;
     const float* weights;
     void* trace;
 } cvr_decode_params;

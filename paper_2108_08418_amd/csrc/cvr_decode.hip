@@ -69,6 +69,7 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
     if (p->wg_threads != 0 && p->wg_threads != 256 && p->wg_threads != 512 && p->wg_threads != 1024)
         return fail(CVR_EINVAL, "decode: wg_threads must be 0, 256, 512 or 1024");
     if (p->rows_per_step < 0 || p->rows_per_step > 2) return fail(CVR_EINVAL, "decode: rows_per_step must be 0, 1 or 2");
+    if (p->min_waves != 0 && p->min_waves != 8) return fail(CVR_EINVAL, "decode: min_waves must be 0 or 8");
     return CVR_OK;
 }
 
@@ -129,13 +130,16 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
         frames = frames_fit(batch);
     }
     int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
-    const int wg = params->wg_threads, rows = params->rows_per_step;
+    const int wg = params->wg_threads, rows = params->rows_per_step, mw = params->min_waves;
     const bool sp = params->algo == CVR_SP;
     if (params->math == CVR_F64)
-        return sp ? decode_f64_sp(batch, a, s, qc, frames, queue, wg, rows) : decode_f64_nms(batch, a, s, qc, frames, queue, wg, rows);
+        return sp ? decode_f64_sp(batch, a, s, qc, frames, queue, wg, rows, mw)
+                  : decode_f64_nms(batch, a, s, qc, frames, queue, wg, rows, mw);
     if (params->store == CVR_F32)
-        return sp ? decode_f32_sp(batch, a, s, qc, frames, queue, wg, rows) : decode_f32_nms(batch, a, s, qc, frames, queue, wg, rows);
-    return sp ? decode_f16_sp(batch, a, s, qc, frames, queue, wg, rows) : decode_f16_nms(batch, a, s, qc, frames, queue, wg, rows);
+        return sp ? decode_f32_sp(batch, a, s, qc, frames, queue, wg, rows, mw)
+                  : decode_f32_nms(batch, a, s, qc, frames, queue, wg, rows, mw);
+    return sp ? decode_f16_sp(batch, a, s, qc, frames, queue, wg, rows, mw)
+              : decode_f16_nms(batch, a, s, qc, frames, queue, wg, rows, mw);
 }
 
 extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,

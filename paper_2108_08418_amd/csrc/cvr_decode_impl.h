@@ -351,12 +351,196 @@ struct LdsCode {
     int2 col[kMaxLdsBlocks];   // x = shift, y = block id
 };
 
-template <typename M, typename S, int ALGO, int MAXD, int kFrameThreads, int ROWS>
-__global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F, const int32_t* order)
+// Wave-uniform values: with WU every wavefront's 64 rows (variables) lie in one
+// block row (column), which holds when Z is a multiple of 64; the protograph
+// entries, degrees and base pointers then live in scalar registers.
+template <bool WU>
+__device__ __forceinline__ int uni(int v)
+{
+    if constexpr (WU) return __builtin_amdgcn_readfirstlane(v);
+    else return v;
+}
+
+// Element idx of a per-frame array as base + zero-extended 32-bit byte offset,
+// the form the global-load unit takes with a scalar base.
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t idx)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t idx)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+}
+
+// Returns v unchanged through an empty asm statement.  A conditionally loaded
+// value whose only use is a conversion would otherwise get that conversion
+// moved next to its load, and with it the wait for the load, which would
+// serialize the loads of a step.
+template <typename T>
+__device__ __forceinline__ T opaque(T v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// One frame, all iterations.  Each pass is written in three phases per step:
+// protograph entries from LDS, then every global load of the step with no use
+// in between (so a wavefront has all of them in flight at once), then the
+// arithmetic.  The per-iteration min-sum weights are staged in LDS.
+template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS, bool WU>
+__device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsCode& sc, int32_t (&s_unsat)[2],
+                                             float (&s_w)[kMaxTypes], int f, const DevFrame& fr, const DevCode& cd)
+{
+    const int tid = int(threadIdx.x);
+    const int Z = cd.Z;
+    const int m = cd.mb * Z, n = cd.nb * Z;
+    const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
+    M* Lp = static_cast<M*>(a.post) + fr.vn_off;
+    const M* Lc = static_cast<const M*>(a.llr) + fr.vn_off;
+    S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
+    M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
+    for (int v = tid; v < n; v += NT) {
+        const M l = at(Lc, v);
+        at(Lp, v) = l;
+        if (tr) tr[v] = l;
+    }
+    if (tid == 0) {
+        s_unsat[0] = 0;
+        s_unsat[1] = 0;
+    }
+    if (a.weights && a.T > 0 && tid < a.n_types) s_w[tid] = a.weights[tid];
+    __syncthreads();
+    for (int t = 0;; ++t) {
+        if (a.ckpt && t < a.T && t % a.ckpt_every == 0) {
+            // checkpoint c2v(t) (all zero at t = 0) before the check pass overwrites it
+            float* ck = a.ckpt + int64_t(t / a.ckpt_every) * a.ckpt_stride + fr.msg_off;
+            const int ef = cd.NB * Z;
+            for (int e = tid; e < ef; e += NT) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(msg[e]));
+            __syncthreads();
+        }
+        // check pass: syndrome test of Lpost(t) and c2v(t+1); ROWS rows per
+        // thread per step
+        int bad = 0;
+        for (int r0 = tid; r0 < m; r0 += ROWS * NT) {
+            int q0[ROWS], d[ROWS], kk[ROWS], sraw[ROWS];
+            int2 ent[ROWS][MAXD];
+            M lr[ROWS][MAXD];
+            S mr[ROWS][MAXD];
+#pragma unroll
+            for (int h = 0; h < ROWS; ++h) {
+                const int r = r0 + h * NT;
+                const bool live = r < m;
+                const int rr = live ? r : r0;
+                const int i = uni<WU>(zsh >= 0 ? (rr >> zsh) : rr / Z);
+                kk[h] = rr - i * Z;
+                q0[h] = uni<WU>(sc.rptr[i]);
+                d[h] = live ? uni<WU>(sc.rptr[i + 1]) - q0[h] : 0;
+                sraw[h] = (syn && live) ? int(at(syn, rr)) : 0;
+#pragma unroll
+                for (int q = 0; q < MAXD; ++q) ent[h][q] = (q < d[h]) ? sc.row[q0[h] + q] : make_int2(0, 0);
+            }
+#pragma unroll
+            for (int h = 0; h < ROWS; ++h) {
+#pragma unroll
+                for (int q = 0; q < MAXD; ++q) {
+                    lr[h][q] = M(0);
+                    mr[h][q] = S(0);
+                    if (q < d[h]) {
+                        const int shift = uni<WU>(ent[h][q].x);
+                        const int col = uni<WU>(ent[h][q].y & 0xfffff);
+                        int uu = kk[h] + shift;
+                        uu = uu >= Z ? uu - Z : uu;
+                        lr[h][q] = at(Lp, uint32_t(col * Z + uu));
+                        if (t > 0) mr[h][q] = at(msg, uint32_t((q0[h] + q) * Z + kk[h]));
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < ROWS; ++h) {
+                if (d[h] == 0) continue;
+                M x[MAXD];
+                int par = sraw[h] & 1;
+                bool nan = false;
+#pragma unroll
+                for (int q = 0; q < MAXD; ++q) {
+                    x[q] = M(0);
+                    if (q < d[h]) {
+                        const M lp = lr[h][q];
+                        par ^= (lp < M(0)) ? 1 : 0;
+                        nan |= (lp != lp);
+                        x[q] = (t == 0) ? lp : lp - M(StoreT<S>::get(opaque(mr[h][q])));
+                    }
+                }
+                bad += par | (nan ? 1 : 0);
+                if (t < a.T) {
+                    const int qb = q0[h], kh = kk[h];
+                    const int2(&eh)[MAXD] = ent[h];
+                    auto weight = [&](int q) -> M { return a.weights ? M(s_w[uni<WU>(eh[q].y >> 20)]) : M(a.alpha); };
+                    auto emit = [&](int q, M v) { at(msg, uint32_t((qb + q) * Z + kh)) = StoreT<S>::put(v); };
+                    check_rule<M, ALGO, MAXD>(x, d[h], sraw[h] & 1, M(a.clamp), weight, emit);
+                }
+            }
+        }
+        if (bad) atomicAdd(&s_unsat[t & 1], bad);
+        __syncthreads();
+        const int u = s_unsat[t & 1];
+        if ((a.early_stop && u == 0) || t >= a.T) {
+            if (tid == 0) {
+                a.iters[f] = t;
+                a.ok[f] = uint8_t(u == 0);
+            }
+            break;
+        }
+        if (tid == 0) s_unsat[(t + 1) & 1] = 0;
+        // the next iteration's weights: every read of s_w for iteration t
+        // happened before the barrier above
+        if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
+        // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows
+        // ascending; the messages are loaded 8 at a time, then summed in order
+        for (int v = tid; v < n; v += NT) {
+            const int j = uni<WU>(zsh >= 0 ? (v >> zsh) : v / Z);
+            const int uu = v - j * Z;
+            const int qa = uni<WU>(sc.cptr[j]);
+            const int dv = uni<WU>(sc.cptr[j + 1]) - qa;
+            M acc = at(Lc, v);
+            for (int q8 = 0; q8 < dv; q8 += 8) {
+                int2 e[8];
+                S c[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) e[q] = (q8 + q < dv) ? sc.col[qa + q8 + q] : make_int2(0, 0);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    c[q] = S(0);
+                    if (q8 + q < dv) {
+                        const int shift = uni<WU>(e[q].x);
+                        const int blk = uni<WU>(e[q].y);
+                        int k = uu - shift;
+                        k = k < 0 ? k + Z : k;
+                        c[q] = at(msg, uint32_t(blk * Z + k));
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q8 + q < dv) acc += M(StoreT<S>::get(opaque(c[q])));
+            }
+            at(Lp, v) = acc;
+            if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
+        }
+        __syncthreads();
+    }
+    for (int v = tid; v < n; v += NT) a.bits[fr.vn_off + v] = at(Lp, v) < M(0) ? 1 : 0;
+}
+
+template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS, bool WU, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F, const int32_t* order)
 {
     __shared__ LdsCode sc;
     __shared__ int32_t s_frame;
     __shared__ int32_t s_unsat[2];
+    __shared__ float s_w[kMaxTypes];
     const int tid = int(threadIdx.x);
     int cur = -1;
     for (;;) {
@@ -365,14 +549,14 @@ __global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t*
             s_frame = slot < F ? order[slot] : F;
         }
         __syncthreads();
-        const int f = s_frame;
+        const int f = __builtin_amdgcn_readfirstlane(s_frame);     // the same for the whole workgroup
         if (f >= F) break;
         const DevFrame fr = a.frames[f];
         const DevCode& cd = a.codes[fr.code];
         if (fr.code != cur) {
-            for (int q = tid; q <= cd.mb; q += kFrameThreads) sc.rptr[q] = cd.qrow_ptr[q];
-            for (int q = tid; q <= cd.nb; q += kFrameThreads) sc.cptr[q] = cd.qcol_ptr[q];
-            for (int q = tid; q < cd.NB; q += kFrameThreads) {
+            for (int q = tid; q <= cd.mb; q += NT) sc.rptr[q] = cd.qrow_ptr[q];
+            for (int q = tid; q <= cd.nb; q += NT) sc.cptr[q] = cd.qcol_ptr[q];
+            for (int q = tid; q < cd.NB; q += NT) {
                 const QcBlock br = cd.qrow[q];
                 sc.row[q] = make_int2(br.shift, br.other | (br.type << 20));
                 const QcBlock bc = cd.qcol[q];
@@ -380,122 +564,7 @@ __global__ __launch_bounds__(kFrameThreads) void k_frames_qc(DecArgs a, int32_t*
             }
             cur = fr.code;
         }
-        const int Z = cd.Z;
-        const int m = cd.mb * Z, n = cd.nb * Z;
-        const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
-        M* Lp = static_cast<M*>(a.post) + fr.vn_off;
-        const M* Lc = static_cast<const M*>(a.llr) + fr.vn_off;
-        S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
-        const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
-        M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
-        for (int v = tid; v < n; v += kFrameThreads) {
-            const M l = Lc[v];
-            Lp[v] = l;
-            if (tr) tr[v] = l;
-        }
-        if (tid == 0) {
-            s_unsat[0] = 0;
-            s_unsat[1] = 0;
-        }
-        __syncthreads();
-        for (int t = 0;; ++t) {
-            if (a.ckpt && t < a.T && t % a.ckpt_every == 0) {
-                // checkpoint c2v(t) (all zero at t = 0) before the check pass overwrites it
-                float* ck = a.ckpt + int64_t(t / a.ckpt_every) * a.ckpt_stride + fr.msg_off;
-                const int ef = cd.NB * Z;
-                for (int e = tid; e < ef; e += kFrameThreads) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(msg[e]));
-                __syncthreads();
-            }
-            // check pass: syndrome test of Lpost(t) and c2v(t+1); ROWS rows per
-            // thread per step so that their loads are in flight together
-            int bad = 0;
-            const float* wt = a.weights ? a.weights + int64_t(t) * a.n_types : nullptr;
-            for (int r0 = tid; r0 < m; r0 += ROWS * kFrameThreads) {
-                M x[ROWS][MAXD];
-                int q0[ROWS], d[ROWS], kk[ROWS], sbit[ROWS], par[ROWS];
-                bool nan[ROWS];
-#pragma unroll
-                for (int h = 0; h < ROWS; ++h) {
-                    const int r = r0 + h * kFrameThreads;
-                    const bool live = r < m;
-                    const int rr = live ? r : r0;
-                    const int i = zsh >= 0 ? (rr >> zsh) : rr / Z;
-                    kk[h] = rr - i * Z;
-                    q0[h] = sc.rptr[i];
-                    d[h] = live ? sc.rptr[i + 1] - q0[h] : 0;
-                    sbit[h] = (syn && live) ? (syn[rr] & 1) : 0;
-                    par[h] = sbit[h];
-                    nan[h] = false;
-                }
-#pragma unroll
-                for (int h = 0; h < ROWS; ++h) {
-#pragma unroll
-                    for (int q = 0; q < MAXD; ++q) {
-                        x[h][q] = M(0);
-                        if (q < d[h]) {
-                            const int2 e = sc.row[q0[h] + q];
-                            int uu = kk[h] + e.x;
-                            uu = uu >= Z ? uu - Z : uu;
-                            const M lp = Lp[(e.y & 0xfffff) * Z + uu];
-                            par[h] ^= (lp < M(0)) ? 1 : 0;
-                            nan[h] |= (lp != lp);
-                            x[h][q] = (t == 0) ? lp : lp - M(StoreT<S>::get(msg[(q0[h] + q) * Z + kk[h]]));
-                        }
-                    }
-                }
-#pragma unroll
-                for (int h = 0; h < ROWS; ++h) {
-                    if (d[h] == 0) continue;
-                    bad += par[h] | (nan[h] ? 1 : 0);
-                    if (t < a.T) {
-                        const int qb = q0[h], kh = kk[h];
-                        auto weight = [&](int q) -> M { return wt ? M(wt[sc.row[qb + q].y >> 20]) : M(a.alpha); };
-                        auto emit = [&](int q, M v) { msg[(qb + q) * Z + kh] = StoreT<S>::put(v); };
-                        check_rule<M, ALGO, MAXD>(x[h], d[h], sbit[h], M(a.clamp), weight, emit);
-                    }
-                }
-            }
-            if (bad) atomicAdd(&s_unsat[t & 1], bad);
-            __syncthreads();
-            const int u = s_unsat[t & 1];
-            if ((a.early_stop && u == 0) || t >= a.T) {
-                if (tid == 0) {
-                    a.iters[f] = t;
-                    a.ok[f] = uint8_t(u == 0);
-                }
-                break;
-            }
-            if (tid == 0) s_unsat[(t + 1) & 1] = 0;
-            // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows
-            // ascending; the messages are loaded 8 at a time, then summed in order
-            for (int v = tid; v < n; v += kFrameThreads) {
-                const int j = zsh >= 0 ? (v >> zsh) : v / Z;
-                const int uu = v - j * Z;
-                const int qa = sc.cptr[j];
-                const int dv = sc.cptr[j + 1] - qa;
-                M acc = Lc[v];
-                for (int q8 = 0; q8 < dv; q8 += 8) {
-                    M c[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        c[q] = M(0);
-                        if (q8 + q < dv) {
-                            const int2 e = sc.col[qa + q8 + q];
-                            int k = uu - e.x;
-                            k = k < 0 ? k + Z : k;
-                            c[q] = M(StoreT<S>::get(msg[e.y * Z + k]));
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (q8 + q < dv) acc += c[q];
-                }
-                Lp[v] = acc;
-                if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
-            }
-            __syncthreads();
-        }
-        for (int v = tid; v < n; v += kFrameThreads) a.bits[fr.vn_off + v] = Lp[v] < M(0) ? 1 : 0;
+        decode_frame<M, S, ALGO, MAXD, NT, ROWS, WU>(a, sc, s_unsat, s_w, f, fr, cd);
     }
 }
 
@@ -600,46 +669,69 @@ static inline int device_cus()
     return cus;
 }
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS>
+template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS, bool WU, int MINW>
 static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s)
 {
     static int per_cu = 0;      // resident workgroups per CU of this instantiation
     if (per_cu == 0) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_frames_qc<M, S, ALGO, MAXD, NT, ROWS>, NT, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_frames_qc<M, S, ALGO, MAXD, NT, ROWS, WU, MINW>, NT, 0) !=
+                hipSuccess ||
             v < 1)
             v = 1;
         per_cu = v;
     }
     const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
     ProfScope prof(CVR_PROF_FRAMES, s);
-    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD, NT, ROWS>), dim3(grid), dim3(NT), 0, s, a, queue, b->F, b->d_order);
+    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD, NT, ROWS, WU, MINW>), dim3(grid), dim3(NT), 0, s, a, queue, b->F,
+                       b->d_order);
     return check_launch("decode (persistent)");
 }
 
+// Every code of the batch has Z % 64 == 0: each wavefront stays inside one
+// block row / column, and the wave-uniform kernel applies.
+static inline bool wave_uniform(const cvr_batch_s* b)
+{
+    for (const cvr_code_t c : b->codes)
+        if (c->dev.Z % 64) return false;
+    return true;
+}
+
 template <typename M, typename S, int ALGO, int MAXD>
-static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int wg, int rows)
+static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int wg, int rows,
+                             int minw)
 {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, queue, int64_t(1));
     if (cvr_status st = check_launch("decode queue reset")) return st;
-    if (rows == 2) {
-        if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 2>(b, a, queue, s);
-        if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 2>(b, a, queue, s);
-        return launch_frames<M, S, ALGO, MAXD, 512, 2>(b, a, queue, s);
+    if (!wave_uniform(b)) return launch_frames<M, S, ALGO, MAXD, 512, 1, false, 1>(b, a, queue, s);
+    if constexpr (MAXD > 8) {
+        // rows of more than 8 edges need more registers than the wide shapes
+        // leave (they would spill): 256 or 512 threads, one row per step
+        if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 1, true, 1>(b, a, queue, s);
+        return launch_frames<M, S, ALGO, MAXD, 512, 1, true, 1>(b, a, queue, s);
     }
-    if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 1>(b, a, queue, s);
-    if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 1>(b, a, queue, s);
-    return launch_frames<M, S, ALGO, MAXD, 512, 1>(b, a, queue, s);
+    if (minw == 8) {
+        if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 1, true, 8>(b, a, queue, s);
+        return launch_frames<M, S, ALGO, MAXD, 512, 1, true, 8>(b, a, queue, s);
+    }
+    if (rows == 2) {
+        if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 2, true, 1>(b, a, queue, s);
+        if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 2, true, 1>(b, a, queue, s);
+        return launch_frames<M, S, ALGO, MAXD, 512, 2, true, 1>(b, a, queue, s);
+    }
+    if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 1, true, 1>(b, a, queue, s);
+    if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 1, true, 1>(b, a, queue, s);
+    return launch_frames<M, S, ALGO, MAXD, 512, 1, true, 1>(b, a, queue, s);
 }
 
 template <typename M, typename S, int ALGO>
 static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue,
-                               int wg, int rows)
+                               int wg, int rows, int minw)
 {
     if (frames) {
-        if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, wg, rows);
-        if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, wg, rows);
-        return run_frames<M, S, ALGO, 32>(b, a, queue, s, wg, rows);
+        if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, wg, rows, minw);
+        if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, wg, rows, minw);
+        return run_frames<M, S, ALGO, 32>(b, a, queue, s, wg, rows, minw);
     }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
@@ -690,7 +782,7 @@ static inline bool frames_fit(const cvr_batch_s* b)
 // One instantiation per (math, store, rule); each lives in its own translation unit.
 #define CVR_DECL_DISPATCH(NAME)                                                                      \
     cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue, \
-                    int wg, int rows)
+                    int wg, int rows, int minw)
 CVR_DECL_DISPATCH(decode_f64_sp);
 CVR_DECL_DISPATCH(decode_f64_nms);
 CVR_DECL_DISPATCH(decode_f32_sp);

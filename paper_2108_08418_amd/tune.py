@@ -9,17 +9,17 @@ from __future__ import annotations
 
 from . import api
 
-CANDIDATES = [(512, 1), (1024, 1), (256, 1), (512, 2), (1024, 2), (256, 2)]
+CANDIDATES = [(512, 1, 0), (1024, 1, 0), (256, 1, 0), (512, 2, 0), (1024, 2, 0), (512, 1, 8), (1024, 1, 8)]
 
 
 def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, candidates=CANDIDATES):
-    """Returns ((wg_threads, rows_per_step), {candidate: ms per decode})."""
+    """Returns ((wg_threads, rows_per_step, min_waves), {candidate: ms per decode})."""
     import torch
     timings = {}
-    saved = (params.wg_threads, params.rows_per_step)
+    saved = (params.wg_threads, params.rows_per_step, params.min_waves)
     try:
-        for wg, rows in candidates:
-            params.wg_threads, params.rows_per_step = wg, rows
+        for wg, rows, mw in candidates:
+            params.wg_threads, params.rows_per_step, params.min_waves = wg, rows, mw
             api.ldpc_decode_batch(batch, params, llr, syndrome, workspace=workspace, out=out)   # warm
             torch.cuda.synchronize()
             api.profile_enable(True)
@@ -29,9 +29,9 @@ def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, 
             torch.cuda.synchronize()
             api.profile_enable(False)
             ms, cnt = api.profile_read(api.PROF_FRAMES, reset=True)
-            timings[(wg, rows)] = ms / max(cnt, 1)
+            timings[(wg, rows, mw)] = ms / max(cnt, 1)
     finally:
-        params.wg_threads, params.rows_per_step = saved
+        params.wg_threads, params.rows_per_step, params.min_waves = saved
         api.profile_enable(False)
     best = min(timings, key=timings.get)
     return best, timings

@@ -116,13 +116,16 @@ def test_layouts_and_schedules_are_bit_identical():
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8),
                  dict(algo=api.NMS, store=api.F32, alpha=0.7)):
         runs = []
-        for code, sched, wg, rows in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0),
-                                      (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 256, 2),
-                                      (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 1),
-                                      (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 2),
-                                      (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0),
-                                      (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0)):
-            p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, rows_per_step=rows, **base)
+        for code, sched, wg, rows, mw in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, 0),
+                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 256, 2, 0),
+                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 1, 0),
+                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 2, 0),
+                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 1, 8),
+                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 1, 8),
+                                          (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0, 0),
+                                          (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0)):
+            p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, rows_per_step=rows,
+                           min_waves=mw, **base)
             runs.append(_decode_gpu(code, F, L, syn, p, trace=True))
         for r in runs[1:]:
             for k in ("bits", "post", "iters", "ok", "trace"):
