@@ -60,7 +60,6 @@ def parse():
                     "the last learned row up to --max-iter")
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent"])
     ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
-    ap.add_argument("--rows", type=int, default=0, help="check rows per thread per step (0 = default)")
     ap.add_argument("--min-waves", dest="min_waves", type=int, default=0, help="0 or 8 resident waves per SIMD")
     ap.add_argument("--cpu-frames", type=int, default=16, help="sub-blocks per stage in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -156,7 +155,7 @@ def main():
             for dec, wts in (("sp", ""), ("nms", args.weights or "learned")):
                 a = copy.copy(args)
                 a.workload, a.decoder, a.weights, a.no_cpu_baseline = name, dec, wts, True
-                a.wg = a.rows = a.min_waves = 0
+                a.wg = a.min_waves = 0
                 res = recon(a, WORKLOADS[name], dev)
                 print(json.dumps(res), flush=True)
         return
@@ -190,7 +189,7 @@ def recon(args, wl, dev):
     store = api.F32 if args.decoder == "sp" else api.F16
     sched = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT}[args.schedule]
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        schedule=sched, wg_threads=args.wg, rows_per_step=args.rows, min_waves=args.min_waves)
+                        schedule=sched, wg_threads=args.wg, min_waves=args.min_waves)
     stage_params = {2: params, 3: params}
     if args.weights:
         if algo != api.NMS:
@@ -224,17 +223,19 @@ def recon(args, wl, dev):
         api.ldpc_decode_batch(batches[3], stage_params[3], llr, syn[3], workspace=ws, out=outs[3])
 
     tuned = None
-    if not args.no_tune and args.wg == 0 and args.rows == 0 and args.schedule != "passes":
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    persistent = args.schedule == "persistent" or (args.schedule == "auto" and batches[2].F >= cus)
+    if not args.no_tune and args.wg == 0 and persistent:
         # pick the launch shape on this workload's own slice-2 decode (untimed)
         step()
         api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
         from paper_2108_08418_amd.tune import tune_decode
-        (wgt, rwt, mwt), tim = tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2])
+        best, tim = tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2])
         for pp in {id(v): v for v in (params, *stage_params.values())}.values():
-            pp.wg_threads, pp.rows_per_step, pp.min_waves = wgt, rwt, mwt
-        args.wg, args.rows, args.min_waves = wgt, rwt, mwt
-        tuned = {f"{k[0]}x{k[1]}w{k[2]}": round(v, 3) for k, v in tim.items()}
-        print(f"# tuned: wg={args.wg} rows={args.rows} min_waves={args.min_waves} {tuned}", file=sys.stderr, flush=True)
+            pp.wg_threads, pp.min_waves = best
+        args.wg, args.min_waves = best
+        tuned = {f"{k[0]}w{k[1]}": round(v, 3) for k, v in tim.items()}
+        print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -277,9 +278,8 @@ def recon(args, wl, dev):
     traffic = traffic_src = None
     if per_ms > 0:
         wg = args.wg or 512
-        rows = args.rows or 1
         mt = "float, float" if store == api.F32 else "float, __half"
-        inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, {rows}, true, "
+        inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
                 f"{8 if args.min_waves == 8 else 1}>")
         roof_kernel = inst
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
@@ -311,7 +311,7 @@ def recon(args, wl, dev):
             "decoder": ("sum-product" if algo == api.SP else
                         (f"learned normalized min-sum ({args.weights})" if args.weights else
                          f"normalized min-sum alpha={args.alpha}")),
-            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "rows_per_step": args.rows, "min_waves": args.min_waves,
+            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "min_waves": args.min_waves,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -385,7 +385,7 @@ def ragged(args, wl, dev):
     algo = api.SP if args.decoder == "sp" else api.NMS
     store = api.F32 if args.decoder == "sp" else api.F16
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        wg_threads=args.wg, rows_per_step=args.rows, min_waves=args.min_waves)
+                        wg_threads=args.wg, min_waves=args.min_waves)
     ws = api.alloc_workspace(batch, params, dev)
     out = dict(bits=torch.empty(total_n, dtype=torch.uint8, device=dev), post=None,
                iters=torch.empty(F, dtype=torch.int32, device=dev), ok=torch.empty(F, dtype=torch.uint8, device=dev))
@@ -396,12 +396,13 @@ def ragged(args, wl, dev):
         api.ldpc_decode_batch(batch, params, llr, syn, workspace=ws, out=out)
 
     tuned = None
-    if not args.no_tune and args.wg == 0 and args.rows == 0:
+    if not args.no_tune and args.wg == 0:
         from paper_2108_08418_amd.tune import tune_decode
-        (params.wg_threads, params.rows_per_step, params.min_waves), tim = tune_decode(batch, params, llr, syn, ws, out)
-        args.wg, args.rows, args.min_waves = params.wg_threads, params.rows_per_step, params.min_waves
-        tuned = {f"{k[0]}x{k[1]}w{k[2]}": round(v, 3) for k, v in tim.items()}
-        print(f"# tuned: wg={args.wg} rows={args.rows} min_waves={args.min_waves} {tuned}", file=sys.stderr, flush=True)
+        best, tim = tune_decode(batch, params, llr, syn, ws, out)
+        params.wg_threads, params.min_waves = best
+        args.wg, args.min_waves = best
+        tuned = {f"{k[0]}w{k[1]}": round(v, 3) for k, v in tim.items()}
+        print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     graph = None
@@ -438,9 +439,9 @@ def ragged(args, wl, dev):
     achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9 if per_ms > 0 else None
     if achieved is None:                  # graph replay: whole step timed by the host clock
         achieved = (args.steps * dec_bytes) / t_total / 1e9
-    wg, rows = args.wg or 512, args.rows or 1
+    wg = args.wg or 512
     mt = "float, float" if store == api.F32 else "float, __half"
-    inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, {rows}, true, "
+    inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
             f"{8 if args.min_waves == 8 else 1}>")
     traffic, traffic_src = recorded_traffic(inst)
     value = total_n / (t_total / args.steps)
@@ -453,7 +454,7 @@ def ragged(args, wl, dev):
         "config": {"workload": args.workload, "frames": F, "total_bits": total_n,
                    "sizes": list(sizes), "counts": list(counts), "code_rate": 0.0625,
                    "decoder": ("sum-product" if algo == api.SP else f"normalized min-sum alpha={args.alpha}"),
-                   "max_iter": args.max_iter, "graph": bool(args.graph), "wg_threads": wg, "rows_per_step": rows,
+                   "max_iter": args.max_iter, "graph": bool(args.graph), "wg_threads": wg,
                    "min_waves": args.min_waves,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": inst, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

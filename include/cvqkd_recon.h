@@ -178,15 +178,14 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            CVR_SCHED_PASSES: two kernel launches per iteration over all
  *            frames (any code); CVR_SCHED_PERSISTENT: one persistent launch in
  *            which each workgroup iterates whole frames to their stop (QC codes
- *            with <= 2048 circulants and <= 512 block rows/columns, else
- *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible.
- *  wg_threads, rows_per_step, min_waves  tuning knobs of the persistent
- *            decoder that do not change results: workgroup size 256, 512 or
- *            1024 (0 = 512); check rows per thread per step, 1 or 2 (0 = 1);
- *            min_waves 8 compiles for 8 resident waves per SIMD (workgroup
- *            512 or 1024, one row per step), 0 lets the compiler choose.
- *            Batches with a check row of more than 8 edges run 256 or 512
- *            threads (1024 -> 512), one row per step, min_waves ignored.      */
+ *            with <= 2048 circulants, <= 512 block rows/columns and Z <= 65535, else
+ *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible
+ *            and the batch has at least one frame per compute unit, else passes.
+ *  wg_threads, min_waves  tuning knobs of the persistent decoder that do
+ *            not change results: workgroup size 512 or 1024 (0 = 512);
+ *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
+ *            compiler choose.  Binary64 math and batches with a check row of
+ *            more than 8 edges always run 512 threads.                        */
 enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2 };
 
 typedef struct {
@@ -199,7 +198,6 @@ typedef struct {
     float msg_clamp;           /* > 0; SP only */
     int32_t schedule;
     int32_t wg_threads;
-    int32_t rows_per_step;
     int32_t min_waves;
     const float* weights;
     void* trace;

@@ -149,7 +149,6 @@ class Params:
     weights: torch.Tensor | None = None   # device fp32 [max_iter, n_types]
     schedule: int = SCHED_AUTO
     wg_threads: int = 0
-    rows_per_step: int = 0
     min_waves: int = 0
 
     def c_struct(self, trace: torch.Tensor | None = None) -> DecodeParams:
@@ -158,7 +157,6 @@ class Params:
         p.math, p.store, p.alpha, p.msg_clamp = int(self.math), int(self.store), float(self.alpha), float(self.msg_clamp)
         p.schedule = int(self.schedule)
         p.wg_threads = int(self.wg_threads)
-        p.rows_per_step = int(self.rows_per_step)
         p.min_waves = int(self.min_waves)
         if self.weights is not None:
             if self.weights.dtype != torch.float32:

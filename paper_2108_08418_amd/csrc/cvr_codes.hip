@@ -328,6 +328,11 @@ extern "C" cvr_status cvr_batch_create(const cvr_code_t* codes, int32_t n_codes,
         b->total_m = std::max(b->total_m, fr.chk_offset + d.m);
         b->max_row_deg = std::max(b->max_row_deg, d.max_row_deg);
         b->max_types = std::max(b->max_types, d.n_types);
+        if (d.is_qc) {
+            b->max_mb = std::max(b->max_mb, d.mb);
+            b->max_nb = std::max(b->max_nb, d.nb);
+            b->max_NB = std::max(b->max_NB, d.NB);
+        }
         if (!d.is_qc) b->all_qc = false;
     }
     b->total_E = msg;

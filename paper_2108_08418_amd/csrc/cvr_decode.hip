@@ -66,9 +66,8 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
         return fail(CVR_EUNSUPPORTED, "decode: F64 math is implemented with F64 storage only");
     if (p->algo == CVR_SP && !(p->msg_clamp > 0.0f)) return fail(CVR_EINVAL, "decode: msg_clamp must be > 0");
     if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_PERSISTENT) return fail(CVR_EINVAL, "decode: bad schedule");
-    if (p->wg_threads != 0 && p->wg_threads != 256 && p->wg_threads != 512 && p->wg_threads != 1024)
-        return fail(CVR_EINVAL, "decode: wg_threads must be 0, 256, 512 or 1024");
-    if (p->rows_per_step < 0 || p->rows_per_step > 2) return fail(CVR_EINVAL, "decode: rows_per_step must be 0, 1 or 2");
+    if (p->wg_threads != 0 && p->wg_threads != 512 && p->wg_threads != 1024)
+        return fail(CVR_EINVAL, "decode: wg_threads must be 0, 512 or 1024");
     if (p->min_waves != 0 && p->min_waves != 8) return fail(CVR_EINVAL, "decode: min_waves must be 0 or 8");
     return CVR_OK;
 }
@@ -124,22 +123,21 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
     if (params->schedule == CVR_SCHED_PERSISTENT) {
         if (!frames_fit(batch))
             return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the persistent schedule needs QC codes with <= 2048 "
-                                          "circulants and <= 512 block rows/columns");
+                                          "circulants, <= 512 block rows/columns and Z <= 65535");
         frames = true;
     } else if (params->schedule == CVR_SCHED_AUTO) {
-        frames = frames_fit(batch);
+        // a workgroup per frame leaves compute units idle below one frame per
+        // CU; the per-pass kernels spread every frame's rows over the chip
+        frames = frames_fit(batch) && batch->F >= device_cus();
     }
     int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
-    const int wg = params->wg_threads, rows = params->rows_per_step, mw = params->min_waves;
+    const LaunchShape sh{params->wg_threads, params->min_waves};
     const bool sp = params->algo == CVR_SP;
     if (params->math == CVR_F64)
-        return sp ? decode_f64_sp(batch, a, s, qc, frames, queue, wg, rows, mw)
-                  : decode_f64_nms(batch, a, s, qc, frames, queue, wg, rows, mw);
+        return sp ? decode_f64_sp(batch, a, s, qc, frames, queue, sh) : decode_f64_nms(batch, a, s, qc, frames, queue, sh);
     if (params->store == CVR_F32)
-        return sp ? decode_f32_sp(batch, a, s, qc, frames, queue, wg, rows, mw)
-                  : decode_f32_nms(batch, a, s, qc, frames, queue, wg, rows, mw);
-    return sp ? decode_f16_sp(batch, a, s, qc, frames, queue, wg, rows, mw)
-              : decode_f16_nms(batch, a, s, qc, frames, queue, wg, rows, mw);
+        return sp ? decode_f32_sp(batch, a, s, qc, frames, queue, sh) : decode_f32_nms(batch, a, s, qc, frames, queue, sh);
+    return sp ? decode_f16_sp(batch, a, s, qc, frames, queue, sh) : decode_f16_nms(batch, a, s, qc, frames, queue, sh);
 }
 
 extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,

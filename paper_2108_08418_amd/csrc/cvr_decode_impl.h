@@ -32,27 +32,25 @@ namespace cvr {
 // ---------------------------------------------------------------------------
 // phi(x) = -ln tanh(x/2) = 2 atanh(e^-x) = ln((1 + e^-x) / (1 - e^-x)), x >= 0;
 // phi(0) = inf, phi(inf) = 0, and phi(phi(x)) = x.
-// binary32: one hardware exponential, then either the odd series of 2 atanh(u)
-// (u = e^-x < 1/4, truncation < 5e-9 relative) or one hardware logarithm of
-// (1 + u) / (1 - u), with 1 - u from its Taylor series below x = 1/8 where the
-// subtraction would cancel.  Relative error stays near 2e-6.
+// binary32, branch-free on the hardware exp2 / reciprocal / log2 (about 1 ulp
+// each): u = e^-x; where u < 1/8 the odd series of 2 atanh(u) to u^7 (the rest
+// is below u^8/9 / (1 - u^2) < 7e-9 relative), elsewhere ln((1 + u) / (1 - u))
+// (>= ln(9/7), so the log keeps its relative accuracy) with 1 - u from its
+// Taylor series below x = 1/8 where the subtraction would cancel.  Relative
+// error stays below about 1e-6.
 __device__ __forceinline__ float phi(float x)
 {
-    const float u = __expf(-x);
-    if (u < 0.25f) {
-        const float u2 = u * u;
-        float p = 1.0f / 11.0f;
-        p = p * u2 + 1.0f / 9.0f;
-        p = p * u2 + 1.0f / 7.0f;
-        p = p * u2 + 1.0f / 5.0f;
-        p = p * u2 + 1.0f / 3.0f;
-        p = p * u2 + 1.0f;
-        return 2.0f * u * p;
-    }
-    const float omu = (x < 0.125f)
-        ? x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))))
-        : 1.0f - u;
-    return __logf(__fdividef(1.0f + u, omu));
+    const float u = __builtin_amdgcn_exp2f(x * -1.44269504f);
+    const float u2 = u * u;
+    float p = 1.0f / 7.0f;
+    p = p * u2 + 1.0f / 5.0f;
+    p = p * u2 + 1.0f / 3.0f;
+    p = p * u2 + 1.0f;
+    const float series = 2.0f * u * p;
+    const float taylor = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))));
+    const float omu = (x < 0.125f) ? taylor : 1.0f - u;
+    const float lg = __builtin_amdgcn_logf((1.0f + u) * __builtin_amdgcn_rcpf(omu)) * 0.693147181f;
+    return (u < 0.125f) ? series : lg;
 }
 // binary64: the library's correctly rounded-ish expm1 / log1p.
 __device__ __forceinline__ double phi(double x) { return log1p(2.0 / expm1(x)); }
@@ -115,19 +113,19 @@ __device__ __forceinline__ void check_rule(const M (&x)[MAXD], int d, int syn, M
             }
         }
     } else {
+        // smallest and second smallest |x| and the first position of the
+        // smallest, branch-free; a NaN compares false and changes nothing
         M m1 = M(INFINITY), m2 = M(INFINITY);
         int i1 = -1;
 #pragma unroll
         for (int k = 0; k < MAXD; ++k) {
             if (k < d) {
                 const M v = mabs(x[k]);
-                if (v < m1) {
-                    m2 = m1;
-                    m1 = v;
-                    i1 = k;
-                } else if (v < m2) {
-                    m2 = v;
-                }
+                const bool lt = v < m1;
+                const M c = (v < m2) ? v : m2;
+                m2 = lt ? m1 : c;
+                i1 = lt ? k : i1;
+                m1 = lt ? v : m1;
             }
         }
 #pragma unroll
@@ -172,11 +170,44 @@ struct DecArgs {
     int32_t ckpt_every;
 };
 
+// Tuning knobs of the persistent decoder (none of them changes results).
+struct LaunchShape {
+    int32_t wg, min_waves;
+};
+
 __device__ __forceinline__ void add_unsat(int32_t* slot, int pred)
 {
     const int cnt = __syncthreads_count(pred);
     if (threadIdx.x == 0 && cnt) atomicAdd(slot, cnt);
 }
+
+// Returns v unchanged through an empty asm statement.  A conditionally loaded
+// value whose only use is a conversion would otherwise get that conversion
+// moved next to its load, and with it the wait for the load, which would
+// serialize the loads of a step.
+template <typename T>
+__device__ __forceinline__ T opaque(T v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Element idx of a per-frame array as base + zero-extended 32-bit byte offset,
+// the form the global-load unit takes with a scalar base.
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t idx)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, uint32_t idx)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+}
+
+// Every pass below is written in phases: indices / protograph entries, then all
+// global loads of the step with no use in between (so they are in flight
+// together), then the arithmetic.
 
 // ---------------------------------------------------------------------------
 // generic (explicit CSR) passes
@@ -197,6 +228,20 @@ __global__ __launch_bounds__(kTile) void k_check_generic(DecArgs a)
         const int e0 = cd.row_ptr[r];
         const int d = cd.row_ptr[r + 1] - e0;
         const int syn = a.syn ? (a.syn[fr.chk_off + r] & 1) : 0;
+        int col[MAXD];
+        M lr[MAXD];
+        S mr[MAXD];
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) {
+            col[k] = 0;
+            mr[k] = S(0);
+            if (k < d) {
+                col[k] = cd.col_idx[e0 + k];
+                if (a.t > 0) mr[k] = msg[e0 + k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MAXD; ++k) lr[k] = (k < d) ? at(Lp, uint32_t(col[k])) : M(0);
         int par = syn;
         bool nan = false;
         M x[MAXD];
@@ -204,10 +249,10 @@ __global__ __launch_bounds__(kTile) void k_check_generic(DecArgs a)
         for (int k = 0; k < MAXD; ++k) {
             x[k] = M(0);
             if (k < d) {
-                const M lp = Lp[cd.col_idx[e0 + k]];
+                const M lp = lr[k];
                 par ^= (lp < M(0)) ? 1 : 0;
                 nan |= (lp != lp);
-                x[k] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(msg[e0 + k]));
+                x[k] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(opaque(mr[k])));
             }
         }
         bad = par | (nan ? 1 : 0);
@@ -253,7 +298,18 @@ __global__ __launch_bounds__(kTile) void k_var_generic(DecArgs a)
     if (int(threadIdx.x) >= count) return;
     const S* msg = static_cast<const S*>(a.c2v) + fr.msg_off;
     M acc = static_cast<const M*>(a.llr)[fr.vn_off + v];
-    for (int k = cd.col_ptr[v]; k < cd.col_ptr[v + 1]; ++k) acc += M(StoreT<S>::get(msg[cd.col_edge[k]]));
+    const int k0 = cd.col_ptr[v], dv = cd.col_ptr[v + 1] - k0;
+    for (int q8 = 0; q8 < dv; q8 += 8) {            // CSR edge order, 8 loads at a time
+        int ed[8];
+        S c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ed[q] = (q8 + q < dv) ? cd.col_edge[k0 + q8 + q] : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = (q8 + q < dv) ? at(msg, uint32_t(ed[q])) : S(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q8 + q < dv) acc += M(StoreT<S>::get(opaque(c[q])));
+    }
     static_cast<M*>(a.post)[fr.vn_off + v] = acc;
     if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
 }
@@ -279,6 +335,23 @@ __global__ __launch_bounds__(kTile) void k_check_qc(DecArgs a)
     int bad = 0;
     if (int(threadIdx.x) < count) {
         const int syn = a.syn ? (a.syn[fr.chk_off + int64_t(i) * Z + k] & 1) : 0;
+        QcBlock blk[MAXD];
+        M lr[MAXD];
+        S mr[MAXD];
+#pragma unroll
+        for (int q = 0; q < MAXD; ++q)
+            if (q < d) blk[q] = cd.qrow[q0 + q];
+#pragma unroll
+        for (int q = 0; q < MAXD; ++q) {
+            lr[q] = M(0);
+            mr[q] = S(0);
+            if (q < d) {
+                int u = k + blk[q].shift;
+                u = u >= Z ? u - Z : u;
+                lr[q] = at(Lp, uint32_t(blk[q].other * Z + u));
+                if (a.t > 0) mr[q] = at(msg, uint32_t(blk[q].blk * Z + k));
+            }
+        }
         int par = syn;
         bool nan = false;
         M x[MAXD];
@@ -286,20 +359,17 @@ __global__ __launch_bounds__(kTile) void k_check_qc(DecArgs a)
         for (int q = 0; q < MAXD; ++q) {
             x[q] = M(0);
             if (q < d) {
-                const QcBlock blk = cd.qrow[q0 + q];
-                int u = k + blk.shift;
-                u = u >= Z ? u - Z : u;
-                const M lp = Lp[int64_t(blk.other) * Z + u];
+                const M lp = lr[q];
                 par ^= (lp < M(0)) ? 1 : 0;
                 nan |= (lp != lp);
-                x[q] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(msg[int64_t(blk.blk) * Z + k]));
+                x[q] = (a.t == 0) ? lp : lp - M(StoreT<S>::get(opaque(mr[q])));
             }
         }
         bad = par | (nan ? 1 : 0);
         if (a.t < a.T) {
             const float* wt = a.weights ? a.weights + int64_t(a.t) * a.n_types : nullptr;
-            auto weight = [&](int q) -> M { return wt ? M(wt[cd.qrow[q0 + q].type]) : M(a.alpha); };
-            auto emit = [&](int q, M v) { msg[int64_t(cd.qrow[q0 + q].blk) * Z + k] = StoreT<S>::put(v); };
+            auto weight = [&](int q) -> M { return wt ? M(wt[blk[q].type]) : M(a.alpha); };
+            auto emit = [&](int q, M v) { at(msg, uint32_t(blk[q].blk * Z + k)) = StoreT<S>::put(v); };
             check_rule<M, ALGO, MAXD>(x, d, syn, M(a.clamp), weight, emit);
         }
     }
@@ -322,11 +392,25 @@ __global__ __launch_bounds__(kTile) void k_var_qc(DecArgs a)
     const S* msg = static_cast<const S*>(a.c2v) + fr.msg_off;
     const int64_t v = int64_t(j) * Z + u;
     M acc = static_cast<const M*>(a.llr)[fr.vn_off + v];
-    for (int q = cd.qcol_ptr[j]; q < cd.qcol_ptr[j + 1]; ++q) {      // block rows ascending
-        const QcBlock blk = cd.qcol[q];
-        int k = u - blk.shift;
-        k = k < 0 ? k + Z : k;
-        acc += M(StoreT<S>::get(msg[int64_t(blk.blk) * Z + k]));
+    const int qa = cd.qcol_ptr[j], dv = cd.qcol_ptr[j + 1] - qa;
+    for (int q8 = 0; q8 < dv; q8 += 8) {            // block rows ascending, 8 loads at a time
+        QcBlock blk[8];
+        S c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q8 + q < dv) blk[q] = cd.qcol[qa + q8 + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            c[q] = S(0);
+            if (q8 + q < dv) {
+                int k = u - blk[q].shift;
+                k = k < 0 ? k + Z : k;
+                c[q] = at(msg, uint32_t(blk[q].blk * Z + k));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q8 + q < dv) acc += M(StoreT<S>::get(opaque(c[q])));
     }
     static_cast<M*>(a.post)[fr.vn_off + v] = acc;
     if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
@@ -338,17 +422,19 @@ __global__ __launch_bounds__(kTile) void k_var_qc(DecArgs a)
 // Each workgroup takes whole frames from an atomic queue and runs all of a
 // frame's iterations itself: the two half-iterations are separated by
 // __syncthreads only, so frames stop independently, no grid-wide barrier or
-// per-iteration launch exists, and a frame's state is touched by one CU only
-// (it stays in that XCD's L2 / the Infinity Cache while the frame is decoded).
-// The protograph tables of the current code are cached in LDS.
-constexpr int kMaxLdsBlocks = 2048;
+// per-iteration launch exists, and a frame's state is touched by one CU only.
+constexpr int kMaxLdsBlocks = 2048;   // protograph limits of the persistent path
 constexpr int kMaxLdsDim = 512;
+constexpr int kMaxLdsZ = 65535;
 
-struct LdsCode {
-    int32_t rptr[kMaxLdsDim + 1];
-    int32_t cptr[kMaxLdsDim + 1];
-    int2 row[kMaxLdsBlocks];   // x = shift, y = block column | type << 20 (block id = position)
-    int2 col[kMaxLdsBlocks];   // x = shift, y = block id
+// Dynamic LDS of the persistent decoder: the protograph tables of the current
+// code, in 32-bit words at the offsets that LdsMap carries (sized for the
+// largest code of the batch):
+//   rptr [mb+1], cptr [nb+1]   block-row / block-column pointers
+//   row  [NB]   shift | block column << 16 | type << 25 (block id = position)
+//   col  [NB]   shift | block id << 16
+struct LdsMap {
+    int32_t rptr, cptr, row, col, words;
 };
 
 // Wave-uniform values: with WU every wavefront's 64 rows (variables) lie in one
@@ -361,50 +447,183 @@ __device__ __forceinline__ int uni(int v)
     else return v;
 }
 
-// Element idx of a per-frame array as base + zero-extended 32-bit byte offset,
-// the form the global-load unit takes with a scalar base.
-template <typename T>
-__device__ __forceinline__ T& at(T* base, uint32_t idx)
+// What the row and column steps of one frame need.
+template <typename M, typename S>
+struct FrameCtx {
+    M* Lp;
+    const M* Lc;
+    S* msg;
+    const int32_t* s_row;
+    const int32_t* s_col;
+    const float* s_w;
+    int Z, t, T;
+    bool weighted;
+    float alpha, clamp;
+};
+
+// Check row k of the block row whose table entries start at q0, with exactly D
+// edges (D and the entries wave-uniform): the D posteriors and, for t > 0, the
+// D stored messages are loaded before any arithmetic; the code is straight-line.
+// Returns 1 when the row's syndrome test fails on Lpost(t).
+template <typename M, typename S, int ALGO, int D, bool WU>
+__device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k, int sraw)
 {
-    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * uint32_t(sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ const T& at(const T* base, uint32_t idx)
-{
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+    int32_t e[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) e[q] = uni<WU>(c.s_row[q0 + q]);
+    M lr[D];
+    S mr[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        int uu = k + (e[q] & 0xffff);
+        uu = uu >= c.Z ? uu - c.Z : uu;
+        lr[q] = at(c.Lp, uint32_t(((e[q] >> 16) & 0x1ff) * c.Z + uu));
+    }
+    if (c.t > 0) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) mr[q] = at(c.msg, uint32_t((q0 + q) * c.Z + k));
+    } else {
+#pragma unroll
+        for (int q = 0; q < D; ++q) mr[q] = S(0);      // c2v(0) = 0
+    }
+    M x[D];
+    int par = sraw & 1;
+    bool nan = false;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        par ^= (lr[q] < M(0)) ? 1 : 0;
+        nan |= (lr[q] != lr[q]);
+        x[q] = lr[q] - M(StoreT<S>::get(mr[q]));
+    }
+    if (c.t < c.T) {
+        auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
+        auto emit = [&](int q, M v) { at(c.msg, uint32_t((q0 + q) * c.Z + k)) = StoreT<S>::put(v); };
+        check_rule<M, ALGO, D>(x, D, sraw & 1, M(c.clamp), weight, emit);
+    }
+    return par | (nan ? 1 : 0);
 }
 
-// Returns v unchanged through an empty asm statement.  A conditionally loaded
-// value whose only use is a conversion would otherwise get that conversion
-// moved next to its load, and with it the wait for the load, which would
-// serialize the loads of a step.
-template <typename T>
-__device__ __forceinline__ T opaque(T v)
+// The same for any degree d <= MAXD (masked; entries may differ across lanes).
+template <typename M, typename S, int ALGO, int MAXD, bool WU>
+__device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, int d, int k, int sraw)
 {
-    asm volatile("" : "+v"(v));
-    return v;
+    int32_t e[MAXD];
+    M lr[MAXD];
+    S mr[MAXD];
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) e[q] = (q < d) ? c.s_row[q0 + q] : 0;
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) {
+        lr[q] = M(0);
+        mr[q] = S(0);
+        if (q < d) {
+            const int eq = uni<WU>(e[q]);
+            int uu = k + (eq & 0xffff);
+            uu = uu >= c.Z ? uu - c.Z : uu;
+            lr[q] = at(c.Lp, uint32_t(((eq >> 16) & 0x1ff) * c.Z + uu));
+            if (c.t > 0) mr[q] = at(c.msg, uint32_t((q0 + q) * c.Z + k));
+        }
+    }
+    M x[MAXD];
+    int par = sraw & 1;
+    bool nan = false;
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) {
+        x[q] = M(0);
+        if (q < d) {
+            par ^= (lr[q] < M(0)) ? 1 : 0;
+            nan |= (lr[q] != lr[q]);
+            x[q] = lr[q] - M(StoreT<S>::get(opaque(mr[q])));
+        }
+    }
+    if (c.t < c.T) {
+        auto weight = [&](int q) -> M {
+            return c.weighted ? M(c.s_w[uni<WU>((e[q] >> 25) & 0xf)]) : M(c.alpha);
+        };
+        auto emit = [&](int q, M v) { at(c.msg, uint32_t((q0 + q) * c.Z + k)) = StoreT<S>::put(v); };
+        check_rule<M, ALGO, MAXD>(x, d, sraw & 1, M(c.clamp), weight, emit);
+    }
+    return par | (nan ? 1 : 0);
 }
 
-// One frame, all iterations.  Each pass is written in three phases per step:
-// protograph entries from LDS, then every global load of the step with no use
-// in between (so a wavefront has all of them in flight at once), then the
-// arithmetic.  The per-iteration min-sum weights are staged in LDS.
-template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS, bool WU>
-__device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsCode& sc, int32_t (&s_unsat)[2],
+// Lch + the D messages of variable u of the block column whose table entries
+// start at qa, summed in table order (block rows ascending); D wave-uniform.
+template <typename M, typename S, int D, bool WU>
+__device__ __forceinline__ M var_sum(const FrameCtx<M, S>& c, int qa, int u, M acc)
+{
+    int32_t e[D];
+    S m[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) e[q] = uni<WU>(c.s_col[qa + q]);
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        int k = u - (e[q] & 0xffff);
+        k = k < 0 ? k + c.Z : k;
+        m[q] = at(c.msg, uint32_t((e[q] >> 16) * c.Z + k));
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) acc += M(StoreT<S>::get(m[q]));
+    return acc;
+}
+
+// The same for any degree (8 loads at a time, masked).
+template <typename M, typename S, bool WU>
+__device__ __forceinline__ M var_sum_any(const FrameCtx<M, S>& c, int qa, int dv, int u, M acc)
+{
+    for (int q8 = 0; q8 < dv; q8 += 8) {
+        int32_t e[8];
+        S m[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = (q8 + q < dv) ? c.s_col[qa + q8 + q] : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            m[q] = S(0);
+            if (q8 + q < dv) {
+                const int eq = uni<WU>(e[q]);
+                int k = u - (eq & 0xffff);
+                k = k < 0 ? k + c.Z : k;
+                m[q] = at(c.msg, uint32_t((eq >> 16) * c.Z + k));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q8 + q < dv) acc += M(StoreT<S>::get(opaque(m[q])));
+    }
+    return acc;
+}
+
+// One frame, all iterations.  With WU every wavefront's rows (variables) share
+// one block row (column), so the degree is wave-uniform and each step runs
+// the straight-line body of its exact degree (1..8); larger degrees and
+// codes with Z % 64 != 0 take the masked bodies.  The per-iteration min-sum
+// weights are staged in LDS.
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU>
+__device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm, int32_t* dsm, int32_t (&s_unsat)[2],
                                              float (&s_w)[kMaxTypes], int f, const DevFrame& fr, const DevCode& cd)
 {
     const int tid = int(threadIdx.x);
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
-    M* Lp = static_cast<M*>(a.post) + fr.vn_off;
-    const M* Lc = static_cast<const M*>(a.llr) + fr.vn_off;
-    S* msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    const int32_t* s_rptr = dsm + lm.rptr;
+    const int32_t* s_cptr = dsm + lm.cptr;
+    FrameCtx<M, S> c;
+    c.Lp = static_cast<M*>(a.post) + fr.vn_off;
+    c.Lc = static_cast<const M*>(a.llr) + fr.vn_off;
+    c.msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    c.s_row = dsm + lm.row;
+    c.s_col = dsm + lm.col;
+    c.s_w = s_w;
+    c.Z = Z;
+    c.T = a.T;
+    c.weighted = a.weights != nullptr;
+    c.alpha = a.alpha;
+    c.clamp = a.clamp;
     const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
     M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
     for (int v = tid; v < n; v += NT) {
-        const M l = at(Lc, v);
-        at(Lp, v) = l;
+        const M l = at(c.Lc, v);
+        at(c.Lp, v) = l;
         if (tr) tr[v] = l;
     }
     if (tid == 0) {
@@ -414,74 +633,38 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsCode& sc
     if (a.weights && a.T > 0 && tid < a.n_types) s_w[tid] = a.weights[tid];
     __syncthreads();
     for (int t = 0;; ++t) {
+        c.t = t;
         if (a.ckpt && t < a.T && t % a.ckpt_every == 0) {
             // checkpoint c2v(t) (all zero at t = 0) before the check pass overwrites it
             float* ck = a.ckpt + int64_t(t / a.ckpt_every) * a.ckpt_stride + fr.msg_off;
             const int ef = cd.NB * Z;
-            for (int e = tid; e < ef; e += NT) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(msg[e]));
+            for (int e = tid; e < ef; e += NT) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(c.msg[e]));
             __syncthreads();
         }
-        // check pass: syndrome test of Lpost(t) and c2v(t+1); ROWS rows per
-        // thread per step
+        // check pass: syndrome test of Lpost(t) and c2v(t+1)
         int bad = 0;
-        for (int r0 = tid; r0 < m; r0 += ROWS * NT) {
-            int q0[ROWS], d[ROWS], kk[ROWS], sraw[ROWS];
-            int2 ent[ROWS][MAXD];
-            M lr[ROWS][MAXD];
-            S mr[ROWS][MAXD];
-#pragma unroll
-            for (int h = 0; h < ROWS; ++h) {
-                const int r = r0 + h * NT;
-                const bool live = r < m;
-                const int rr = live ? r : r0;
-                const int i = uni<WU>(zsh >= 0 ? (rr >> zsh) : rr / Z);
-                kk[h] = rr - i * Z;
-                q0[h] = uni<WU>(sc.rptr[i]);
-                d[h] = live ? uni<WU>(sc.rptr[i + 1]) - q0[h] : 0;
-                sraw[h] = (syn && live) ? int(at(syn, rr)) : 0;
-#pragma unroll
-                for (int q = 0; q < MAXD; ++q) ent[h][q] = (q < d[h]) ? sc.row[q0[h] + q] : make_int2(0, 0);
-            }
-#pragma unroll
-            for (int h = 0; h < ROWS; ++h) {
-#pragma unroll
-                for (int q = 0; q < MAXD; ++q) {
-                    lr[h][q] = M(0);
-                    mr[h][q] = S(0);
-                    if (q < d[h]) {
-                        const int shift = uni<WU>(ent[h][q].x);
-                        const int col = uni<WU>(ent[h][q].y & 0xfffff);
-                        int uu = kk[h] + shift;
-                        uu = uu >= Z ? uu - Z : uu;
-                        lr[h][q] = at(Lp, uint32_t(col * Z + uu));
-                        if (t > 0) mr[h][q] = at(msg, uint32_t((q0[h] + q) * Z + kk[h]));
-                    }
+        for (int r = tid; r < m; r += NT) {
+            const int i = uni<WU>(zsh >= 0 ? (r >> zsh) : r / Z);
+            const int k = r - i * Z;
+            const int q0 = uni<WU>(s_rptr[i]);
+            const int d = uni<WU>(s_rptr[i + 1]) - q0;
+            const int sraw = syn ? int(at(syn, r)) : 0;
+            if constexpr (WU) {
+                switch (d) {
+                case 1: bad += check_row<M, S, ALGO, 1, WU>(c, q0, k, sraw); break;
+                case 2: bad += check_row<M, S, ALGO, 2, WU>(c, q0, k, sraw); break;
+                case 3: bad += check_row<M, S, ALGO, 3, WU>(c, q0, k, sraw); break;
+                case 4: bad += check_row<M, S, ALGO, 4, WU>(c, q0, k, sraw); break;
+                case 5: bad += check_row<M, S, ALGO, 5, WU>(c, q0, k, sraw); break;
+                case 6: bad += check_row<M, S, ALGO, 6, WU>(c, q0, k, sraw); break;
+                case 7: bad += check_row<M, S, ALGO, 7, WU>(c, q0, k, sraw); break;
+                case 8: bad += check_row<M, S, ALGO, 8, WU>(c, q0, k, sraw); break;
+                default:
+                    if constexpr (MAXD > 8) bad += check_row_any<M, S, ALGO, MAXD, WU>(c, q0, d, k, sraw);
+                    break;
                 }
-            }
-#pragma unroll
-            for (int h = 0; h < ROWS; ++h) {
-                if (d[h] == 0) continue;
-                M x[MAXD];
-                int par = sraw[h] & 1;
-                bool nan = false;
-#pragma unroll
-                for (int q = 0; q < MAXD; ++q) {
-                    x[q] = M(0);
-                    if (q < d[h]) {
-                        const M lp = lr[h][q];
-                        par ^= (lp < M(0)) ? 1 : 0;
-                        nan |= (lp != lp);
-                        x[q] = (t == 0) ? lp : lp - M(StoreT<S>::get(opaque(mr[h][q])));
-                    }
-                }
-                bad += par | (nan ? 1 : 0);
-                if (t < a.T) {
-                    const int qb = q0[h], kh = kk[h];
-                    const int2(&eh)[MAXD] = ent[h];
-                    auto weight = [&](int q) -> M { return a.weights ? M(s_w[uni<WU>(eh[q].y >> 20)]) : M(a.alpha); };
-                    auto emit = [&](int q, M v) { at(msg, uint32_t((qb + q) * Z + kh)) = StoreT<S>::put(v); };
-                    check_rule<M, ALGO, MAXD>(x, d[h], sraw[h] & 1, M(a.clamp), weight, emit);
-                }
+            } else {
+                bad += check_row_any<M, S, ALGO, MAXD, WU>(c, q0, d, k, sraw);
             }
         }
         if (bad) atomicAdd(&s_unsat[t & 1], bad);
@@ -498,46 +681,62 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsCode& sc
         // the next iteration's weights: every read of s_w for iteration t
         // happened before the barrier above
         if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
-        // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows
-        // ascending; the messages are loaded 8 at a time, then summed in order
+        // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows ascending
         for (int v = tid; v < n; v += NT) {
             const int j = uni<WU>(zsh >= 0 ? (v >> zsh) : v / Z);
             const int uu = v - j * Z;
-            const int qa = uni<WU>(sc.cptr[j]);
-            const int dv = uni<WU>(sc.cptr[j + 1]) - qa;
-            M acc = at(Lc, v);
-            for (int q8 = 0; q8 < dv; q8 += 8) {
-                int2 e[8];
-                S c[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) e[q] = (q8 + q < dv) ? sc.col[qa + q8 + q] : make_int2(0, 0);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    c[q] = S(0);
-                    if (q8 + q < dv) {
-                        const int shift = uni<WU>(e[q].x);
-                        const int blk = uni<WU>(e[q].y);
-                        int k = uu - shift;
-                        k = k < 0 ? k + Z : k;
-                        c[q] = at(msg, uint32_t(blk * Z + k));
-                    }
+            const int qa = uni<WU>(s_cptr[j]);
+            const int dv = uni<WU>(s_cptr[j + 1]) - qa;
+            M acc = at(c.Lc, v);
+            if constexpr (WU) {
+                switch (dv) {
+                case 1: acc = var_sum<M, S, 1, WU>(c, qa, uu, acc); break;
+                case 2: acc = var_sum<M, S, 2, WU>(c, qa, uu, acc); break;
+                case 3: acc = var_sum<M, S, 3, WU>(c, qa, uu, acc); break;
+                case 4: acc = var_sum<M, S, 4, WU>(c, qa, uu, acc); break;
+                case 5: acc = var_sum<M, S, 5, WU>(c, qa, uu, acc); break;
+                case 6: acc = var_sum<M, S, 6, WU>(c, qa, uu, acc); break;
+                case 7: acc = var_sum<M, S, 7, WU>(c, qa, uu, acc); break;
+                case 8: acc = var_sum<M, S, 8, WU>(c, qa, uu, acc); break;
+                default: acc = var_sum_any<M, S, WU>(c, qa, dv, uu, acc); break;
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q8 + q < dv) acc += M(StoreT<S>::get(opaque(c[q])));
+            } else {
+                acc = var_sum_any<M, S, WU>(c, qa, dv, uu, acc);
             }
-            at(Lp, v) = acc;
+            at(c.Lp, v) = acc;
             if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
         }
         __syncthreads();
     }
-    for (int v = tid; v < n; v += NT) a.bits[fr.vn_off + v] = at(Lp, v) < M(0) ? 1 : 0;
+    for (int v = tid; v < n; v += NT) a.bits[fr.vn_off + v] = at(c.Lp, v) < M(0) ? 1 : 0;
 }
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS, bool WU, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, int32_t* queue, int32_t F, const int32_t* order)
+// Loads the LDS tables of code cd (see LdsMap); every thread of the workgroup
+// calls it, and it ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void load_code_tables(const LdsMap& lm, int32_t* dsm, const DevCode& cd)
 {
-    __shared__ LdsCode sc;
+    const int tid = int(threadIdx.x);
+    int32_t* s_rptr = dsm + lm.rptr;
+    int32_t* s_cptr = dsm + lm.cptr;
+    int32_t* s_row = dsm + lm.row;
+    int32_t* s_col = dsm + lm.col;
+    for (int q = tid; q <= cd.mb; q += NT) s_rptr[q] = cd.qrow_ptr[q];
+    for (int q = tid; q <= cd.nb; q += NT) s_cptr[q] = cd.qcol_ptr[q];
+    for (int q = tid; q < cd.NB; q += NT) {
+        const QcBlock br = cd.qrow[q];
+        s_row[q] = br.shift | (br.other << 16) | (br.type << 25);
+        const QcBlock bc = cd.qcol[q];
+        s_col[q] = bc.shift | (bc.blk << 16);
+    }
+    __syncthreads();
+}
+
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, int32_t* queue, int32_t F,
+                                                        const int32_t* order)
+{
+    extern __shared__ __align__(16) int32_t dsm[];
     __shared__ int32_t s_frame;
     __shared__ int32_t s_unsat[2];
     __shared__ float s_w[kMaxTypes];
@@ -554,17 +753,10 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, int32_t* queu
         const DevFrame fr = a.frames[f];
         const DevCode& cd = a.codes[fr.code];
         if (fr.code != cur) {
-            for (int q = tid; q <= cd.mb; q += NT) sc.rptr[q] = cd.qrow_ptr[q];
-            for (int q = tid; q <= cd.nb; q += NT) sc.cptr[q] = cd.qcol_ptr[q];
-            for (int q = tid; q < cd.NB; q += NT) {
-                const QcBlock br = cd.qrow[q];
-                sc.row[q] = make_int2(br.shift, br.other | (br.type << 20));
-                const QcBlock bc = cd.qcol[q];
-                sc.col[q] = make_int2(bc.shift, bc.blk);
-            }
+            load_code_tables<NT>(lm, dsm, cd);
             cur = fr.code;
         }
-        decode_frame<M, S, ALGO, MAXD, NT, ROWS, WU>(a, sc, s_unsat, s_w, f, fr, cd);
+        decode_frame<M, S, ALGO, MAXD, NT, WU>(a, lm, dsm, s_unsat, s_w, f, fr, cd);
     }
 }
 
@@ -669,22 +861,28 @@ static inline int device_cus()
     return cus;
 }
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, int ROWS, bool WU, int MINW>
+static inline LdsMap lds_map(const cvr_batch_s* b)
+{
+    LdsMap lm{};
+    lm.rptr = 0;
+    lm.cptr = lm.rptr + b->max_mb + 1;
+    lm.row = lm.cptr + b->max_nb + 1;
+    lm.col = lm.row + b->max_NB;
+    lm.words = lm.col + b->max_NB;
+    return lm;
+}
+
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
 static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s)
 {
-    static int per_cu = 0;      // resident workgroups per CU of this instantiation
-    if (per_cu == 0) {
-        int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_frames_qc<M, S, ALGO, MAXD, NT, ROWS, WU, MINW>, NT, 0) !=
-                hipSuccess ||
-            v < 1)
-            v = 1;
-        per_cu = v;
-    }
+    auto kern = k_frames_qc<M, S, ALGO, MAXD, NT, WU, MINW>;
+    const LdsMap lm = lds_map(b);
+    const size_t dyn = size_t(lm.words) * 4;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, dyn) != hipSuccess || per_cu < 1) per_cu = 1;
     const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
     ProfScope prof(CVR_PROF_FRAMES, s);
-    hipLaunchKernelGGL((k_frames_qc<M, S, ALGO, MAXD, NT, ROWS, WU, MINW>), dim3(grid), dim3(NT), 0, s, a, queue, b->F,
-                       b->d_order);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), dyn, s, a, lm, queue, b->F, b->d_order);
     return check_launch("decode (persistent)");
 }
 
@@ -698,40 +896,33 @@ static inline bool wave_uniform(const cvr_batch_s* b)
 }
 
 template <typename M, typename S, int ALGO, int MAXD>
-static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int wg, int rows,
-                             int minw)
+static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, const LaunchShape& sh)
 {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, queue, int64_t(1));
     if (cvr_status st = check_launch("decode queue reset")) return st;
-    if (!wave_uniform(b)) return launch_frames<M, S, ALGO, MAXD, 512, 1, false, 1>(b, a, queue, s);
-    if constexpr (MAXD > 8) {
-        // rows of more than 8 edges need more registers than the wide shapes
-        // leave (they would spill): 256 or 512 threads, one row per step
-        if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 1, true, 1>(b, a, queue, s);
-        return launch_frames<M, S, ALGO, MAXD, 512, 1, true, 1>(b, a, queue, s);
+    if (!wave_uniform(b)) return launch_frames<M, S, ALGO, MAXD, 512, false, 1>(b, a, queue, s);
+    if constexpr (MAXD > 8 || sizeof(M) == 8) {
+        // binary64, and rows of more than 8 edges, need more registers than
+        // the other shapes leave: 512 threads only
+        return launch_frames<M, S, ALGO, MAXD, 512, true, 1>(b, a, queue, s);
+    } else {
+        if (sh.min_waves == 8) {
+            if (sh.wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, true, 8>(b, a, queue, s);
+            return launch_frames<M, S, ALGO, MAXD, 512, true, 8>(b, a, queue, s);
+        }
+        if (sh.wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, true, 1>(b, a, queue, s);
+        return launch_frames<M, S, ALGO, MAXD, 512, true, 1>(b, a, queue, s);
     }
-    if (minw == 8) {
-        if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 1, true, 8>(b, a, queue, s);
-        return launch_frames<M, S, ALGO, MAXD, 512, 1, true, 8>(b, a, queue, s);
-    }
-    if (rows == 2) {
-        if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 2, true, 1>(b, a, queue, s);
-        if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 2, true, 1>(b, a, queue, s);
-        return launch_frames<M, S, ALGO, MAXD, 512, 2, true, 1>(b, a, queue, s);
-    }
-    if (wg == 256) return launch_frames<M, S, ALGO, MAXD, 256, 1, true, 1>(b, a, queue, s);
-    if (wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, 1, true, 1>(b, a, queue, s);
-    return launch_frames<M, S, ALGO, MAXD, 512, 1, true, 1>(b, a, queue, s);
 }
 
 template <typename M, typename S, int ALGO>
 static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue,
-                               int wg, int rows, int minw)
+                               const LaunchShape& sh)
 {
     if (frames) {
-        if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, wg, rows, minw);
-        if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, wg, rows, minw);
-        return run_frames<M, S, ALGO, 32>(b, a, queue, s, wg, rows, minw);
+        if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, sh);
+        if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, sh);
+        return run_frames<M, S, ALGO, 32>(b, a, queue, s, sh);
     }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
@@ -773,7 +964,7 @@ static inline bool frames_fit(const cvr_batch_s* b)
 {
     if (!b->all_qc) return false;
     for (const cvr_code_t c : b->codes)
-        if (c->dev.NB > kMaxLdsBlocks || c->dev.mb > kMaxLdsDim || c->dev.nb > kMaxLdsDim || c->dev.Z >= (1 << 20))
+        if (c->dev.NB > kMaxLdsBlocks || c->dev.mb > kMaxLdsDim || c->dev.nb > kMaxLdsDim || c->dev.Z > kMaxLdsZ)
             return false;
     return true;
 }
@@ -782,7 +973,7 @@ static inline bool frames_fit(const cvr_batch_s* b)
 // One instantiation per (math, store, rule); each lives in its own translation unit.
 #define CVR_DECL_DISPATCH(NAME)                                                                      \
     cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue, \
-                    int wg, int rows, int minw)
+                    const LaunchShape& sh)
 CVR_DECL_DISPATCH(decode_f64_sp);
 CVR_DECL_DISPATCH(decode_f64_nms);
 CVR_DECL_DISPATCH(decode_f32_sp);

@@ -111,6 +111,7 @@ struct cvr_batch_s {
     int64_t total_n = 0, total_m = 0, total_E = 0;
     int32_t max_row_deg = 0;
     int32_t max_types = 1;
+    int32_t max_mb = 0, max_nb = 0, max_NB = 0;   // largest QC protograph dimensions of the batch
     bool all_qc = false;
     std::vector<cvr_code_t> codes;
     std::vector<cvr::DevFrame> frames_host;

@@ -47,6 +47,14 @@ struct GradArgs {
     int32_t T, K, n_types, F;
 };
 
+// protograph tables of the current code, in LDS
+struct LdsCode {
+    int32_t rptr[kMaxLdsDim + 1];
+    int32_t cptr[kMaxLdsDim + 1];
+    int2 row[kMaxLdsBlocks];   // x = shift, y = block column | type << 20 (block id = position)
+    int2 col[kMaxLdsBlocks];   // x = shift, y = block id
+};
+
 template <int MAXD>
 __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
 {
@@ -389,7 +397,7 @@ extern "C" cvr_status nms_unrolled_fwd(cvr_batch_t batch, int32_t T, int32_t ckp
     a.ckpt = ckpt;
     a.ckpt_stride = batch->total_E;
     a.ckpt_every = ckpt_every;
-    return decode_f32_nms(batch, a, hipStream_t(stream), true, true, reinterpret_cast<int32_t*>(dws + w.queue), 0, 0, 0);
+    return decode_f32_nms(batch, a, hipStream_t(stream), true, true, reinterpret_cast<int32_t*>(dws + w.queue), LaunchShape{0, 0});
 }
 
 extern "C" cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckpt_every, const float* weights,

@@ -1,25 +1,27 @@
 """Autotuner of the persistent decoder's launch shape.
 
-Times ``ldpc_decode_batch`` for every (workgroup size, check rows per step)
-candidate on the caller's own batch and inputs with HIP events on the launch
-stream (the library's launch timing) and returns the fastest.  The knobs
-change the launch configuration only, never the results.
+Times ``ldpc_decode_batch`` for every (workgroup size, minimum waves per
+SIMD) candidate on the caller's own batch and inputs with HIP events on the launch stream (the library's launch
+timing) and returns the fastest.  The knobs change the launch configuration
+only, never the results.
 """
 from __future__ import annotations
 
 from . import api
 
-CANDIDATES = [(512, 1, 0), (1024, 1, 0), (256, 1, 0), (512, 2, 0), (1024, 2, 0), (512, 1, 8), (1024, 1, 8)]
+CANDIDATES = [(512, 0), (1024, 0), (512, 8), (1024, 8)]
+KNOBS = ("wg_threads", "min_waves")
 
 
 def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, candidates=CANDIDATES):
-    """Returns ((wg_threads, rows_per_step, min_waves), {candidate: ms per decode})."""
+    """Returns (best candidate as a tuple in KNOBS order, {candidate: ms per decode})."""
     import torch
     timings = {}
-    saved = (params.wg_threads, params.rows_per_step, params.min_waves)
+    saved = tuple(getattr(params, k) for k in KNOBS)
     try:
-        for wg, rows, mw in candidates:
-            params.wg_threads, params.rows_per_step, params.min_waves = wg, rows, mw
+        for cand in candidates:
+            for k, v in zip(KNOBS, cand):
+                setattr(params, k, v)
             api.ldpc_decode_batch(batch, params, llr, syndrome, workspace=workspace, out=out)   # warm
             torch.cuda.synchronize()
             api.profile_enable(True)
@@ -29,9 +31,10 @@ def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, 
             torch.cuda.synchronize()
             api.profile_enable(False)
             ms, cnt = api.profile_read(api.PROF_FRAMES, reset=True)
-            timings[(wg, rows, mw)] = ms / max(cnt, 1)
+            timings[tuple(cand)] = ms / max(cnt, 1)
     finally:
-        params.wg_threads, params.rows_per_step, params.min_waves = saved
+        for k, v in zip(KNOBS, saved):
+            setattr(params, k, v)
         api.profile_enable(False)
     best = min(timings, key=timings.get)
     return best, timings

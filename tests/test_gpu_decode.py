@@ -90,9 +90,14 @@ def test_slice_stage_sp_fp32_qc(j):
     print(f"[decode slice{j} SP f32 qc]", flush=True)
     n, F = 65536, 16
     qc, csr, L, syn, truth = _slice_stage(j, n, F, seed=12345)
-    p = api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32)
+    p = api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32, schedule=api.SCHED_PERSISTENT)
     code = api.Code.from_qc(qc)
     res = _decode_gpu(code, F, L, syn, p, trace=True)
+    # 16 frames: the default schedule runs the per-pass kernels; bit-identical
+    res_auto = _decode_gpu(code, F, L, syn, api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32),
+                           trace=True)
+    for k in ("bits", "post", "iters", "ok", "trace"):
+        np.testing.assert_array_equal(res[k], res_auto[k])
     Ft = 4
     ref = oracle.decode(csr, L[:Ft], syn[:Ft], algo=oracle.SP, max_iter=100, trace=True)
     sub = {k: (v.reshape(F, -1)[:Ft] if k in ("bits",) else v[:Ft]) for k, v in res.items() if v is not None and k != "post"}
@@ -116,16 +121,13 @@ def test_layouts_and_schedules_are_bit_identical():
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8),
                  dict(algo=api.NMS, store=api.F32, alpha=0.7)):
         runs = []
-        for code, sched, wg, rows, mw in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, 0),
-                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 256, 2, 0),
-                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 1, 0),
-                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 2, 0),
-                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 1, 8),
-                                          (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 1, 8),
-                                          (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0, 0),
-                                          (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0)):
-            p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, rows_per_step=rows,
-                           min_waves=mw, **base)
+        for code, sched, wg, mw in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0),
+                                    (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 0),
+                                    (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 8),
+                                    (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8),
+                                    (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0),
+                                    (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0)):
+            p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, min_waves=mw, **base)
             runs.append(_decode_gpu(code, F, L, syn, p, trace=True))
         for r in runs[1:]:
             for k in ("bits", "post", "iters", "ok", "trace"):
@@ -139,12 +141,13 @@ def test_persistent_schedule_rejects_explicit_codes():
         _decode_gpu(api.Code.from_csr(csr), 2, np.zeros((2, 1024)), None, p)
 
 
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES])
 @pytest.mark.parametrize("store", [api.F32, api.F16])
-def test_nms_bit_exact_against_binary32_oracle(store):
+def test_nms_bit_exact_against_binary32_oracle(store, sched):
     """Min-sum uses only +, -, x, min and the binary16 rounding: with the oracle
     taking every step in binary32 (the kernel's precision) the two agree bit for
     bit at every iteration."""
-    print(f"[decode NMS store={store}]", flush=True)
+    print(f"[decode NMS store={store} schedule={sched}]", flush=True)
     qc = inputs.lambda_half_rate_spec(16384)
     csr = qc.to_csr()
     F = 8
@@ -152,7 +155,7 @@ def test_nms_bit_exact_against_binary32_oracle(store):
     s2 = inputs.sigma2_from_ebn0(np.linspace(1.5, 3.0, F), 0.5)
     llr = inputs.bpsk_llr(bits, s2, seed=6)
     syn, _ = oracle.syndrome(csr, bits)
-    p = api.Params(algo=api.NMS, max_iter=30, math=api.F32, store=store, alpha=0.8)
+    p = api.Params(algo=api.NMS, max_iter=30, math=api.F32, store=store, alpha=0.8, schedule=sched)
     res = _decode_gpu(api.Code.from_qc(qc), F, llr, syn, p, trace=True)
     ref = oracle.decode(csr, llr, syn, algo=oracle.NMS, alpha=float(np.float32(0.8)), max_iter=30, trace=True,
                         store_half=(store == api.F16), prec32=True)
@@ -185,11 +188,18 @@ def test_nms_uniform_weights_equal_alpha():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_ragged_batch_mixed_codes_and_gaps():
+@pytest.mark.parametrize("sizes,sched", [
+    ((4096, 8192, 4096), api.SCHED_PERSISTENT),        # Z = 32 / 64: lane-varying block rows
+    ((8192, 16384, 8192), api.SCHED_PERSISTENT),       # Z % 64 == 0: wave-uniform kernel
+    ((4096, 8192, 4096), api.SCHED_PASSES),
+])
+def test_ragged_batch_mixed_codes_and_gaps(sizes, sched):
     """Frames of different codes and lengths at scattered offsets: each frame
-    decodes exactly as it does alone."""
-    print("[decode ragged]", flush=True)
-    specs = [inputs.slice_code_spec(3, 4096), inputs.slice_code_spec(2, 8192), inputs.lambda_half_rate_spec(4096)]
+    decodes exactly as it does alone (the persistent decoder reloads its LDS
+    tables at every change of code)."""
+    print(f"[decode ragged sizes={sizes} schedule={sched}]", flush=True)
+    specs = [inputs.slice_code_spec(3, sizes[0]), inputs.slice_code_spec(2, sizes[1]),
+             inputs.lambda_half_rate_spec(sizes[2])]
     codes = [api.Code.from_qc(q) for q in specs]
     order = [0, 2, 1, 0, 1, 2, 2]
     frames, vo, co = [], 17, 5
@@ -210,19 +220,21 @@ def test_ragged_batch_mixed_codes_and_gaps():
         S[c0:c0 + len(s)] = s
     batch = api.Batch(codes, frames)
     assert batch.total_n <= total_n and batch.F == len(order)
-    p = api.Params(algo=api.SP, max_iter=30, math=api.F32, store=api.F32)
+    p = api.Params(algo=api.SP, max_iter=30, math=api.F32, store=api.F32, schedule=sched)
     out = api.ldpc_decode_batch(batch, p, _g(L), _g(S))
     torch.cuda.synchronize()
+    solo_p = api.Params(algo=api.SP, max_iter=30, math=api.F32, store=api.F32, schedule=api.SCHED_PASSES)
     for i, (c, v0, c0) in enumerate(frames):
-        solo = _decode_gpu(codes[c], 1, llrs[i][None, :], syns[i][None, :], p)
+        solo = _decode_gpu(codes[c], 1, llrs[i][None, :], syns[i][None, :], solo_p)
         n = specs[c].n
         np.testing.assert_array_equal(out["bits"][v0:v0 + n].cpu().numpy(), solo["bits"])
         np.testing.assert_array_equal(out["post"][v0:v0 + n].cpu().numpy(), solo["post"])
         assert int(out["iters"][i]) == int(solo["iters"][0])
 
 
-def test_failure_injection_and_edge_cases():
-    print("[decode edge cases]", flush=True)
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES])
+def test_failure_injection_and_edge_cases(sched):
+    print(f"[decode edge cases schedule={sched}]", flush=True)
     qc = inputs.lambda_half_rate_spec(4096)
     csr = qc.to_csr()
     code = api.Code.from_qc(qc)
@@ -235,7 +247,7 @@ def test_failure_injection_and_edge_cases():
     llr[3] = (1 - 2 * bits[3].astype(np.float32)) * 30.0      # clean frame: stops at t = 0
     syn_bad = syn.copy()
     syn_bad[4, 11] ^= 1                                       # corrupted syndrome bit
-    p = api.Params(algo=api.SP, max_iter=25, math=api.F32, store=api.F32)
+    p = api.Params(algo=api.SP, max_iter=25, math=api.F32, store=api.F32, schedule=sched)
     res = _decode_gpu(code, F, llr, syn_bad, p)
     assert res["ok"][0] == 1
     assert res["ok"][1] == 0 and res["iters"][1] == 25
@@ -246,11 +258,11 @@ def test_failure_injection_and_edge_cases():
     solo = _decode_gpu(code, 1, llr[:1], syn[:1], p)
     np.testing.assert_array_equal(solo["bits"], res["bits"].reshape(F, -1)[0])
     # max_iter = 0: channel decisions, ok iff already a coset member
-    p0 = api.Params(algo=api.SP, max_iter=0, math=api.F32, store=api.F32)
+    p0 = api.Params(algo=api.SP, max_iter=0, math=api.F32, store=api.F32, schedule=sched)
     r0 = _decode_gpu(code, F, llr, syn_bad, p0)
     assert (r0["iters"] == 0).all() and r0["ok"][3] == 1 and r0["ok"][0] == 0
     # no early stop: every frame runs max_iter iterations
-    pn = api.Params(algo=api.SP, max_iter=12, math=api.F32, store=api.F32, early_stop=False)
+    pn = api.Params(algo=api.SP, max_iter=12, math=api.F32, store=api.F32, early_stop=False, schedule=sched)
     rn = _decode_gpu(code, F, llr, syn_bad, pn)
     assert (rn["iters"] == 12).all()
     # empty batch is a no-op
@@ -268,14 +280,16 @@ def test_repeat_runs_are_bit_identical():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_graph_capture_replays_match_eager():
-    """The decode (queue reset + persistent kernel, no memset) captured in a HIP
-    graph: every replay, with unrelated eager work in between, equals eager."""
-    print("[decode graph]", flush=True)
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES])
+def test_graph_capture_replays_match_eager(sched):
+    """The decode (queue reset + persistent kernel, or the per-pass launches;
+    no memset) captured in a HIP graph: every replay, with unrelated eager work
+    in between, equals eager."""
+    print(f"[decode graph schedule={sched}]", flush=True)
     qc, csr, L, syn, _ = _slice_stage(2, 16384, 8, seed=21)
     code = api.Code.from_qc(qc)
     batch = api.Batch.uniform(code, 8)
-    p = api.Params(algo=api.NMS, max_iter=60, math=api.F32, store=api.F16, alpha=0.75)
+    p = api.Params(algo=api.NMS, max_iter=60, math=api.F32, store=api.F16, alpha=0.75, schedule=sched)
     llr = _g(L.reshape(-1).astype(np.float32))
     sg = _g(syn.reshape(-1))
     ref = api.ldpc_decode_batch(batch, p, llr, sg)
@@ -324,7 +338,8 @@ def test_ragged_low_rate_met_batch_sampled_against_oracle():
     for (c, v0, c0) in frames:
         syn[c0:c0 + qcs[c].m] = oracle.syndrome(qcs[c].to_csr(), bits[v0:v0 + sizes[c]][None, :])[0][0]
     batch = api.Batch(codes, frames)
-    p = api.Params(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75)
+    p = api.Params(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75,
+                   schedule=api.SCHED_PERSISTENT)
     out = api.ldpc_decode_batch(batch, p, _g(llr), _g(syn))
     torch.cuda.synchronize()
     picks = [int(np.nonzero(order == c)[0][0]) for c in range(3)] + [len(frames) - 1]
