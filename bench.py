@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent"])
     ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
     ap.add_argument("--min-waves", dest="min_waves", type=int, default=0, help="0 or 8 resident waves per SIMD")
+    ap.add_argument("--lds-cache", dest="lds_cache_kb", type=int, default=0,
+                    help="LDS posterior cache KiB of the persistent decoder (0 = auto, -1 = none)")
     ap.add_argument("--cpu-frames", type=int, default=16, help="sub-blocks per stage in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2108)
@@ -155,7 +157,7 @@ def main():
             for dec, wts in (("sp", ""), ("nms", args.weights or "learned")):
                 a = copy.copy(args)
                 a.workload, a.decoder, a.weights, a.no_cpu_baseline = name, dec, wts, True
-                a.wg = a.min_waves = 0
+                a.wg = a.min_waves = a.lds_cache_kb = 0
                 res = recon(a, WORKLOADS[name], dev)
                 print(json.dumps(res), flush=True)
         return
@@ -189,7 +191,8 @@ def recon(args, wl, dev):
     store = api.F32 if args.decoder == "sp" else api.F16
     sched = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT}[args.schedule]
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        schedule=sched, wg_threads=args.wg, min_waves=args.min_waves)
+                        schedule=sched, wg_threads=args.wg, min_waves=args.min_waves,
+                        lds_cache_kb=args.lds_cache_kb)
     stage_params = {2: params, 3: params}
     if args.weights:
         if algo != api.NMS:
@@ -232,9 +235,9 @@ def recon(args, wl, dev):
         from paper_2108_08418_amd.tune import tune_decode
         best, tim = tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2])
         for pp in {id(v): v for v in (params, *stage_params.values())}.values():
-            pp.wg_threads, pp.min_waves = best
-        args.wg, args.min_waves = best
-        tuned = {f"{k[0]}w{k[1]}": round(v, 3) for k, v in tim.items()}
+            pp.wg_threads, pp.min_waves, pp.lds_cache_kb = best
+        args.wg, args.min_waves, args.lds_cache_kb = best
+        tuned = {f"{k[0]}w{k[1]}c{k[2]}": round(v, 3) for k, v in tim.items()}
         print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -280,7 +283,7 @@ def recon(args, wl, dev):
         wg = args.wg or 512
         mt = "float, float" if store == api.F32 else "float, __half"
         inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
-                f"{8 if args.min_waves == 8 else 1}>")
+                f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
         roof_kernel = inst
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
@@ -311,7 +314,7 @@ def recon(args, wl, dev):
             "decoder": ("sum-product" if algo == api.SP else
                         (f"learned normalized min-sum ({args.weights})" if args.weights else
                          f"normalized min-sum alpha={args.alpha}")),
-            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "min_waves": args.min_waves,
+            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "min_waves": args.min_waves, "lds_cache_kb": args.lds_cache_kb,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -385,7 +388,7 @@ def ragged(args, wl, dev):
     algo = api.SP if args.decoder == "sp" else api.NMS
     store = api.F32 if args.decoder == "sp" else api.F16
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        wg_threads=args.wg, min_waves=args.min_waves)
+                        wg_threads=args.wg, min_waves=args.min_waves, lds_cache_kb=args.lds_cache_kb)
     ws = api.alloc_workspace(batch, params, dev)
     out = dict(bits=torch.empty(total_n, dtype=torch.uint8, device=dev), post=None,
                iters=torch.empty(F, dtype=torch.int32, device=dev), ok=torch.empty(F, dtype=torch.uint8, device=dev))
@@ -399,9 +402,9 @@ def ragged(args, wl, dev):
     if not args.no_tune and args.wg == 0:
         from paper_2108_08418_amd.tune import tune_decode
         best, tim = tune_decode(batch, params, llr, syn, ws, out)
-        params.wg_threads, params.min_waves = best
-        args.wg, args.min_waves = best
-        tuned = {f"{k[0]}w{k[1]}": round(v, 3) for k, v in tim.items()}
+        params.wg_threads, params.min_waves, params.lds_cache_kb = best
+        args.wg, args.min_waves, args.lds_cache_kb = best
+        tuned = {f"{k[0]}w{k[1]}c{k[2]}": round(v, 3) for k, v in tim.items()}
         print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -442,7 +445,7 @@ def ragged(args, wl, dev):
     wg = args.wg or 512
     mt = "float, float" if store == api.F32 else "float, __half"
     inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
-            f"{8 if args.min_waves == 8 else 1}>")
+            f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
     traffic, traffic_src = recorded_traffic(inst)
     value = total_n / (t_total / args.steps)
     result = {
@@ -454,7 +457,7 @@ def ragged(args, wl, dev):
         "config": {"workload": args.workload, "frames": F, "total_bits": total_n,
                    "sizes": list(sizes), "counts": list(counts), "code_rate": 0.0625,
                    "decoder": ("sum-product" if algo == api.SP else f"normalized min-sum alpha={args.alpha}"),
-                   "max_iter": args.max_iter, "graph": bool(args.graph), "wg_threads": wg,
+                   "max_iter": args.max_iter, "graph": bool(args.graph), "wg_threads": wg, "lds_cache_kb": args.lds_cache_kb,
                    "min_waves": args.min_waves,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": inst, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

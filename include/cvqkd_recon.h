@@ -185,7 +185,11 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
  *            compiler choose.  Binary64 math and batches with a check row of
- *            more than 8 edges always run 512 threads.                        */
+ *            more than 8 edges always run 512 threads.
+ *  lds_cache_kb  posteriors of the highest-degree block columns that the
+ *            persistent decoder keeps in LDS (results unchanged): 0 = as much
+ *            as fits without fewer resident workgroups, -1 = none, > 0 = that
+ *            many KiB (capped by the LDS size).                               */
 enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2 };
 
 typedef struct {
@@ -199,6 +203,7 @@ typedef struct {
     int32_t schedule;
     int32_t wg_threads;
     int32_t min_waves;
+    int32_t lds_cache_kb;
     const float* weights;
     void* trace;
 } cvr_decode_params;

@@ -150,6 +150,7 @@ class Params:
     schedule: int = SCHED_AUTO
     wg_threads: int = 0
     min_waves: int = 0
+    lds_cache_kb: int = 0
 
     def c_struct(self, trace: torch.Tensor | None = None) -> DecodeParams:
         p = DecodeParams()
@@ -158,6 +159,7 @@ class Params:
         p.schedule = int(self.schedule)
         p.wg_threads = int(self.wg_threads)
         p.min_waves = int(self.min_waves)
+        p.lds_cache_kb = int(self.lds_cache_kb)
         if self.weights is not None:
             if self.weights.dtype != torch.float32:
                 raise ValueError("weights must be float32")

@@ -192,6 +192,11 @@ extern "C" cvr_status cvr_code_create_qc(int32_t nb, int32_t mb, int32_t Z, cons
                 qcol[fill[j]++] = QcBlock{i, shift[i * nb + j], b, block_type ? block_type[i * nb + j] : 0};
             }
     }
+    std::vector<int32_t> rank(static_cast<size_t>(nb));
+    for (int32_t j = 0; j < nb; ++j) rank[size_t(j)] = j;
+    std::stable_sort(rank.begin(), rank.end(), [&](int32_t x, int32_t y) {
+        return qcol_ptr[x + 1] - qcol_ptr[x] > qcol_ptr[y + 1] - qcol_ptr[y];
+    });
     // explicit CSR expansion (the generic kernels and syndrome checks use it)
     const int64_t E = int64_t(NB) * Z;
     std::vector<int32_t> rp(size_t(m) + 1, 0), ci(static_cast<size_t>(E));
@@ -217,13 +222,15 @@ extern "C" cvr_status cvr_code_create_qc(int32_t nb, int32_t mb, int32_t Z, cons
         d.mb = mb;
         d.Z = Z;
         d.NB = NB;
-        int32_t *p_rp, *p_cp;
+        int32_t *p_rp, *p_cp, *p_rk;
         QcBlock *p_r, *p_c;
         if (!st) st = upload(h->allocations, qrow_ptr.data(), qrow_ptr.size(), &p_rp);
         if (!st) st = upload(h->allocations, qrow.data(), qrow.size(), &p_r);
         if (!st) st = upload(h->allocations, qcol_ptr.data(), qcol_ptr.size(), &p_cp);
         if (!st) st = upload(h->allocations, qcol.data(), qcol.size(), &p_c);
+        if (!st) st = upload(h->allocations, rank.data(), rank.size(), &p_rk);
         if (!st) {
+            d.qcol_rank = p_rk;
             d.qrow_ptr = p_rp;
             d.qrow = p_r;
             d.qcol_ptr = p_cp;

@@ -69,6 +69,7 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
     if (p->wg_threads != 0 && p->wg_threads != 512 && p->wg_threads != 1024)
         return fail(CVR_EINVAL, "decode: wg_threads must be 0, 512 or 1024");
     if (p->min_waves != 0 && p->min_waves != 8) return fail(CVR_EINVAL, "decode: min_waves must be 0 or 8");
+    if (p->lds_cache_kb < -1 || p->lds_cache_kb > 1024) return fail(CVR_EINVAL, "decode: lds_cache_kb must be in [-1, 1024]");
     return CVR_OK;
 }
 
@@ -131,7 +132,7 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
         frames = frames_fit(batch) && batch->F >= device_cus();
     }
     int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
-    const LaunchShape sh{params->wg_threads, params->min_waves};
+    const LaunchShape sh{params->wg_threads, params->min_waves, params->lds_cache_kb};
     const bool sp = params->algo == CVR_SP;
     if (params->math == CVR_F64)
         return sp ? decode_f64_sp(batch, a, s, qc, frames, queue, sh) : decode_f64_nms(batch, a, s, qc, frames, queue, sh);

@@ -172,7 +172,7 @@ struct DecArgs {
 
 // Tuning knobs of the persistent decoder (none of them changes results).
 struct LaunchShape {
-    int32_t wg, min_waves;
+    int32_t wg, min_waves, lds_kb;
 };
 
 __device__ __forceinline__ void add_unsat(int32_t* slot, int pred)
@@ -427,15 +427,31 @@ constexpr int kMaxLdsBlocks = 2048;   // protograph limits of the persistent pat
 constexpr int kMaxLdsDim = 512;
 constexpr int kMaxLdsZ = 65535;
 
-// Dynamic LDS of the persistent decoder: the protograph tables of the current
-// code, in 32-bit words at the offsets that LdsMap carries (sized for the
-// largest code of the batch):
+// Dynamic LDS of the persistent decoder, in 32-bit words at the offsets that
+// LdsMap carries (sized for the largest code of the batch):
 //   rptr [mb+1], cptr [nb+1]   block-row / block-column pointers
-//   row  [NB]   shift | block column << 16 | type << 25 (block id = position)
+//   row  [NB]   shift | loc << 16 | type << 25 | cached << 29; loc is the block
+//               column, or its cache slot when the column is cached
 //   col  [NB]   shift | block id << 16
+//   cslot[nb]   cache slot of each block column, -1 when it is not cached
+//   cache       posteriors of the cached block columns, Z per slot
+// The cached columns are the code's highest-degree ones: a posterior is
+// gathered once per edge and written once per iteration, so a column of
+// degree d kept in LDS saves d + 1 HBM accesses per value and iteration.
 struct LdsMap {
-    int32_t rptr, cptr, row, col, words;
+    int32_t rptr, cptr, row, col, cslot, cache;   // word offsets
+    int32_t cache_bytes;
 };
+constexpr int32_t kCached = 1 << 29;
+
+// An LDS read that the compiler cannot merge with a global load of the other
+// branch (a merged load would be a slower generic-address FLAT load); the
+// explicit LDS address space keeps the volatile access a ds_read.
+template <typename T>
+__device__ __forceinline__ T lds_read(const T* p)
+{
+    return *(const volatile __attribute__((address_space(3))) T*)(p);
+}
 
 // Wave-uniform values: with WU every wavefront's 64 rows (variables) lie in one
 // block row (column), which holds when Z is a multiple of 64; the protograph
@@ -455,6 +471,8 @@ struct FrameCtx {
     S* msg;
     const int32_t* s_row;
     const int32_t* s_col;
+    const int32_t* s_cslot;
+    M* s_post;
     const float* s_w;
     int Z, t, T;
     bool weighted;
@@ -465,7 +483,7 @@ struct FrameCtx {
 // edges (D and the entries wave-uniform): the D posteriors and, for t > 0, the
 // D stored messages are loaded before any arithmetic; the code is straight-line.
 // Returns 1 when the row's syndrome test fails on Lpost(t).
-template <typename M, typename S, int ALGO, int D, bool WU>
+template <typename M, typename S, int ALGO, int D, bool WU, bool CACHE>
 __device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k, int sraw)
 {
     int32_t e[D];
@@ -477,7 +495,9 @@ __device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k,
     for (int q = 0; q < D; ++q) {
         int uu = k + (e[q] & 0xffff);
         uu = uu >= c.Z ? uu - c.Z : uu;
-        lr[q] = at(c.Lp, uint32_t(((e[q] >> 16) & 0x1ff) * c.Z + uu));
+        const int idx = ((e[q] >> 16) & 0x1ff) * c.Z + uu;
+        if (CACHE && (e[q] & kCached)) lr[q] = lds_read(c.s_post + idx);
+        else lr[q] = at(c.Lp, uint32_t(idx));
     }
     if (c.t > 0) {
 #pragma unroll
@@ -504,7 +524,7 @@ __device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k,
 }
 
 // The same for any degree d <= MAXD (masked; entries may differ across lanes).
-template <typename M, typename S, int ALGO, int MAXD, bool WU>
+template <typename M, typename S, int ALGO, int MAXD, bool WU, bool CACHE>
 __device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, int d, int k, int sraw)
 {
     int32_t e[MAXD];
@@ -520,7 +540,9 @@ __device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, in
             const int eq = uni<WU>(e[q]);
             int uu = k + (eq & 0xffff);
             uu = uu >= c.Z ? uu - c.Z : uu;
-            lr[q] = at(c.Lp, uint32_t(((eq >> 16) & 0x1ff) * c.Z + uu));
+            const int idx = ((eq >> 16) & 0x1ff) * c.Z + uu;
+            if (CACHE && (eq & kCached)) lr[q] = lds_read(c.s_post + idx);
+            else lr[q] = at(c.Lp, uint32_t(idx));
             if (c.t > 0) mr[q] = at(c.msg, uint32_t((q0 + q) * c.Z + k));
         }
     }
@@ -597,7 +619,7 @@ __device__ __forceinline__ M var_sum_any(const FrameCtx<M, S>& c, int qa, int dv
 // the straight-line body of its exact degree (1..8); larger degrees and
 // codes with Z % 64 != 0 take the masked bodies.  The per-iteration min-sum
 // weights are staged in LDS.
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU>
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, bool CACHE>
 __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm, int32_t* dsm, int32_t (&s_unsat)[2],
                                              float (&s_w)[kMaxTypes], int f, const DevFrame& fr, const DevCode& cd)
 {
@@ -613,6 +635,8 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     c.msg = static_cast<S*>(a.c2v) + fr.msg_off;
     c.s_row = dsm + lm.row;
     c.s_col = dsm + lm.col;
+    c.s_cslot = dsm + lm.cslot;
+    c.s_post = reinterpret_cast<M*>(dsm + lm.cache);
     c.s_w = s_w;
     c.Z = Z;
     c.T = a.T;
@@ -621,9 +645,14 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     c.clamp = a.clamp;
     const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
     M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
+    auto column = [&](int v) { return uni<WU>(zsh >= 0 ? (v >> zsh) : v / Z); };
+    auto slot_of = [&](int j) { return CACHE ? uni<WU>(c.s_cslot[j]) : -1; };
     for (int v = tid; v < n; v += NT) {
+        const int j = column(v);
+        const int slot = slot_of(j);
         const M l = at(c.Lc, v);
-        at(c.Lp, v) = l;
+        if (slot >= 0) c.s_post[slot * Z + (v - j * Z)] = l;
+        else at(c.Lp, v) = l;
         if (tr) tr[v] = l;
     }
     if (tid == 0) {
@@ -651,20 +680,20 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
             const int sraw = syn ? int(at(syn, r)) : 0;
             if constexpr (WU) {
                 switch (d) {
-                case 1: bad += check_row<M, S, ALGO, 1, WU>(c, q0, k, sraw); break;
-                case 2: bad += check_row<M, S, ALGO, 2, WU>(c, q0, k, sraw); break;
-                case 3: bad += check_row<M, S, ALGO, 3, WU>(c, q0, k, sraw); break;
-                case 4: bad += check_row<M, S, ALGO, 4, WU>(c, q0, k, sraw); break;
-                case 5: bad += check_row<M, S, ALGO, 5, WU>(c, q0, k, sraw); break;
-                case 6: bad += check_row<M, S, ALGO, 6, WU>(c, q0, k, sraw); break;
-                case 7: bad += check_row<M, S, ALGO, 7, WU>(c, q0, k, sraw); break;
-                case 8: bad += check_row<M, S, ALGO, 8, WU>(c, q0, k, sraw); break;
+                case 1: bad += check_row<M, S, ALGO, 1, WU, CACHE>(c, q0, k, sraw); break;
+                case 2: bad += check_row<M, S, ALGO, 2, WU, CACHE>(c, q0, k, sraw); break;
+                case 3: bad += check_row<M, S, ALGO, 3, WU, CACHE>(c, q0, k, sraw); break;
+                case 4: bad += check_row<M, S, ALGO, 4, WU, CACHE>(c, q0, k, sraw); break;
+                case 5: bad += check_row<M, S, ALGO, 5, WU, CACHE>(c, q0, k, sraw); break;
+                case 6: bad += check_row<M, S, ALGO, 6, WU, CACHE>(c, q0, k, sraw); break;
+                case 7: bad += check_row<M, S, ALGO, 7, WU, CACHE>(c, q0, k, sraw); break;
+                case 8: bad += check_row<M, S, ALGO, 8, WU, CACHE>(c, q0, k, sraw); break;
                 default:
-                    if constexpr (MAXD > 8) bad += check_row_any<M, S, ALGO, MAXD, WU>(c, q0, d, k, sraw);
+                    if constexpr (MAXD > 8) bad += check_row_any<M, S, ALGO, MAXD, WU, CACHE>(c, q0, d, k, sraw);
                     break;
                 }
             } else {
-                bad += check_row_any<M, S, ALGO, MAXD, WU>(c, q0, d, k, sraw);
+                bad += check_row_any<M, S, ALGO, MAXD, WU, CACHE>(c, q0, d, k, sraw);
             }
         }
         if (bad) atomicAdd(&s_unsat[t & 1], bad);
@@ -683,10 +712,11 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
         // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows ascending
         for (int v = tid; v < n; v += NT) {
-            const int j = uni<WU>(zsh >= 0 ? (v >> zsh) : v / Z);
+            const int j = column(v);
             const int uu = v - j * Z;
             const int qa = uni<WU>(s_cptr[j]);
             const int dv = uni<WU>(s_cptr[j + 1]) - qa;
+            const int slot = slot_of(j);
             M acc = at(c.Lc, v);
             if constexpr (WU) {
                 switch (dv) {
@@ -703,17 +733,31 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
             } else {
                 acc = var_sum_any<M, S, WU>(c, qa, dv, uu, acc);
             }
-            at(c.Lp, v) = acc;
+            if (slot >= 0) c.s_post[slot * Z + uu] = acc;
+            else at(c.Lp, v) = acc;
             if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
         }
         __syncthreads();
     }
-    for (int v = tid; v < n; v += NT) a.bits[fr.vn_off + v] = at(c.Lp, v) < M(0) ? 1 : 0;
+    // hard decisions; cached posteriors go back to HBM
+    for (int v = tid; v < n; v += NT) {
+        const int j = column(v);
+        const int slot = slot_of(j);
+        M l;
+        if (slot >= 0) {
+            l = c.s_post[slot * Z + (v - j * Z)];
+            at(c.Lp, v) = l;
+        } else {
+            l = at(c.Lp, v);
+        }
+        a.bits[fr.vn_off + v] = l < M(0) ? 1 : 0;
+    }
 }
 
-// Loads the LDS tables of code cd (see LdsMap); every thread of the workgroup
+// Loads the LDS tables of code cd (see LdsMap) and assigns the posterior cache
+// slots to its highest-degree block columns; every thread of the workgroup
 // calls it, and it ends with a barrier.
-template <int NT>
+template <typename M, int NT>
 __device__ __forceinline__ void load_code_tables(const LdsMap& lm, int32_t* dsm, const DevCode& cd)
 {
     const int tid = int(threadIdx.x);
@@ -721,18 +765,26 @@ __device__ __forceinline__ void load_code_tables(const LdsMap& lm, int32_t* dsm,
     int32_t* s_cptr = dsm + lm.cptr;
     int32_t* s_row = dsm + lm.row;
     int32_t* s_col = dsm + lm.col;
+    int32_t* s_cslot = dsm + lm.cslot;
+    const int nslot = min(cd.nb, int(lm.cache_bytes / (int64_t(cd.Z) * int64_t(sizeof(M)))));
     for (int q = tid; q <= cd.mb; q += NT) s_rptr[q] = cd.qrow_ptr[q];
     for (int q = tid; q <= cd.nb; q += NT) s_cptr[q] = cd.qcol_ptr[q];
+    for (int q = tid; q < cd.nb; q += NT) s_cslot[q] = -1;
+    __syncthreads();
+    for (int q = tid; q < nslot; q += NT) s_cslot[cd.qcol_rank[q]] = q;
+    __syncthreads();
     for (int q = tid; q < cd.NB; q += NT) {
         const QcBlock br = cd.qrow[q];
-        s_row[q] = br.shift | (br.other << 16) | (br.type << 25);
+        const int slot = s_cslot[br.other];
+        const int loc = slot >= 0 ? slot : br.other;
+        s_row[q] = br.shift | (loc << 16) | (br.type << 25) | (slot >= 0 ? kCached : 0);
         const QcBlock bc = cd.qcol[q];
         s_col[q] = bc.shift | (bc.blk << 16);
     }
     __syncthreads();
 }
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW, bool CACHE>
 __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, int32_t* queue, int32_t F,
                                                         const int32_t* order)
 {
@@ -753,10 +805,10 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, in
         const DevFrame fr = a.frames[f];
         const DevCode& cd = a.codes[fr.code];
         if (fr.code != cur) {
-            load_code_tables<NT>(lm, dsm, cd);
+            load_code_tables<M, NT>(lm, dsm, cd);
             cur = fr.code;
         }
-        decode_frame<M, S, ALGO, MAXD, NT, WU>(a, lm, dsm, s_unsat, s_w, f, fr, cd);
+        decode_frame<M, S, ALGO, MAXD, NT, WU, CACHE>(a, lm, dsm, s_unsat, s_w, f, fr, cd);
     }
 }
 
@@ -861,28 +913,69 @@ static inline int device_cus()
     return cus;
 }
 
-static inline LdsMap lds_map(const cvr_batch_s* b)
+static inline int device_attr(hipDeviceAttribute_t attr, int fallback)
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, attr, dev) == hipSuccess && v > 0) return v;
+    return fallback;
+}
+
+// LDS map of a batch: the tables of its largest code, then the posterior cache.
+static inline LdsMap lds_map(const cvr_batch_s* b, int cache_bytes)
 {
     LdsMap lm{};
     lm.rptr = 0;
     lm.cptr = lm.rptr + b->max_mb + 1;
     lm.row = lm.cptr + b->max_nb + 1;
     lm.col = lm.row + b->max_NB;
-    lm.words = lm.col + b->max_NB;
+    lm.cslot = lm.col + b->max_NB;
+    lm.cache = (lm.cslot + b->max_nb + 3) / 4 * 4;     // 16-byte aligned
+    lm.cache_bytes = cache_bytes;
     return lm;
 }
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
-static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s)
+// lds_kb < 0: no posterior cache; 0: the largest cache that keeps the
+// register-limited number of resident workgroups per CU; > 0: that many KiB
+// (occupancy follows).
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW, bool CACHE>
+static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int lds_kb)
 {
-    auto kern = k_frames_qc<M, S, ALGO, MAXD, NT, WU, MINW>;
-    const LdsMap lm = lds_map(b);
-    const size_t dyn = size_t(lm.words) * 4;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, dyn) != hipSuccess || per_cu < 1) per_cu = 1;
+    auto kern = k_frames_qc<M, S, ALGO, MAXD, NT, WU, MINW, CACHE>;
+    static int lds_blk = 0, lds_cu = 0, static_lds = 0;
+    if (lds_blk == 0) {
+        lds_cu = device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 65536);
+        lds_blk = std::min(lds_cu, device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536));
+        hipFuncAttributes fa{};
+        static_lds = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)) == hipSuccess
+                         ? int(fa.sharedSizeBytes) : 1024;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds_blk - static_lds);
+    }
+    const int tab = lds_map(b, 0).cache * 4;
+    const int room = lds_blk - static_lds - tab;
+    if (room < 0) return fail(CVR_EUNSUPPORTED, "decode (persistent): code tables exceed LDS");
+    auto occupancy = [&](int dyn) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, NT, size_t(dyn)) != hipSuccess || v < 1) v = 1;
+        return v;
+    };
+    int cache = 0;
+    if (!CACHE) {
+        cache = 0;
+    } else if (lds_kb > 0) {
+        cache = std::min(room, lds_kb * 1024);
+    } else if (lds_kb == 0) {
+        const int want = occupancy(tab);                 // workgroups per CU without a cache
+        cache = std::min(room, lds_cu / want - static_lds - tab - 512);
+        while (cache > 0 && occupancy(tab + cache) < want) cache -= 2048;
+    }
+    cache = std::max(0, cache) / 256 * 256;
+    const LdsMap lm = lds_map(b, cache);
+    const int dyn = tab + cache;
+    const int per_cu = occupancy(dyn);
     const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
     ProfScope prof(CVR_PROF_FRAMES, s);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), dyn, s, a, lm, queue, b->F, b->d_order);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), size_t(dyn), s, a, lm, queue, b->F, b->d_order);
     return check_launch("decode (persistent)");
 }
 
@@ -895,23 +988,31 @@ static inline bool wave_uniform(const cvr_batch_s* b)
     return true;
 }
 
+template <typename M, typename S, int ALGO, int MAXD, bool CACHE>
+static cvr_status run_shape(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, const LaunchShape& sh)
+{
+    if (sh.min_waves == 8) {
+        if (sh.wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, true, 8, CACHE>(b, a, queue, s, sh.lds_kb);
+        return launch_frames<M, S, ALGO, MAXD, 512, true, 8, CACHE>(b, a, queue, s, sh.lds_kb);
+    }
+    if (sh.wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, true, 1, CACHE>(b, a, queue, s, sh.lds_kb);
+    return launch_frames<M, S, ALGO, MAXD, 512, true, 1, CACHE>(b, a, queue, s, sh.lds_kb);
+}
+
 template <typename M, typename S, int ALGO, int MAXD>
 static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, const LaunchShape& sh)
 {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, queue, int64_t(1));
     if (cvr_status st = check_launch("decode queue reset")) return st;
-    if (!wave_uniform(b)) return launch_frames<M, S, ALGO, MAXD, 512, false, 1>(b, a, queue, s);
+    if (!wave_uniform(b)) return launch_frames<M, S, ALGO, MAXD, 512, false, 1, false>(b, a, queue, s, -1);
     if constexpr (MAXD > 8 || sizeof(M) == 8) {
         // binary64, and rows of more than 8 edges, need more registers than
-        // the other shapes leave: 512 threads only
-        return launch_frames<M, S, ALGO, MAXD, 512, true, 1>(b, a, queue, s);
+        // the other shapes leave: 512 threads, no posterior cache
+        return launch_frames<M, S, ALGO, MAXD, 512, true, 1, false>(b, a, queue, s, -1);
     } else {
-        if (sh.min_waves == 8) {
-            if (sh.wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, true, 8>(b, a, queue, s);
-            return launch_frames<M, S, ALGO, MAXD, 512, true, 8>(b, a, queue, s);
-        }
-        if (sh.wg == 1024) return launch_frames<M, S, ALGO, MAXD, 1024, true, 1>(b, a, queue, s);
-        return launch_frames<M, S, ALGO, MAXD, 512, true, 1>(b, a, queue, s);
+        // the cache costs a wave-uniform branch per edge: separate kernels
+        if (sh.lds_kb >= 0) return run_shape<M, S, ALGO, MAXD, true>(b, a, queue, s, sh);
+        return run_shape<M, S, ALGO, MAXD, false>(b, a, queue, s, sh);
     }
 }
 

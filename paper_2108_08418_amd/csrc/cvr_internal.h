@@ -74,6 +74,7 @@ struct DevCode {
     const QcBlock* qrow;
     const int32_t* qcol_ptr;
     const QcBlock* qcol;
+    const int32_t* qcol_rank;   // block columns by degree, descending (ties: lower index first)
 };
 
 struct DevFrame {

@@ -1,7 +1,7 @@
 """Autotuner of the persistent decoder's launch shape.
 
 Times ``ldpc_decode_batch`` for every (workgroup size, minimum waves per
-SIMD) candidate on the caller's own batch and inputs with HIP events on the launch stream (the library's launch
+SIMD, LDS posterior cache) candidate on the caller's own batch and inputs with HIP events on the launch stream (the library's launch
 timing) and returns the fastest.  The knobs change the launch configuration
 only, never the results.
 """
@@ -9,8 +9,10 @@ from __future__ import annotations
 
 from . import api
 
-CANDIDATES = [(512, 0), (1024, 0), (512, 8), (1024, 8)]
-KNOBS = ("wg_threads", "min_waves")
+# lds_cache_kb: 0 = as much as keeps the register-limited occupancy, -1 = none,
+# 150 = nearly all of a CU's LDS (one workgroup per CU)
+CANDIDATES = [(512, 0, 0), (1024, 0, 0), (512, 8, 0), (1024, 8, 0), (1024, 8, -1), (1024, 0, 150)]
+KNOBS = ("wg_threads", "min_waves", "lds_cache_kb")
 
 
 def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, candidates=CANDIDATES):

@@ -121,13 +121,18 @@ def test_layouts_and_schedules_are_bit_identical():
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8),
                  dict(algo=api.NMS, store=api.F32, alpha=0.7)):
         runs = []
-        for code, sched, wg, mw in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0),
-                                    (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 0),
-                                    (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 8),
-                                    (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8),
-                                    (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0),
-                                    (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0)):
-            p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, min_waves=mw, **base)
+        # (code, schedule, workgroup, min waves, LDS posterior cache KiB)
+        for code, sched, wg, mw, lk in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, 0),
+                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, -1),
+                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 0, 5),
+                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 0, 0),
+                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 8, 0),
+                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 0),
+                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 150),
+                                        (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0, 0),
+                                        (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0)):
+            p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, min_waves=mw,
+                           lds_cache_kb=lk, **base)
             runs.append(_decode_gpu(code, F, L, syn, p, trace=True))
         for r in runs[1:]:
             for k in ("bits", "post", "iters", "ok", "trace"):
@@ -188,16 +193,18 @@ def test_nms_uniform_weights_equal_alpha():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("sizes,sched", [
-    ((4096, 8192, 4096), api.SCHED_PERSISTENT),        # Z = 32 / 64: lane-varying block rows
-    ((8192, 16384, 8192), api.SCHED_PERSISTENT),       # Z % 64 == 0: wave-uniform kernel
-    ((4096, 8192, 4096), api.SCHED_PASSES),
+@pytest.mark.parametrize("sizes,sched,lds_kb", [
+    ((4096, 8192, 4096), api.SCHED_PERSISTENT, 0),        # Z = 32 / 64: lane-varying block rows
+    ((8192, 16384, 8192), api.SCHED_PERSISTENT, 0),       # Z % 64 == 0: wave-uniform kernel
+    ((8192, 16384, 8192), api.SCHED_PERSISTENT, 20),      # a few cached columns, a different number per code
+    ((8192, 16384, 8192), api.SCHED_PERSISTENT, -1),
+    ((4096, 8192, 4096), api.SCHED_PASSES, 0),
 ])
-def test_ragged_batch_mixed_codes_and_gaps(sizes, sched):
+def test_ragged_batch_mixed_codes_and_gaps(sizes, sched, lds_kb):
     """Frames of different codes and lengths at scattered offsets: each frame
     decodes exactly as it does alone (the persistent decoder reloads its LDS
-    tables at every change of code)."""
-    print(f"[decode ragged sizes={sizes} schedule={sched}]", flush=True)
+    tables and posterior cache at every change of code)."""
+    print(f"[decode ragged sizes={sizes} schedule={sched} lds={lds_kb}]", flush=True)
     specs = [inputs.slice_code_spec(3, sizes[0]), inputs.slice_code_spec(2, sizes[1]),
              inputs.lambda_half_rate_spec(sizes[2])]
     codes = [api.Code.from_qc(q) for q in specs]
@@ -220,7 +227,7 @@ def test_ragged_batch_mixed_codes_and_gaps(sizes, sched):
         S[c0:c0 + len(s)] = s
     batch = api.Batch(codes, frames)
     assert batch.total_n <= total_n and batch.F == len(order)
-    p = api.Params(algo=api.SP, max_iter=30, math=api.F32, store=api.F32, schedule=sched)
+    p = api.Params(algo=api.SP, max_iter=30, math=api.F32, store=api.F32, schedule=sched, lds_cache_kb=lds_kb)
     out = api.ldpc_decode_batch(batch, p, _g(L), _g(S))
     torch.cuda.synchronize()
     solo_p = api.Params(algo=api.SP, max_iter=30, math=api.F32, store=api.F32, schedule=api.SCHED_PASSES)
