@@ -77,11 +77,15 @@ def parse():
 
 
 def csrc_hash() -> str:
+    """Hash of the sources the decoder kernels are built from (a recorded
+    traffic figure is valid while it is unchanged)."""
     import hashlib
     from pathlib import Path
     h = hashlib.sha256()
-    for p in sorted((Path(ROOT) / "paper_2108_08418_amd" / "csrc").glob("*")):
-        if p.suffix in (".hip", ".h"):
+    csrc = Path(ROOT) / "paper_2108_08418_amd" / "csrc"
+    for p in sorted(csrc.glob("*")):
+        if p.name in ("cvr_decode_impl.h", "cvr_internal.h", "cvr_decode.hip", "cvr_codes.hip") or \
+                p.name.startswith("cvr_dec_"):
             h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
