@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--min-waves", dest="min_waves", type=int, default=0, help="0 or 8 resident waves per SIMD")
     ap.add_argument("--lds-cache", dest="lds_cache_kb", type=int, default=0,
                     help="LDS posterior cache KiB of the persistent decoder (0 = auto, -1 = none)")
-    ap.add_argument("--cpu-frames", type=int, default=16, help="sub-blocks per stage in the oracle sample")
+    ap.add_argument("--cpu-frames", type=int, default=48, help="sub-blocks per stage in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2108)
     ap.add_argument("--graph", action="store_true", help="replay the decode from a captured HIP graph")
@@ -90,10 +90,11 @@ def csrc_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel_name: str):
+def recorded_traffic(kernel_name: str, workload: str, decoder: str, weights: str):
     """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded under
-    profiles/ for this kernel instantiation, or None when no record exists or
-    the kernel sources changed since the counters were taken."""
+    profiles/ for this kernel instantiation, workload, decoder and weights, or None when
+    no record exists or the decoder sources changed since the counters were
+    taken."""
     from pathlib import Path
     sha = csrc_hash()
     for p in sorted((Path(ROOT) / "profiles").glob("*_hbm_traffic.md")):
@@ -101,7 +102,9 @@ def recorded_traffic(kernel_name: str):
         if "```json" not in text:
             continue
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-        if rec.get("source_sha") == sha and rec.get("kernel", "").startswith(kernel_name):
+        if (rec.get("source_sha") == sha and rec.get("kernel", "").startswith(kernel_name)
+                and rec.get("workload") == workload and rec.get("decoder") == decoder
+                and rec.get("weights", "") == (weights or "")):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], p.name
     return None, None
 
@@ -292,7 +295,7 @@ def recon(args, wl, dev):
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
         iter_gbs = achieved
-        traffic, traffic_src = recorded_traffic(inst)
+        traffic, traffic_src = recorded_traffic(inst, args.workload, args.decoder, args.weights)
     else:
         roof_kernel = "decoder check-node pass (k_check_qc)"
         achieved = (args.steps * chk_bytes) / (chk_ms * 1e-3) / 1e9 if chk_ms > 0 else None
@@ -450,7 +453,7 @@ def ragged(args, wl, dev):
     mt = "float, float" if store == api.F32 else "float, __half"
     inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
             f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
-    traffic, traffic_src = recorded_traffic(inst)
+    traffic, traffic_src = recorded_traffic(inst, args.workload, args.decoder, args.weights)
     value = total_n / (t_total / args.steps)
     result = {
         "metric": "decoded bits/s of a batch of uneven sub-blocks (one persistent launch)",
@@ -502,8 +505,8 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 2 * Ns / dt, "unit": "bits/s", "cores": min(cores, os.cpu_count() or cores),
             "kind": "oracle", "seconds": dt,
-            "sample": f"first {Fs} sub-blocks (of {n}) of both coded slices: fp64 quantiser, syndromes, "
-                      f"slice LLRs and decoding; decode threads across sub-blocks"}
+            "sample": f"first {Fs} of the {len(x_np) // n} sub-blocks of {n} bits of both coded slices: fp64 "
+                      f"quantiser, syndromes, slice LLRs and decoding; decode threads across sub-blocks"}
 
 
 if __name__ == "__main__":

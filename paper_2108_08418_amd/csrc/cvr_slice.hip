@@ -107,11 +107,32 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double v)
     }
 }
 
+// Pr(lo <= Z < hi) for a standard normal Z in the same mirrored form as
+// ln_interval, from the complementary error function: the upper-tail case is
+// (erfc(lo/sqrt 2) - erfc(hi/sqrt 2)) / 2, the case containing the mean
+// 1 - (erfc(|lo|/sqrt 2) + erfc(hi/sqrt 2)) / 2.  erfc keeps its relative
+// accuracy down to about 1e-300, i.e. |z| up to about 37.
+__device__ __forceinline__ double interval_prob(double lo, double hi)
+{
+    if (hi <= 0.0) {
+        const double t = lo;
+        lo = -hi;
+        hi = -t;
+    }
+    const double ea = erfc(fabs(lo) * M_SQRT1_2);
+    const double eb = erfc(hi * M_SQRT1_2);
+    return (lo >= 0.0) ? 0.5 * (ea - eb) : 1.0 - 0.5 * (ea + eb);
+}
+
 // One thread per sample.  Only the 2^(m - |known|) labels that agree with the
 // sample's known slice bits are visited (a uniform trip count: the free bit
 // positions are the same for every sample), so wavefronts do not diverge over
 // interval membership.  Interval bounds come from an LDS copy of the
 // thresholds with t_0 = -inf and t_{2^m} = +inf.
+// The two sums of interval probabilities are formed in linear fp64 (two erfc
+// per interval, one log per sample); a sample whose smaller sum falls below
+// 1e-290, where erfc would lose relative accuracy or underflow, is redone in
+// the log domain (ln_interval and a running log-sum-exp).
 __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
 {
     __shared__ double bnd[kMaxThr + 2];
@@ -121,30 +142,48 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
     __syncthreads();
     const uint32_t freemask = uint32_t(K - 1) & ~a.known;
     const int nfree = __popc(freemask);
+    const double inv_sigma = 1.0 / a.sigma;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += stride) {
         const double x = a.x[i];
         uint32_t kb = 0;
         for (int q = 0; q < a.m_bits; ++q)
             if ((a.known >> q) & 1u) kb |= uint32_t(a.slices[int64_t(q) * a.n + i] & 1) << q;
-        double m0 = -INFINITY, s0 = 0.0, m1 = -INFINITY, s1 = 0.0;
-        for (int c = 0; c < (1 << nfree); ++c) {
-            // deposit the bits of c into the free label positions
+        // interval index and bit j of the c-th label consistent with the known bits
+        auto label = [&](int c, uint32_t& k) {
             uint32_t g = kb, fm = freemask;
             for (int b = 0; b < nfree; ++b) {
                 const uint32_t low = fm & (~fm + 1u);
                 if ((c >> b) & 1) g |= low;
                 fm &= fm - 1u;
             }
-            // interval index of label g
-            uint32_t k = g;
+            k = g;
             if (a.gray)
                 for (uint32_t sh = 1; sh < 8; sh <<= 1) k ^= k >> sh;
-            const double lp = ln_interval((bnd[k] - x) / a.sigma, (bnd[k + 1] - x) / a.sigma);
-            if ((g >> a.j) & 1u) lse_push(m1, s1, lp);
-            else lse_push(m0, s0, lp);
+            return (g >> a.j) & 1u;
+        };
+        double p0 = 0.0, p1 = 0.0;
+        for (int c = 0; c < (1 << nfree); ++c) {
+            uint32_t k;
+            const uint32_t bit = label(c, k);
+            const double p = interval_prob((bnd[k] - x) * inv_sigma, (bnd[k + 1] - x) * inv_sigma);
+            if (bit) p1 += p;
+            else p0 += p;
         }
-        const double L = (m0 + log(s0)) - (m1 + log(s1));
+        double L;
+        if (p0 > 1e-290 && p1 > 1e-290) {
+            L = log(p0 / p1);
+        } else {
+            double m0 = -INFINITY, s0 = 0.0, m1 = -INFINITY, s1 = 0.0;
+            for (int c = 0; c < (1 << nfree); ++c) {
+                uint32_t k;
+                const uint32_t bit = label(c, k);
+                const double lp = ln_interval((bnd[k] - x) / a.sigma, (bnd[k + 1] - x) / a.sigma);
+                if (bit) lse_push(m1, s1, lp);
+                else lse_push(m0, s0, lp);
+            }
+            L = (m0 + log(s0)) - (m1 + log(s1));
+        }
         if (a.out_f64) static_cast<double*>(a.out)[i] = L;
         else static_cast<float*>(a.out)[i] = float(L);
     }

@@ -69,6 +69,25 @@ def test_slice_llr_fp64_parity(j, mask):
     assert err.max() <= 1e-12, (err.max(), int(err.argmax()))
 
 
+@pytest.mark.parametrize("j,mask", [(2, 0b11), (3, 0b111), (1, 0b1101)])
+def test_slice_llr_extreme_inputs_use_the_log_domain(j, mask):
+    """Samples so far out that the interval probabilities underflow in linear
+    fp64 (|z| up to 1.7e3): the kernel redoes them in the log domain and stays
+    finite and within the same bound of the oracle; ordinary samples in the
+    same launch are unaffected."""
+    rng = np.random.default_rng(7 + j)
+    far = np.array([-1000.0, -100.0, -40.0, -25.0, 25.0, 40.0, 100.0, 1000.0])
+    x = np.concatenate([far, rng.standard_normal(4096 - far.size)])
+    S = rng.integers(0, 2, size=(4, x.size), dtype=np.uint8)
+    Lg = api.slice_llr(_g(x), SIG, TH4, 4, j, mask, _g(S), out_dtype=api.F64)
+    torch.cuda.synchronize()
+    Lo = oracle.slice_llr(x, SIG, TH4, 4, oracle.GRAY, j, mask, S)
+    Lg = Lg.cpu().numpy()
+    assert np.isfinite(Lg).all() and np.isfinite(Lo).all()
+    err = np.abs(Lg - Lo) / np.maximum(1.0, np.abs(Lo))
+    assert err.max() <= 1e-12, (err.max(), int(err.argmax()))
+
+
 def test_slice_llr_fp32_output_is_rounded_fp64():
     N = (1 << 20) + 7
     x, y = inputs.gaussian_pairs(N, SNR, seed=9)
