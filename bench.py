@@ -40,6 +40,11 @@ WORKLOADS = {
     # SNR 0.16, decoded in one persistent launch
     "ragged-4096-frames": dict(kind="ragged", sizes=(4096, 16384, 65536, 262144), counts=(2176, 1024, 640, 256),
                                snr=0.16),
+    # one training step of the differentiable unrolled min-sum: 256 frames of
+    # the rate-1/2 code (n = 16384), Eb/N0 uniform in [1.5, 3] dB, 20 iterations,
+    # 20 x 3 weights, checkpoints every 5 iterations; forward, BCE loss, adjoint,
+    # Adam update
+    "train-nms-r12-n16384-T20": dict(kind="train", n=16384, F=256, T=20, K=5),
 }
 SNR = 3.0
 M_BITS = 4
@@ -171,6 +176,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl.get("kind") == "ragged":
         return ragged(args, wl, dev)
+    if wl.get("kind") == "train":
+        return train_step(args, wl, dev)
     print(json.dumps(recon(args, wl, dev)))
 
 
@@ -261,7 +268,7 @@ def recon(args, wl, dev):
     t_total = time.perf_counter() - t_start
     api.profile_enable(False)
     prof = {name: api.profile_read(k, reset=True) for k, name in enumerate(
-        ["quantize", "slice_llr", "syndrome", "check", "var", "dec_setup", "decode_persistent", "other"])}
+        ["quantize", "slice_llr", "syndrome", "check", "var", "dec_setup", "decode_persistent", "adjoint"])}
     ms_step = 1e3 * t_total / args.steps
     decoded_bits = 2 * N
     value = decoded_bits / (t_total / args.steps)
@@ -476,6 +483,81 @@ def ragged(args, wl, dev):
         "mean_iters": float(iters.mean()),
         "bit_errors": int(err.sum()),
         "autotune_ms_per_decode": tuned,
+    }
+    print(json.dumps(result))
+
+
+def adjoint_bytes(F, E, n, T, K):
+    """Algorithmic bytes of the adjoint launch: for each frame, the forward
+    iterations recomputed from the checkpoints (T - ceil(T / K); each reads and
+    writes every fp32 message once and moves 12 bytes per variable), and T
+    reverse iterations, each reading the messages of iteration t and the
+    adjoint of the messages and writing the new adjoint (12 bytes per edge)
+    plus 12 bytes per variable (channel LLR, posterior)."""
+    nseg = -(-T // K)
+    return float(F) * ((T - nseg) * (8 * E + 12 * n) + T * (12 * E + 12 * n))
+
+
+def train_step(args, wl, dev):
+    """One training step of the unrolled min-sum: forward with checkpoints,
+    loss, adjoint, optimiser update, on inputs already resident in HBM."""
+    import torch
+
+    from paper_2108_08418_amd import api, inputs
+    from paper_2108_08418_amd.train import BpskFrames
+
+    n, F, T, K = wl["n"], wl["F"], wl["T"], wl["K"]
+    qc = inputs.lambda_half_rate_spec(n)
+    frames = BpskFrames(qc, F, (1.5, 3.0), 0.5, dev)
+    llr, syn, bits = frames.batch(0)
+    batch = api.Batch.uniform(frames.code, F)
+    sign = 1.0 - 2.0 * bits.to(torch.float32)
+    w = torch.full((T, qc.n_types), 0.75, dtype=torch.float32, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=0.02)
+    torch.cuda.synchronize()
+
+    def step():
+        post = api.NMSUnrolled.apply(w, llr, syn, batch, T, K)
+        loss = torch.nn.functional.softplus(-sign * post).mean()
+        opt.zero_grad(set_to_none=False)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            w.clamp_(0.05, 1.5)
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    api.profile_enable(True)
+    for k in range(8):
+        api.profile_read(k, reset=True)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    api.profile_enable(False)
+    fwd_ms, fwd_n = api.profile_read(api.PROF_FRAMES, reset=True)
+    adj_ms, adj_n = api.profile_read(api.PROF_ADJOINT, reset=True)
+    E = qc.n_edges
+    adj_bytes = adjoint_bytes(F, E, n, T, K)
+    achieved = adj_bytes * adj_n / (adj_ms * 1e-3) / 1e9 if adj_ms > 0 else None
+    step_s = t_total / args.steps
+    result = {
+        "metric": "unrolled min-sum training: bits/s through forward + adjoint",
+        "value": F * n / step_s, "unit": "bits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * step_s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic: seeded random words and BPSK/AWGN, Eb/N0 uniform in [1.5, 3] dB",
+        "config": {"workload": args.workload, "frames": F, "n": n, "T": T, "ckpt_every": K,
+                   "code": qc.name, "n_types": qc.n_types, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "void cvr::k_nms_bwd_qc<8, true, 1024>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": None, "avg_launch_us": 1e3 * adj_ms / adj_n if adj_n else None,
+                     "algorithmic_bytes_per_launch": adj_bytes},
+        "forward_ms": fwd_ms / max(fwd_n, 1), "adjoint_ms": adj_ms / max(adj_n, 1),
+        "edge_iterations_per_s": 2.0 * F * E * T / step_s,
+        "loss": float(loss),
     }
     print(json.dumps(result))
 

@@ -272,7 +272,7 @@ enum {
     CVR_PROF_VAR = 4,          /* decoder variable-node pass (one per iteration)  */
     CVR_PROF_DEC_SETUP = 5,    /* decoder set-up and output passes                */
     CVR_PROF_FRAMES = 6,       /* persistent decoder (whole decode in one launch) */
-    CVR_PROF_OTHER = 7
+    CVR_PROF_ADJOINT = 7       /* nms_unrolled_bwd (adjoint of unrolled min-sum)  */
 };
 
 /* on != 0: every later launch of the library is bracketed by two HIP events on

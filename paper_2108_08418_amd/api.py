@@ -274,7 +274,7 @@ def version() -> int:
 # ---------------------------------------------------------------------------
 # launch timing
 # ---------------------------------------------------------------------------
-PROF_QUANTIZE, PROF_LLR, PROF_SYNDROME, PROF_CHECK, PROF_VAR, PROF_DEC_SETUP, PROF_FRAMES, PROF_OTHER = range(8)
+PROF_QUANTIZE, PROF_LLR, PROF_SYNDROME, PROF_CHECK, PROF_VAR, PROF_DEC_SETUP, PROF_FRAMES, PROF_ADJOINT = range(8)
 
 
 def profile_enable(on: bool = True) -> None:

@@ -55,10 +55,13 @@ struct LdsCode {
     int2 col[kMaxLdsBlocks];   // x = shift, y = block id
 };
 
-template <int MAXD>
-__global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
+// Every step below issues all of its loads before using any of them (so a
+// wavefront keeps them in flight together); with WU (Z % 64 == 0) the block
+// row / column of a wavefront, and so its degree and table entries, are
+// wave-uniform.
+template <int MAXD, bool WU, int NT>
+__global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
 {
-    constexpr int NT = kGradThreads;
     __shared__ LdsCode sc;
     __shared__ float s_red[NT / 64][kGradTypes];
     __shared__ float s_dw[kGradMaxT * kGradTypes];
@@ -94,28 +97,28 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
         float* dllr = a.dllr ? a.dllr + fr.vn_off : nullptr;
 
         auto row_of = [&](int r, int& q0, int& d, int& k) {
-            const int i = zsh >= 0 ? (r >> zsh) : r / Z;
+            const int i = uni<WU>(zsh >= 0 ? (r >> zsh) : r / Z);
             k = r - i * Z;
-            q0 = sc.rptr[i];
-            d = sc.rptr[i + 1] - q0;
+            q0 = uni<WU>(sc.rptr[i]);
+            d = uni<WU>(sc.rptr[i + 1]) - q0;
         };
         auto var_of = [&](int v, int& qa, int& dv, int& u) {
-            const int j = zsh >= 0 ? (v >> zsh) : v / Z;
+            const int j = uni<WU>(zsh >= 0 ? (v >> zsh) : v / Z);
             u = v - j * Z;
-            qa = sc.cptr[j];
-            dv = sc.cptr[j + 1] - qa;
+            qa = uni<WU>(sc.cptr[j]);
+            dv = uni<WU>(sc.cptr[j + 1]) - qa;
         };
         auto edge_var = [&](int q, int k) -> int {       // variable of row-table entry q at check offset k
             const int2 e = sc.row[q];
-            int u = k + e.x;
+            int u = k + uni<WU>(e.x);
             u = u >= Z ? u - Z : u;
-            return (e.y & 0xfffff) * Z + u;
+            return uni<WU>(e.y & 0xfffff) * Z + u;
         };
         auto col_edge = [&](int q, int u) -> int {       // message index of column-table entry q at variable offset u
             const int2 e = sc.col[q];
-            int k = u - e.x;
+            int k = u - uni<WU>(e.x);
             k = k < 0 ? k + Z : k;
-            return e.y * Z + k;
+            return uni<WU>(e.y) * Z + k;
         };
         // L = L_ch + sum of c2v, block rows ascending (the forward's order)
         auto posterior = [&](const float* c2v) {
@@ -123,27 +126,47 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
                 int qa, dv, u;
                 var_of(v, qa, dv, u);
                 float acc = Lc[v];
-                for (int q = 0; q < dv; ++q) acc += c2v[col_edge(qa + q, u)];
+                for (int q8 = 0; q8 < dv; q8 += 8) {
+                    float c[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) c[q] = (q8 + q < dv) ? c2v[col_edge(qa + q8 + q, u)] : 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q8 + q < dv) acc += opaque(c[q]);
+                }
                 Lp[v] = acc;
             }
         };
-        // incoming v2c of a row (as the forward forms it) and its min/sign summary
-        auto row_inputs = [&](int t, const float* c2v, int q0, int d, int k, float (&x)[MAXD]) {
+        // posteriors and messages of a row, and (with gp) the adjoints of its
+        // messages, all loaded first; then the incoming v2c as the forward forms
+        // it (L_post - c2v; the checkpoint at t = 0 holds zeros)
+        auto row_inputs = [&](const float* c2v, int q0, int d, int k, float (&x)[MAXD], float* gp, float (&g)[MAXD]) {
+            float lp[MAXD], cv[MAXD];
 #pragma unroll
             for (int q = 0; q < MAXD; ++q) {
-                x[q] = 0.0f;
+                lp[q] = 0.0f;
+                cv[q] = 0.0f;
+                g[q] = 0.0f;
                 if (q < d) {
-                    const float lp = Lp[edge_var(q0 + q, k)];
-                    x[q] = (t == 0) ? lp : lp - c2v[(q0 + q) * Z + k];
+                    lp[q] = Lp[edge_var(q0 + q, k)];
+                    cv[q] = c2v[(q0 + q) * Z + k];
+                    if (gp) g[q] = gp[(q0 + q) * Z + k];
                 }
             }
+#pragma unroll
+            for (int q = 0; q < MAXD; ++q) x[q] = (q < d) ? opaque(lp[q]) - opaque(cv[q]) : 0.0f;
         };
 
         // dl/dc2v(T) = dl/dL(T) on every edge; dl/dL_ch starts at dl/dL(T)
         for (int r = tid; r < m; r += NT) {
             int q0, d, k;
             row_of(r, q0, d, k);
-            for (int q = 0; q < d; ++q) G[(q0 + q) * Z + k] = dpost[edge_var(q0 + q, k)];
+            float dp[MAXD];
+#pragma unroll
+            for (int q = 0; q < MAXD; ++q) dp[q] = (q < d) ? dpost[edge_var(q0 + q, k)] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < MAXD; ++q)
+                if (q < d) G[(q0 + q) * Z + k] = opaque(dp[q]);
         }
         if (dllr)
             for (int v = tid; v < n; v += NT) dllr[v] = dpost[v];
@@ -166,10 +189,10 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
                 for (int r = tid; r < m; r += NT) {
                     int q0, d, k;
                     row_of(r, q0, d, k);
-                    float x[MAXD];
-                    row_inputs(t, cin, q0, d, k, x);
                     const int sbit = syn ? (syn[r] & 1) : 0;
-                    auto weight = [&](int q) -> float { return wt[sc.row[q0 + q].y >> 20]; };
+                    float x[MAXD], unused[MAXD];
+                    row_inputs(cin, q0, d, k, x, nullptr, unused);
+                    auto weight = [&](int q) -> float { return wt[uni<WU>(sc.row[q0 + q].y >> 20)]; };
                     auto emit = [&](int q, float v) { cout[(q0 + q) * Z + k] = v; };
                     check_rule<float, CVR_NMS, MAXD>(x, d, sbit, 0.0f, weight, emit);
                 }
@@ -185,9 +208,11 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
                 for (int r = tid; r < m; r += NT) {
                     int q0, d, k;
                     row_of(r, q0, d, k);
-                    float x[MAXD];
-                    row_inputs(t, cin, q0, d, k, x);
                     const int sbit = syn ? (syn[r] & 1) : 0;
+                    float x[MAXD], g[MAXD];
+                    row_inputs(cin, q0, d, k, x, G, g);
+                    // signs, and the smallest and second smallest |x| with their
+                    // first positions (branch-free, the forward's tie rule)
                     uint32_t negm = 0;
                     float m1 = INFINITY, m2 = INFINITY;
                     int i1 = -1, i2 = -1;
@@ -196,15 +221,12 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
                         if (q < d) {
                             if (x[q] < 0.0f) negm |= 1u << q;
                             const float v = fabsf(x[q]);
-                            if (v < m1) {
-                                m2 = m1;
-                                i2 = i1;
-                                m1 = v;
-                                i1 = q;
-                            } else if (v < m2) {
-                                m2 = v;
-                                i2 = q;
-                            }
+                            const bool lt = v < m1;
+                            const bool lt2 = !lt && v < m2;
+                            m2 = lt ? m1 : (lt2 ? v : m2);
+                            i2 = lt ? i1 : (lt2 ? q : i2);
+                            m1 = lt ? v : m1;
+                            i1 = lt ? q : i1;
                         }
                     }
                     const uint32_t tot = uint32_t(__popc(negm) & 1) ^ uint32_t(sbit);
@@ -212,14 +234,13 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
 #pragma unroll
                     for (int q = 0; q < MAXD; ++q) {
                         if (q < d) {
-                            const int ty = sc.row[q0 + q].y >> 20;
+                            const int ty = uni<WU>(sc.row[q0 + q].y >> 20);
                             const float sg = ((tot ^ ((negm >> q) & 1u)) != 0) ? -1.0f : 1.0f;
                             const float mag = (q == i1) ? m2 : m1;
-                            const float g = G[(q0 + q) * Z + k];
-                            const float contrib = g * sg * mag;
+                            const float contrib = g[q] * sg * mag;
 #pragma unroll
                             for (int tt = 0; tt < kGradTypes; ++tt) acc[tt] += (tt == ty) ? contrib : 0.0f;
-                            const float u = g * wt[ty] * sg;
+                            const float u = g[q] * wt[ty] * sg;
                             if (q == i1) u1 = u;
                             else s1 += u;
                         }
@@ -248,17 +269,33 @@ __global__ __launch_bounds__(kGradThreads) void k_nms_bwd_qc(GradArgs a)
                         for (int w = 0; w < NT / 64; ++w) v += s_red[w][tt];
                         s_dw[t * kGradTypes + tt] += v;
                     }
-                // through the variable nodes
+                // through the variable nodes: G = (sum of the column's GV) - GV
                 for (int v = tid; v < n; v += NT) {
                     int qa, dv, u;
                     var_of(v, qa, dv, u);
                     float gsum = 0.0f;
-                    for (int q = 0; q < dv; ++q) gsum += GV[col_edge(qa + q, u)];
-                    if (t > 0)
-                        for (int q = 0; q < dv; ++q) {
-                            const int e = col_edge(qa + q, u);
-                            G[e] = gsum - GV[e];
-                        }
+                    if (dv <= 8) {
+                        int e[8];
+                        float gv[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) e[q] = (q < dv) ? col_edge(qa + q, u) : 0;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) gv[q] = (q < dv) ? GV[e[q]] : 0.0f;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (q < dv) gsum += opaque(gv[q]);
+                        if (t > 0)
+#pragma unroll
+                            for (int q = 0; q < 8; ++q)
+                                if (q < dv) G[e[q]] = gsum - gv[q];
+                    } else {
+                        for (int q = 0; q < dv; ++q) gsum += GV[col_edge(qa + q, u)];
+                        if (t > 0)
+                            for (int q = 0; q < dv; ++q) {
+                                const int e = col_edge(qa + q, u);
+                                G[e] = gsum - GV[e];
+                            }
+                    }
                     if (dllr) dllr[v] += gsum;
                 }
                 __syncthreads();
@@ -279,15 +316,43 @@ __global__ __launch_bounds__(256) void k_sum_partials(const float* partials, int
     out[q] = v;
 }
 
-static int grad_grid(const cvr_batch_s* b)
+// Rows of up to 8 edges run 1024 threads per workgroup (a frame per workgroup,
+// so batches of about one frame per CU still have 16 waves per CU); wider rows
+// need more registers than that leaves and run 512.
+template <int MAXD, bool WU, int NT>
+static int bwd_per_cu()
 {
     static int per_cu = 0;
     if (per_cu == 0) {
         int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_nms_bwd_qc<8>, kGradThreads, 0) != hipSuccess || v < 1) v = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_nms_bwd_qc<MAXD, WU, NT>, NT, 0) != hipSuccess || v < 1)
+            v = 1;
         per_cu = v;
     }
-    return int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
+    return per_cu;
+}
+
+// The adjoint launch for batch b: grid (one partial weight-gradient row per
+// workgroup) and, when launch is true, the launch itself.
+template <int MAXD>
+static int bwd_launch(const cvr_batch_s* b, const GradArgs* g, hipStream_t s)
+{
+    constexpr int NT = MAXD <= 8 ? 1024 : 512;
+    const bool wu = wave_uniform(b);
+    const int per_cu = wu ? bwd_per_cu<MAXD, true, NT>() : bwd_per_cu<MAXD, false, NT>();
+    const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
+    if (g) {
+        if (wu) hipLaunchKernelGGL((k_nms_bwd_qc<MAXD, true, NT>), dim3(grid), dim3(NT), 0, s, *g);
+        else hipLaunchKernelGGL((k_nms_bwd_qc<MAXD, false, NT>), dim3(grid), dim3(NT), 0, s, *g);
+    }
+    return grid;
+}
+
+static int grad_grid(const cvr_batch_s* b)
+{
+    if (b->max_row_deg <= 8) return bwd_launch<8>(b, nullptr, nullptr);
+    if (b->max_row_deg <= 16) return bwd_launch<16>(b, nullptr, nullptr);
+    return bwd_launch<32>(b, nullptr, nullptr);
 }
 
 static cvr_status check_unrolled(const char* fn, const cvr_batch_s* b, int32_t T, int32_t K)
@@ -397,7 +462,7 @@ extern "C" cvr_status nms_unrolled_fwd(cvr_batch_t batch, int32_t T, int32_t ckp
     a.ckpt = ckpt;
     a.ckpt_stride = batch->total_E;
     a.ckpt_every = ckpt_every;
-    return decode_f32_nms(batch, a, hipStream_t(stream), true, true, reinterpret_cast<int32_t*>(dws + w.queue), LaunchShape{0, 0, 0});
+    return decode_f32_nms(batch, a, hipStream_t(stream), true, true, reinterpret_cast<int32_t*>(dws + w.queue), LaunchShape{1024, 0, 0});
 }
 
 extern "C" cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckpt_every, const float* weights,
@@ -440,10 +505,10 @@ extern "C" cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckp
     g.F = batch->F;
     const int grid = grad_grid(batch);
     {
-        ProfScope prof(CVR_PROF_OTHER, s);
-        if (batch->max_row_deg <= 8) hipLaunchKernelGGL(k_nms_bwd_qc<8>, dim3(grid), dim3(kGradThreads), 0, s, g);
-        else if (batch->max_row_deg <= 16) hipLaunchKernelGGL(k_nms_bwd_qc<16>, dim3(grid), dim3(kGradThreads), 0, s, g);
-        else hipLaunchKernelGGL(k_nms_bwd_qc<32>, dim3(grid), dim3(kGradThreads), 0, s, g);
+        ProfScope prof(CVR_PROF_ADJOINT, s);
+        if (batch->max_row_deg <= 8) bwd_launch<8>(batch, &g, s);
+        else if (batch->max_row_deg <= 16) bwd_launch<16>(batch, &g, s);
+        else bwd_launch<32>(batch, &g, s);
     }
     if (cvr_status st = check_launch("nms_unrolled_bwd")) return st;
     hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, s, g.partials, grid, count, dweights);
