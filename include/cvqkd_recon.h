@@ -179,8 +179,14 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            frames (any code); CVR_SCHED_PERSISTENT: one persistent launch in
  *            which each workgroup iterates whole frames to their stop (QC codes
  *            with <= 2048 circulants, <= 512 block rows/columns and Z <= 65535, else
- *            CVR_EUNSUPPORTED); CVR_SCHED_AUTO: persistent when possible
- *            and the batch has at least one frame per compute unit, else passes.
+ *            CVR_EUNSUPPORTED); CVR_SCHED_GRID: one launch of resident
+ *            workgroups that sweep the rows (variables) of all frames, with a
+ *            grid-wide barrier between the passes and an early end when every
+ *            frame has stopped (QC codes with Z <= 65535 and <= 512 block
+ *            columns, else CVR_EUNSUPPORTED; slower than passes on MI355X,
+ *            where each barrier writes back and invalidates the per-XCD L2
+ *            caches); CVR_SCHED_AUTO: persistent when possible and the batch
+ *            has at least one frame per compute unit, else passes.
  *  wg_threads, min_waves  tuning knobs of the persistent decoder that do
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
@@ -190,7 +196,7 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            persistent decoder keeps in LDS (results unchanged): 0 = as much
  *            as fits without fewer resident workgroups, -1 = none, > 0 = that
  *            many KiB (capped by the LDS size).                               */
-enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2 };
+enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2, CVR_SCHED_GRID = 3 };
 
 typedef struct {
     int32_t algo;

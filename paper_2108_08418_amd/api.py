@@ -19,7 +19,7 @@ from ._lib import DecodeParams, Frame, check, load
 GRAY, BINARY = 0, 1
 SP, NMS = 0, 1
 F64, F32, F16 = 0, 1, 2
-SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT = 0, 1, 2
+SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT, SCHED_GRID = 0, 1, 2, 3
 
 _TORCH_OF = {F64: torch.float64, F32: torch.float32}
 

@@ -229,7 +229,18 @@ extern "C" cvr_status cvr_code_create_qc(int32_t nb, int32_t mb, int32_t Z, cons
         if (!st) st = upload(h->allocations, qcol_ptr.data(), qcol_ptr.size(), &p_cp);
         if (!st) st = upload(h->allocations, qcol.data(), qcol.size(), &p_c);
         if (!st) st = upload(h->allocations, rank.data(), rank.size(), &p_rk);
+        int32_t *p_rpk = nullptr, *p_cpk = nullptr;
+        if (!st && Z <= 65535 && nb <= 512) {
+            std::vector<int32_t> rpk(qrow.size()), cpk(qcol.size());
+            for (size_t q = 0; q < qrow.size(); ++q)
+                rpk[q] = qrow[q].shift | (qrow[q].other << 16) | (qrow[q].type << 25);
+            for (size_t q = 0; q < qcol.size(); ++q) cpk[q] = qcol[q].shift | (qcol[q].blk << 16);
+            st = upload(h->allocations, rpk.data(), rpk.size(), &p_rpk);
+            if (!st) st = upload(h->allocations, cpk.data(), cpk.size(), &p_cpk);
+        }
         if (!st) {
+            d.qrow_pk = p_rpk;
+            d.qcol_pk = p_cpk;
             d.qcol_rank = p_rk;
             d.qrow_ptr = p_rp;
             d.qrow = p_r;

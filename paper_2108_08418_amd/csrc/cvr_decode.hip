@@ -65,7 +65,7 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
     if (p->math == CVR_F64 && p->store != CVR_F64)
         return fail(CVR_EUNSUPPORTED, "decode: F64 math is implemented with F64 storage only");
     if (p->algo == CVR_SP && !(p->msg_clamp > 0.0f)) return fail(CVR_EINVAL, "decode: msg_clamp must be > 0");
-    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_PERSISTENT) return fail(CVR_EINVAL, "decode: bad schedule");
+    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_GRID) return fail(CVR_EINVAL, "decode: bad schedule");
     if (p->wg_threads != 0 && p->wg_threads != 512 && p->wg_threads != 1024)
         return fail(CVR_EINVAL, "decode: wg_threads must be 0, 512 or 1024");
     if (p->min_waves != 0 && p->min_waves != 8) return fail(CVR_EINVAL, "decode: min_waves must be 0 or 8");
@@ -120,25 +120,33 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
     a.n_types = batch->max_types;
     const hipStream_t s = hipStream_t(stream);
     const bool qc = batch->all_qc;
-    bool frames = false;
+    int mode = 0;
     if (params->schedule == CVR_SCHED_PERSISTENT) {
         if (!frames_fit(batch))
             return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the persistent schedule needs QC codes with <= 2048 "
                                           "circulants, <= 512 block rows/columns and Z <= 65535");
-        frames = true;
+        mode = 1;
+    } else if (params->schedule == CVR_SCHED_GRID) {
+        if (!packed_tables(batch))
+            return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the grid schedule needs QC codes with Z <= 65535 and "
+                                          "<= 512 block columns");
+        mode = 2;
     } else if (params->schedule == CVR_SCHED_AUTO) {
         // a workgroup per frame leaves compute units idle below one frame per
-        // CU; the per-pass kernels spread every frame's rows over the chip
-        frames = frames_fit(batch) && batch->F >= device_cus();
+        // CU; then the per-pass kernels spread every frame's rows over the chip
+        // (the grid schedule does the same in one launch, but its barriers,
+        // which write back and invalidate the per-XCD L2 caches, cost more
+        // than the launches they replace: 18.8 vs 6.0 ms for 16 frames of 2^16)
+        if (frames_fit(batch) && batch->F >= device_cus()) mode = 1;
     }
     int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
     const LaunchShape sh{params->wg_threads, params->min_waves, params->lds_cache_kb};
     const bool sp = params->algo == CVR_SP;
     if (params->math == CVR_F64)
-        return sp ? decode_f64_sp(batch, a, s, qc, frames, queue, sh) : decode_f64_nms(batch, a, s, qc, frames, queue, sh);
+        return sp ? decode_f64_sp(batch, a, s, qc, mode, queue, sh) : decode_f64_nms(batch, a, s, qc, mode, queue, sh);
     if (params->store == CVR_F32)
-        return sp ? decode_f32_sp(batch, a, s, qc, frames, queue, sh) : decode_f32_nms(batch, a, s, qc, frames, queue, sh);
-    return sp ? decode_f16_sp(batch, a, s, qc, frames, queue, sh) : decode_f16_nms(batch, a, s, qc, frames, queue, sh);
+        return sp ? decode_f32_sp(batch, a, s, qc, mode, queue, sh) : decode_f32_nms(batch, a, s, qc, mode, queue, sh);
+    return sp ? decode_f16_sp(batch, a, s, qc, mode, queue, sh) : decode_f16_nms(batch, a, s, qc, mode, queue, sh);
 }
 
 extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,

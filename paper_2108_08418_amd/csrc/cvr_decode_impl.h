@@ -165,6 +165,8 @@ struct DecArgs {
     int32_t T;
     int32_t early_stop;
     int32_t n_types;
+    int32_t* n_active;        // frames still iterating (grid schedule) or NULL
+    const int32_t* grid_err;  // set when a grid barrier gave up (grid schedule) or NULL
     float* ckpt;              // [ceil(T / ckpt_every)][ckpt_stride] c2v(t) at t = 0, K, 2K, ... or NULL
     int64_t ckpt_stride;
     int32_t ckpt_every;
@@ -278,6 +280,7 @@ __device__ __forceinline__ bool frame_stops(const DecArgs& a, const Tile& tl)
             a.iters[tl.frame] = a.t;
             a.ok[tl.frame] = uint8_t(u == 0);
             a.active[tl.frame] = 0;
+            if (a.n_active) atomicSub(a.n_active, 1);
         } else {
             a.unsat[2 * tl.frame + ((a.t + 1) & 1)] = 0;
         }
@@ -754,6 +757,189 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     }
 }
 
+// Per-pass kernels on the packed global tables (QC codes with Z <= 65535):
+// the tile's rows (variables) run the same exact-degree bodies as the
+// persistent decoder.
+template <typename M, typename S>
+__device__ __forceinline__ FrameCtx<M, S> pass_ctx(const DecArgs& a, const DevFrame& fr, const DevCode& cd)
+{
+    FrameCtx<M, S> c;
+    c.Lp = static_cast<M*>(a.post) + fr.vn_off;
+    c.Lc = static_cast<const M*>(a.llr) + fr.vn_off;
+    c.msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    c.s_row = cd.qrow_pk;
+    c.s_col = cd.qcol_pk;
+    c.s_cslot = nullptr;
+    c.s_post = nullptr;
+    c.s_w = a.weights ? a.weights + int64_t(a.t) * a.n_types : nullptr;
+    c.Z = cd.Z;
+    c.t = a.t;
+    c.T = a.T;
+    c.weighted = a.weights != nullptr;
+    c.alpha = a.alpha;
+    c.clamp = a.clamp;
+    return c;
+}
+
+// The check step of tile tl (every thread of the workgroup calls it).
+template <typename M, typename S, int ALGO, int MAXD, bool WU>
+__device__ __forceinline__ void check_tile(const DecArgs& a, const Tile& tl)
+{
+    if (!a.active[tl.frame]) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    const int i = tl.a;
+    const int k = tl.b + int(threadIdx.x);
+    const FrameCtx<M, S> c = pass_ctx<M, S>(a, fr, cd);
+    const int q0 = uni<WU>(cd.qrow_ptr[i]);
+    const int d = uni<WU>(cd.qrow_ptr[i + 1]) - q0;
+    int bad = 0;
+    if (int(threadIdx.x) < count) {
+        const int sraw = a.syn ? int(a.syn[fr.chk_off + int64_t(i) * cd.Z + k]) : 0;
+        if constexpr (WU) {
+            switch (d) {
+            case 1: bad = check_row<M, S, ALGO, 1, WU, false>(c, q0, k, sraw); break;
+            case 2: bad = check_row<M, S, ALGO, 2, WU, false>(c, q0, k, sraw); break;
+            case 3: bad = check_row<M, S, ALGO, 3, WU, false>(c, q0, k, sraw); break;
+            case 4: bad = check_row<M, S, ALGO, 4, WU, false>(c, q0, k, sraw); break;
+            case 5: bad = check_row<M, S, ALGO, 5, WU, false>(c, q0, k, sraw); break;
+            case 6: bad = check_row<M, S, ALGO, 6, WU, false>(c, q0, k, sraw); break;
+            case 7: bad = check_row<M, S, ALGO, 7, WU, false>(c, q0, k, sraw); break;
+            case 8: bad = check_row<M, S, ALGO, 8, WU, false>(c, q0, k, sraw); break;
+            default:
+                if constexpr (MAXD > 8) bad = check_row_any<M, S, ALGO, MAXD, WU, false>(c, q0, d, k, sraw);
+                break;
+            }
+        } else {
+            bad = check_row_any<M, S, ALGO, MAXD, WU, false>(c, q0, d, k, sraw);
+        }
+    }
+    add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
+}
+
+// The variable step of tile tl, after the frame's stop decision.
+template <typename M, typename S, bool WU>
+__device__ __forceinline__ void var_tile(const DecArgs& a, const Tile& tl)
+{
+    if (!a.active[tl.frame]) return;
+    if (frame_stops(a, tl)) return;
+    const DevFrame fr = a.frames[tl.frame];
+    const DevCode& cd = a.codes[fr.code];
+    const int count = tl.count & 0x7fffffff;
+    if (int(threadIdx.x) >= count) return;
+    const int j = tl.a;
+    const int u = tl.b + int(threadIdx.x);
+    const FrameCtx<M, S> c = pass_ctx<M, S>(a, fr, cd);
+    const int qa = uni<WU>(cd.qcol_ptr[j]);
+    const int dv = uni<WU>(cd.qcol_ptr[j + 1]) - qa;
+    const int v = j * cd.Z + u;
+    M acc = at(c.Lc, v);
+    if constexpr (WU) {
+        switch (dv) {
+        case 1: acc = var_sum<M, S, 1, WU>(c, qa, u, acc); break;
+        case 2: acc = var_sum<M, S, 2, WU>(c, qa, u, acc); break;
+        case 3: acc = var_sum<M, S, 3, WU>(c, qa, u, acc); break;
+        case 4: acc = var_sum<M, S, 4, WU>(c, qa, u, acc); break;
+        case 5: acc = var_sum<M, S, 5, WU>(c, qa, u, acc); break;
+        case 6: acc = var_sum<M, S, 6, WU>(c, qa, u, acc); break;
+        case 7: acc = var_sum<M, S, 7, WU>(c, qa, u, acc); break;
+        case 8: acc = var_sum<M, S, 8, WU>(c, qa, u, acc); break;
+        default: acc = var_sum_any<M, S, WU>(c, qa, dv, u, acc); break;
+        }
+    } else {
+        acc = var_sum_any<M, S, WU>(c, qa, dv, u, acc);
+    }
+    at(c.Lp, v) = acc;
+    if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
+}
+
+template <typename M, typename S, int ALGO, int MAXD, bool WU>
+__global__ __launch_bounds__(kTile) void k_check_qc_pk(DecArgs a)
+{
+    check_tile<M, S, ALGO, MAXD, WU>(a, a.tiles[blockIdx.x]);
+}
+
+template <typename M, typename S, bool WU>
+__global__ __launch_bounds__(kTile) void k_var_qc_pk(DecArgs a)
+{
+    var_tile<M, S, WU>(a, a.tiles[blockIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// grid schedule: all iterations of all frames in one launch whose workgroups
+// are all resident; the passes are separated by a grid-wide barrier
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    const Tile* cn_tiles;
+    const Tile* vn_tiles;
+    int64_t n_cn, n_vn;
+    uint32_t* bar;            // [0] arrivals, [1] generation; zero at launch
+    int32_t* err;             // set when a barrier wait gave up
+};
+
+// Grid-wide barrier for a launch whose workgroups are all resident (the host
+// sizes the grid to kGridPerCu workgroups per CU, and the kernel's launch
+// bounds guarantee that many fit).  The last workgroup to arrive resets the
+// count and advances the generation; the others wait for the generation to
+// move.  A wait is bounded in wall-clock time (0.2 s); after a barrier has
+// given up (reported through err) no later barrier waits, so the launch
+// always ends, and the frames are then reported as not decoded.  The fences
+// make every global write before the barrier visible to every workgroup after
+// it (they write back and invalidate the per-XCD L2 caches).
+constexpr int kGridPerCu = 4;
+
+__device__ __forceinline__ void grid_sync(const GridArgs& g, uint32_t& gen)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t arrived = atomicAdd(&g.bar[0], 1u);
+        if (arrived == gridDim.x - 1) {
+            atomicExch(&g.bar[0], 0u);
+            __threadfence();
+            atomicAdd(&g.bar[1], 1u);
+        } else if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&g.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > 20000000ull) {       // 0.2 s of the 100 MHz counter
+                    atomicExch(g.err, 1);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        ++gen;
+    }
+    __syncthreads();
+}
+
+template <typename M, typename S, int ALGO, int MAXD, bool WU>
+__global__ __launch_bounds__(kTile, kGridPerCu) void k_grid_qc(DecArgs a, GridArgs g)
+{
+    uint32_t gen = 0;
+    for (int t = 0;; ++t) {
+        a.t = t;
+        for (int64_t ti = blockIdx.x; ti < g.n_cn; ti += gridDim.x) check_tile<M, S, ALGO, MAXD, WU>(a, g.cn_tiles[ti]);
+        grid_sync(g, gen);
+        for (int64_t ti = blockIdx.x; ti < g.n_vn; ti += gridDim.x) var_tile<M, S, WU>(a, g.vn_tiles[ti]);
+        grid_sync(g, gen);
+        const int left = __hip_atomic_load(a.n_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == 0 || t >= a.T) break;
+    }
+}
+
+__global__ __launch_bounds__(64) static void k_grid_init(uint32_t* bar, int32_t* n_active, int32_t F)
+{
+    if (threadIdx.x == 0) {
+        bar[0] = 0;
+        bar[1] = 0;
+        bar[2] = 0;     // err
+        *n_active = F;
+    }
+}
+
 // Loads the LDS tables of code cd (see LdsMap) and assigns the posterior cache
 // slots to its highest-degree block columns; every thread of the workgroup
 // calls it, and it ends with a barrier.
@@ -841,6 +1027,7 @@ __global__ __launch_bounds__(kTile) void k_dec_final(DecArgs a)
     const Tile tl = a.tiles[blockIdx.x];
     const DevFrame fr = a.frames[tl.frame];
     const int count = tl.count & 0x7fffffff;
+    if (a.grid_err && *a.grid_err && (tl.count & kFirstTile) && threadIdx.x == 0) a.ok[tl.frame] = 0;
     if (int(threadIdx.x) >= count) return;
     const int64_t v = fr.vn_off + tl.a + int(threadIdx.x);
     a.bits[v] = static_cast<const M*>(a.post)[v] < M(0) ? 1 : 0;
@@ -855,10 +1042,22 @@ __global__ __launch_bounds__(256) static void k_zero_i32(int32_t* p, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Every code of the batch has Z % 64 == 0: each wavefront stays inside one
+// block row / column, and the wave-uniform kernel applies.
+static inline bool wave_uniform(const cvr_batch_s* b)
+{
+    for (const cvr_code_t c : b->codes)
+        if (c->dev.Z % 64) return false;
+    return true;
+}
+
 template <typename M, typename S, int ALGO, int MAXD>
 static cvr_status run_decode(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc)
 {
     const int64_t nvt = b->n_vn_tiles;
+    bool packed = qc;
+    for (const cvr_code_t c : b->codes) packed = packed && c->dev.qrow_pk && c->dev.qcol_pk;
+    const bool wu = packed && wave_uniform(b);
     a.tiles = b->d_vn_tiles;
     {
         ProfScope prof(CVR_PROF_DEC_SETUP, s);
@@ -867,7 +1066,20 @@ static cvr_status run_decode(const cvr_batch_s* b, DecArgs a, hipStream_t s, boo
     if (cvr_status st = check_launch("decode init")) return st;
     for (int t = 0; t <= a.T; ++t) {
         a.t = t;
-        if (qc) {
+        if (qc && packed) {
+            a.tiles = b->d_qcn_tiles;
+            {
+                ProfScope prof(CVR_PROF_CHECK, s);
+                if (wu) hipLaunchKernelGGL((k_check_qc_pk<M, S, ALGO, MAXD, true>), dim3(b->n_qcn_tiles), dim3(kTile), 0, s, a);
+                else hipLaunchKernelGGL((k_check_qc_pk<M, S, ALGO, MAXD, false>), dim3(b->n_qcn_tiles), dim3(kTile), 0, s, a);
+            }
+            a.tiles = b->d_qvn_tiles;
+            {
+                ProfScope prof(CVR_PROF_VAR, s);
+                if (wu) hipLaunchKernelGGL((k_var_qc_pk<M, S, true>), dim3(b->n_qvn_tiles), dim3(kTile), 0, s, a);
+                else hipLaunchKernelGGL((k_var_qc_pk<M, S, false>), dim3(b->n_qvn_tiles), dim3(kTile), 0, s, a);
+            }
+        } else if (qc) {
             a.tiles = b->d_qcn_tiles;
             {
                 ProfScope prof(CVR_PROF_CHECK, s);
@@ -979,14 +1191,6 @@ static cvr_status launch_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue,
     return check_launch("decode (persistent)");
 }
 
-// Every code of the batch has Z % 64 == 0: each wavefront stays inside one
-// block row / column, and the wave-uniform kernel applies.
-static inline bool wave_uniform(const cvr_batch_s* b)
-{
-    for (const cvr_code_t c : b->codes)
-        if (c->dev.Z % 64) return false;
-    return true;
-}
 
 template <typename M, typename S, int ALGO, int MAXD, bool CACHE>
 static cvr_status run_shape(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, const LaunchShape& sh)
@@ -1016,14 +1220,60 @@ static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hi
     }
 }
 
+// Grid schedule (QC codes with packed tables): set-up, one launch of resident
+// workgroups for all iterations, output.
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_grid(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* qbase)
+{
+    uint32_t* bar = reinterpret_cast<uint32_t*>(qbase + 4);
+    a.n_active = qbase + 8;
+    const int64_t nvt = b->n_vn_tiles;
+    a.tiles = b->d_vn_tiles;
+    {
+        ProfScope prof(CVR_PROF_DEC_SETUP, s);
+        hipLaunchKernelGGL(k_dec_init<M>, dim3(nvt), dim3(kTile), 0, s, a);
+        hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, bar, a.n_active, b->F);
+    }
+    if (cvr_status st = check_launch("decode init")) return st;
+    GridArgs g{b->d_qcn_tiles, b->d_qvn_tiles, b->n_qcn_tiles, b->n_qvn_tiles, bar,
+               reinterpret_cast<int32_t*>(bar + 2)};
+    const bool wu = wave_uniform(b);
+    auto kern = wu ? k_grid_qc<M, S, ALGO, MAXD, true> : k_grid_qc<M, S, ALGO, MAXD, false>;
+    // every workgroup must be resident for the grid barrier: kGridPerCu per CU,
+    // which the kernel's launch bounds guarantee (the occupancy query can
+    // overstate residency: it does not see the scalar-register limit)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTile, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    per_cu = std::min(per_cu, kGridPerCu);
+    const int grid = int(std::min<int64_t>(std::max(b->n_qcn_tiles, b->n_qvn_tiles), int64_t(device_cus()) * per_cu));
+    {
+        ProfScope prof(CVR_PROF_FRAMES, s);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kTile), 0, s, a, g);
+    }
+    if (cvr_status st = check_launch("decode (grid)")) return st;
+    a.tiles = b->d_vn_tiles;
+    a.grid_err = g.err;
+    {
+        ProfScope prof(CVR_PROF_DEC_SETUP, s);
+        hipLaunchKernelGGL(k_dec_final<M>, dim3(nvt), dim3(kTile), 0, s, a);
+    }
+    return check_launch("decode final");
+}
+
+// mode: 0 per-pass launches, 1 persistent frame-per-workgroup, 2 grid
 template <typename M, typename S, int ALGO>
-static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue,
+static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, int mode, int32_t* queue,
                                const LaunchShape& sh)
 {
-    if (frames) {
+    if (mode == 1) {
         if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, sh);
         if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, sh);
         return run_frames<M, S, ALGO, 32>(b, a, queue, s, sh);
+    }
+    if (mode == 2) {
+        if (b->max_row_deg <= 8) return run_grid<M, S, ALGO, 8>(b, a, s, queue);
+        if (b->max_row_deg <= 16) return run_grid<M, S, ALGO, 16>(b, a, s, queue);
+        return run_grid<M, S, ALGO, 32>(b, a, s, queue);
     }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
@@ -1054,10 +1304,19 @@ static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
     off = align256(off + size_t(b->F) * 4);
     w.unsat = off;
     off = align256(off + size_t(b->F) * 8);
-    w.queue = off;
-    off = align256(off + 4);
+    w.queue = off;              // persistent queue [0]; grid barrier [4..6]; active frames [8]
+    off = align256(off + 64);
     w.total = off;
     return w;
+}
+
+// The grid schedule needs packed tables for every code of the batch.
+static inline bool packed_tables(const cvr_batch_s* b)
+{
+    if (!b->all_qc) return false;
+    for (const cvr_code_t c : b->codes)
+        if (!c->dev.qrow_pk || !c->dev.qcol_pk) return false;
+    return true;
 }
 
 // The persistent path needs a quasi-cyclic batch whose protograph tables fit in LDS.
@@ -1073,7 +1332,7 @@ static inline bool frames_fit(const cvr_batch_s* b)
 
 // One instantiation per (math, store, rule); each lives in its own translation unit.
 #define CVR_DECL_DISPATCH(NAME)                                                                      \
-    cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, bool frames, int32_t* queue, \
+    cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, int mode, int32_t* queue, \
                     const LaunchShape& sh)
 CVR_DECL_DISPATCH(decode_f64_sp);
 CVR_DECL_DISPATCH(decode_f64_nms);

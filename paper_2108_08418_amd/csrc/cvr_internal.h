@@ -75,6 +75,10 @@ struct DevCode {
     const int32_t* qcol_ptr;
     const QcBlock* qcol;
     const int32_t* qcol_rank;   // block columns by degree, descending (ties: lower index first)
+    // one word per table entry (NULL unless Z <= 65535 and nb <= 512):
+    // row: shift | block column << 16 | type << 25; column: shift | block id << 16
+    const int32_t* qrow_pk;
+    const int32_t* qcol_pk;
 };
 
 struct DevFrame {

@@ -130,6 +130,7 @@ def test_layouts_and_schedules_are_bit_identical():
                                         (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 0),
                                         (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 150),
                                         (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0, 0),
+                                        (api.Code.from_qc(qc), api.SCHED_GRID, 0, 0, 0),
                                         (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0)):
             p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, min_waves=mw,
                            lds_cache_kb=lk, **base)
@@ -146,7 +147,7 @@ def test_persistent_schedule_rejects_explicit_codes():
         _decode_gpu(api.Code.from_csr(csr), 2, np.zeros((2, 1024)), None, p)
 
 
-@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES])
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GRID])
 @pytest.mark.parametrize("store", [api.F32, api.F16])
 def test_nms_bit_exact_against_binary32_oracle(store, sched):
     """Min-sum uses only +, -, x, min and the binary16 rounding: with the oracle
@@ -199,6 +200,8 @@ def test_nms_uniform_weights_equal_alpha():
     ((8192, 16384, 8192), api.SCHED_PERSISTENT, 20),      # a few cached columns, a different number per code
     ((8192, 16384, 8192), api.SCHED_PERSISTENT, -1),
     ((4096, 8192, 4096), api.SCHED_PASSES, 0),
+    ((4096, 8192, 4096), api.SCHED_GRID, 0),             # lane-varying block rows
+    ((8192, 16384, 8192), api.SCHED_GRID, 0),            # wave-uniform
 ])
 def test_ragged_batch_mixed_codes_and_gaps(sizes, sched, lds_kb):
     """Frames of different codes and lengths at scattered offsets: each frame
@@ -239,7 +242,7 @@ def test_ragged_batch_mixed_codes_and_gaps(sizes, sched, lds_kb):
         assert int(out["iters"][i]) == int(solo["iters"][0])
 
 
-@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES])
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GRID])
 def test_failure_injection_and_edge_cases(sched):
     print(f"[decode edge cases schedule={sched}]", flush=True)
     qc = inputs.lambda_half_rate_spec(4096)
@@ -287,7 +290,7 @@ def test_repeat_runs_are_bit_identical():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES])
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GRID])
 def test_graph_capture_replays_match_eager(sched):
     """The decode (queue reset + persistent kernel, or the per-pass launches;
     no memset) captured in a HIP graph: every replay, with unrelated eager work
