@@ -4,6 +4,6 @@
 namespace cvr {
 CVR_DECL_DISPATCH(decode_f16_nms)
 {
-    return dispatch_deg<float, __half, CVR_NMS>(b, a, s, qc, mode, queue, sh);
+    return dispatch_deg<float, __half, CVR_NMS>(b, a, s, qc, mode, queue, gridws, sh);
 }
 }  // namespace cvr

@@ -4,6 +4,6 @@
 namespace cvr {
 CVR_DECL_DISPATCH(decode_f64_sp)
 {
-    return dispatch_deg<double, double, CVR_SP>(b, a, s, qc, mode, queue, sh);
+    return dispatch_deg<double, double, CVR_SP>(b, a, s, qc, mode, queue, gridws, sh);
 }
 }  // namespace cvr

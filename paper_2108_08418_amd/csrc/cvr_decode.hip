@@ -140,13 +140,14 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
         if (frames_fit(batch) && batch->F >= device_cus()) mode = 1;
     }
     int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
+    int32_t* gridws = reinterpret_cast<int32_t*>(ws + w.grid);
     const LaunchShape sh{params->wg_threads, params->min_waves, params->lds_cache_kb};
     const bool sp = params->algo == CVR_SP;
     if (params->math == CVR_F64)
-        return sp ? decode_f64_sp(batch, a, s, qc, mode, queue, sh) : decode_f64_nms(batch, a, s, qc, mode, queue, sh);
+        return sp ? decode_f64_sp(batch, a, s, qc, mode, queue, gridws, sh) : decode_f64_nms(batch, a, s, qc, mode, queue, gridws, sh);
     if (params->store == CVR_F32)
-        return sp ? decode_f32_sp(batch, a, s, qc, mode, queue, sh) : decode_f32_nms(batch, a, s, qc, mode, queue, sh);
-    return sp ? decode_f16_sp(batch, a, s, qc, mode, queue, sh) : decode_f16_nms(batch, a, s, qc, mode, queue, sh);
+        return sp ? decode_f32_sp(batch, a, s, qc, mode, queue, gridws, sh) : decode_f32_nms(batch, a, s, qc, mode, queue, gridws, sh);
+    return sp ? decode_f16_sp(batch, a, s, qc, mode, queue, gridws, sh) : decode_f16_nms(batch, a, s, qc, mode, queue, gridws, sh);
 }
 
 extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,

@@ -165,7 +165,6 @@ struct DecArgs {
     int32_t T;
     int32_t early_stop;
     int32_t n_types;
-    int32_t* n_active;        // frames still iterating (grid schedule) or NULL
     const int32_t* grid_err;  // set when a grid barrier gave up (grid schedule) or NULL
     float* ckpt;              // [ceil(T / ckpt_every)][ckpt_stride] c2v(t) at t = 0, K, 2K, ... or NULL
     int64_t ckpt_stride;
@@ -205,6 +204,25 @@ template <typename T>
 __device__ __forceinline__ const T& at(const T* base, uint32_t idx)
 {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * uint32_t(sizeof(T)));
+}
+
+// A load of data that other workgroups of the same launch write: with COH a
+// device-scope load, which skips this CU's L1 (the XCD's L2 holds the current
+// value); otherwise a plain load.
+template <bool COH, typename T>
+__device__ __forceinline__ T ldc(const T* p)
+{
+    if constexpr (!COH) {
+        return *p;
+    } else if constexpr (sizeof(T) == 2) {
+        const unsigned short v =
+            __hip_atomic_load(reinterpret_cast<const unsigned short*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        T r;
+        __builtin_memcpy(&r, &v, 2);
+        return r;
+    } else {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Every pass below is written in phases: indices / protograph entries, then all
@@ -273,16 +291,16 @@ __global__ __launch_bounds__(kTile) void k_check_generic(DecArgs a)
 // Ends finished frames; returns true when this tile's frame must not update.
 __device__ __forceinline__ bool frame_stops(const DecArgs& a, const Tile& tl)
 {
-    const int u = a.unsat[2 * tl.frame + (a.t & 1)];
+    // the counts are updated by atomics: read and reset them with atomics too
+    const int u = __hip_atomic_load(&a.unsat[2 * tl.frame + (a.t & 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool stop = (a.early_stop && u == 0) || a.t >= a.T;
     if ((tl.count & kFirstTile) && threadIdx.x == 0) {
         if (stop) {
             a.iters[tl.frame] = a.t;
             a.ok[tl.frame] = uint8_t(u == 0);
             a.active[tl.frame] = 0;
-            if (a.n_active) atomicSub(a.n_active, 1);
         } else {
-            a.unsat[2 * tl.frame + ((a.t + 1) & 1)] = 0;
+            __hip_atomic_store(&a.unsat[2 * tl.frame + ((a.t + 1) & 1)], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     return stop;
@@ -486,7 +504,7 @@ struct FrameCtx {
 // edges (D and the entries wave-uniform): the D posteriors and, for t > 0, the
 // D stored messages are loaded before any arithmetic; the code is straight-line.
 // Returns 1 when the row's syndrome test fails on Lpost(t).
-template <typename M, typename S, int ALGO, int D, bool WU, bool CACHE>
+template <typename M, typename S, int ALGO, int D, bool WU, bool CACHE, bool COH = false>
 __device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k, int sraw)
 {
     int32_t e[D];
@@ -500,11 +518,11 @@ __device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k,
         uu = uu >= c.Z ? uu - c.Z : uu;
         const int idx = ((e[q] >> 16) & 0x1ff) * c.Z + uu;
         if (CACHE && (e[q] & kCached)) lr[q] = lds_read(c.s_post + idx);
-        else lr[q] = at(c.Lp, uint32_t(idx));
+        else lr[q] = ldc<COH>(&at(c.Lp, uint32_t(idx)));
     }
     if (c.t > 0) {
 #pragma unroll
-        for (int q = 0; q < D; ++q) mr[q] = at(c.msg, uint32_t((q0 + q) * c.Z + k));
+        for (int q = 0; q < D; ++q) mr[q] = ldc<COH>(&at(c.msg, uint32_t((q0 + q) * c.Z + k)));
     } else {
 #pragma unroll
         for (int q = 0; q < D; ++q) mr[q] = S(0);      // c2v(0) = 0
@@ -527,7 +545,7 @@ __device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k,
 }
 
 // The same for any degree d <= MAXD (masked; entries may differ across lanes).
-template <typename M, typename S, int ALGO, int MAXD, bool WU, bool CACHE>
+template <typename M, typename S, int ALGO, int MAXD, bool WU, bool CACHE, bool COH = false>
 __device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, int d, int k, int sraw)
 {
     int32_t e[MAXD];
@@ -545,8 +563,8 @@ __device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, in
             uu = uu >= c.Z ? uu - c.Z : uu;
             const int idx = ((eq >> 16) & 0x1ff) * c.Z + uu;
             if (CACHE && (eq & kCached)) lr[q] = lds_read(c.s_post + idx);
-            else lr[q] = at(c.Lp, uint32_t(idx));
-            if (c.t > 0) mr[q] = at(c.msg, uint32_t((q0 + q) * c.Z + k));
+            else lr[q] = ldc<COH>(&at(c.Lp, uint32_t(idx)));
+            if (c.t > 0) mr[q] = ldc<COH>(&at(c.msg, uint32_t((q0 + q) * c.Z + k)));
         }
     }
     M x[MAXD];
@@ -573,7 +591,7 @@ __device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, in
 
 // Lch + the D messages of variable u of the block column whose table entries
 // start at qa, summed in table order (block rows ascending); D wave-uniform.
-template <typename M, typename S, int D, bool WU>
+template <typename M, typename S, int D, bool WU, bool COH = false>
 __device__ __forceinline__ M var_sum(const FrameCtx<M, S>& c, int qa, int u, M acc)
 {
     int32_t e[D];
@@ -584,7 +602,7 @@ __device__ __forceinline__ M var_sum(const FrameCtx<M, S>& c, int qa, int u, M a
     for (int q = 0; q < D; ++q) {
         int k = u - (e[q] & 0xffff);
         k = k < 0 ? k + c.Z : k;
-        m[q] = at(c.msg, uint32_t((e[q] >> 16) * c.Z + k));
+        m[q] = ldc<COH>(&at(c.msg, uint32_t((e[q] >> 16) * c.Z + k)));
     }
 #pragma unroll
     for (int q = 0; q < D; ++q) acc += M(StoreT<S>::get(m[q]));
@@ -592,7 +610,7 @@ __device__ __forceinline__ M var_sum(const FrameCtx<M, S>& c, int qa, int u, M a
 }
 
 // The same for any degree (8 loads at a time, masked).
-template <typename M, typename S, bool WU>
+template <typename M, typename S, bool WU, bool COH = false>
 __device__ __forceinline__ M var_sum_any(const FrameCtx<M, S>& c, int qa, int dv, int u, M acc)
 {
     for (int q8 = 0; q8 < dv; q8 += 8) {
@@ -607,7 +625,7 @@ __device__ __forceinline__ M var_sum_any(const FrameCtx<M, S>& c, int qa, int dv
                 const int eq = uni<WU>(e[q]);
                 int k = u - (eq & 0xffff);
                 k = k < 0 ? k + c.Z : k;
-                m[q] = at(c.msg, uint32_t((eq >> 16) * c.Z + k));
+                m[q] = ldc<COH>(&at(c.msg, uint32_t((eq >> 16) * c.Z + k)));
             }
         }
 #pragma unroll
@@ -782,10 +800,10 @@ __device__ __forceinline__ FrameCtx<M, S> pass_ctx(const DecArgs& a, const DevFr
 }
 
 // The check step of tile tl (every thread of the workgroup calls it).
-template <typename M, typename S, int ALGO, int MAXD, bool WU>
+template <typename M, typename S, int ALGO, int MAXD, bool WU, bool COH = false>
 __device__ __forceinline__ void check_tile(const DecArgs& a, const Tile& tl)
 {
-    if (!a.active[tl.frame]) return;
+    if (!ldc<COH>(&a.active[tl.frame])) return;
     const DevFrame fr = a.frames[tl.frame];
     const DevCode& cd = a.codes[fr.code];
     const int count = tl.count & 0x7fffffff;
@@ -799,30 +817,30 @@ __device__ __forceinline__ void check_tile(const DecArgs& a, const Tile& tl)
         const int sraw = a.syn ? int(a.syn[fr.chk_off + int64_t(i) * cd.Z + k]) : 0;
         if constexpr (WU) {
             switch (d) {
-            case 1: bad = check_row<M, S, ALGO, 1, WU, false>(c, q0, k, sraw); break;
-            case 2: bad = check_row<M, S, ALGO, 2, WU, false>(c, q0, k, sraw); break;
-            case 3: bad = check_row<M, S, ALGO, 3, WU, false>(c, q0, k, sraw); break;
-            case 4: bad = check_row<M, S, ALGO, 4, WU, false>(c, q0, k, sraw); break;
-            case 5: bad = check_row<M, S, ALGO, 5, WU, false>(c, q0, k, sraw); break;
-            case 6: bad = check_row<M, S, ALGO, 6, WU, false>(c, q0, k, sraw); break;
-            case 7: bad = check_row<M, S, ALGO, 7, WU, false>(c, q0, k, sraw); break;
-            case 8: bad = check_row<M, S, ALGO, 8, WU, false>(c, q0, k, sraw); break;
+            case 1: bad = check_row<M, S, ALGO, 1, WU, false, COH>(c, q0, k, sraw); break;
+            case 2: bad = check_row<M, S, ALGO, 2, WU, false, COH>(c, q0, k, sraw); break;
+            case 3: bad = check_row<M, S, ALGO, 3, WU, false, COH>(c, q0, k, sraw); break;
+            case 4: bad = check_row<M, S, ALGO, 4, WU, false, COH>(c, q0, k, sraw); break;
+            case 5: bad = check_row<M, S, ALGO, 5, WU, false, COH>(c, q0, k, sraw); break;
+            case 6: bad = check_row<M, S, ALGO, 6, WU, false, COH>(c, q0, k, sraw); break;
+            case 7: bad = check_row<M, S, ALGO, 7, WU, false, COH>(c, q0, k, sraw); break;
+            case 8: bad = check_row<M, S, ALGO, 8, WU, false, COH>(c, q0, k, sraw); break;
             default:
-                if constexpr (MAXD > 8) bad = check_row_any<M, S, ALGO, MAXD, WU, false>(c, q0, d, k, sraw);
+                if constexpr (MAXD > 8) bad = check_row_any<M, S, ALGO, MAXD, WU, false, COH>(c, q0, d, k, sraw);
                 break;
             }
         } else {
-            bad = check_row_any<M, S, ALGO, MAXD, WU, false>(c, q0, d, k, sraw);
+            bad = check_row_any<M, S, ALGO, MAXD, WU, false, COH>(c, q0, d, k, sraw);
         }
     }
     add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
 }
 
 // The variable step of tile tl, after the frame's stop decision.
-template <typename M, typename S, bool WU>
+template <typename M, typename S, bool WU, bool COH = false>
 __device__ __forceinline__ void var_tile(const DecArgs& a, const Tile& tl)
 {
-    if (!a.active[tl.frame]) return;
+    if (!ldc<COH>(&a.active[tl.frame])) return;
     if (frame_stops(a, tl)) return;
     const DevFrame fr = a.frames[tl.frame];
     const DevCode& cd = a.codes[fr.code];
@@ -837,18 +855,18 @@ __device__ __forceinline__ void var_tile(const DecArgs& a, const Tile& tl)
     M acc = at(c.Lc, v);
     if constexpr (WU) {
         switch (dv) {
-        case 1: acc = var_sum<M, S, 1, WU>(c, qa, u, acc); break;
-        case 2: acc = var_sum<M, S, 2, WU>(c, qa, u, acc); break;
-        case 3: acc = var_sum<M, S, 3, WU>(c, qa, u, acc); break;
-        case 4: acc = var_sum<M, S, 4, WU>(c, qa, u, acc); break;
-        case 5: acc = var_sum<M, S, 5, WU>(c, qa, u, acc); break;
-        case 6: acc = var_sum<M, S, 6, WU>(c, qa, u, acc); break;
-        case 7: acc = var_sum<M, S, 7, WU>(c, qa, u, acc); break;
-        case 8: acc = var_sum<M, S, 8, WU>(c, qa, u, acc); break;
-        default: acc = var_sum_any<M, S, WU>(c, qa, dv, u, acc); break;
+        case 1: acc = var_sum<M, S, 1, WU, COH>(c, qa, u, acc); break;
+        case 2: acc = var_sum<M, S, 2, WU, COH>(c, qa, u, acc); break;
+        case 3: acc = var_sum<M, S, 3, WU, COH>(c, qa, u, acc); break;
+        case 4: acc = var_sum<M, S, 4, WU, COH>(c, qa, u, acc); break;
+        case 5: acc = var_sum<M, S, 5, WU, COH>(c, qa, u, acc); break;
+        case 6: acc = var_sum<M, S, 6, WU, COH>(c, qa, u, acc); break;
+        case 7: acc = var_sum<M, S, 7, WU, COH>(c, qa, u, acc); break;
+        case 8: acc = var_sum<M, S, 8, WU, COH>(c, qa, u, acc); break;
+        default: acc = var_sum_any<M, S, WU, COH>(c, qa, dv, u, acc); break;
         }
     } else {
-        acc = var_sum_any<M, S, WU>(c, qa, dv, u, acc);
+        acc = var_sum_any<M, S, WU, COH>(c, qa, dv, u, acc);
     }
     at(c.Lp, v) = acc;
     if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
@@ -867,49 +885,54 @@ __global__ __launch_bounds__(kTile) void k_var_qc_pk(DecArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// grid schedule: all iterations of all frames in one launch whose workgroups
-// are all resident; the passes are separated by a grid-wide barrier
+// grid schedule: all iterations of all frames in one launch.  Each frame is
+// worked on by a group of G resident workgroups on one XCD, so the group
+// shares one L2: its barrier needs only atomics, and the loads of data that
+// other members write read that L2 directly; no cache is written back or
+// invalidated.  A workgroup learns its XCD from the XCC_ID register and takes
+// the next place on that XCD (frames f with f % 8 == XCD, G places each), so
+// nothing depends on how the dispatcher numbers workgroups across XCDs.
 // ---------------------------------------------------------------------------
+constexpr int kGridPerCu = 4;      // workgroups per CU of the launch (guaranteed by its launch bounds)
+constexpr int kXcds = 8;
+
 struct GridArgs {
     const Tile* cn_tiles;
     const Tile* vn_tiles;
-    int64_t n_cn, n_vn;
-    uint32_t* bar;            // [0] arrivals, [1] generation; zero at launch
-    int32_t* err;             // set when a barrier wait gave up
+    const int32_t* cn_off;    // [F + 1] each frame's row tiles
+    const int32_t* vn_off;    // [F + 1] each frame's variable tiles
+    uint32_t* bar;            // [F][2] arrivals, generation; zero at launch
+    uint32_t* ticket;         // [kXcds] places taken on each XCD; zero at launch
+    int32_t* err;             // 1: a barrier wait gave up; 2: an XCC_ID outside 0..kXcds-1
+    int32_t F, G;
 };
 
-// Grid-wide barrier for a launch whose workgroups are all resident (the host
-// sizes the grid to kGridPerCu workgroups per CU, and the kernel's launch
-// bounds guarantee that many fit).  The last workgroup to arrive resets the
-// count and advances the generation; the others wait for the generation to
-// move.  A wait is bounded in wall-clock time (0.2 s); after a barrier has
-// given up (reported through err) no later barrier waits, so the launch
-// always ends, and the frames are then reported as not decoded.  The fences
-// make every global write before the barrier visible to every workgroup after
-// it (they write back and invalidate the per-XCD L2 caches).
-constexpr int kGridPerCu = 4;
-
-__device__ __forceinline__ void grid_sync(const GridArgs& g, uint32_t& gen)
+// Barrier of the G workgroups of frame f.  The last to arrive resets the count
+// and advances the generation; the others wait for it, bounded in wall-clock
+// time (0.2 s; after a wait has given up no later one waits, so the launch
+// always ends and the frames are reported as not decoded).  Stores before the
+// barrier have reached the XCD's L2 (the workgroup barrier waits for them),
+// and every load of data that other workgroups write is a device-scope load
+// that reads the L2 (ldc), so no cache has to be written back or invalidated.
+__device__ __forceinline__ void group_sync(const GridArgs& g, int f, uint32_t& gen)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t arrived = atomicAdd(&g.bar[0], 1u);
-        if (arrived == gridDim.x - 1) {
-            atomicExch(&g.bar[0], 0u);
-            __threadfence();
-            atomicAdd(&g.bar[1], 1u);
+        uint32_t* bf = g.bar + 2 * f;
+        const uint32_t arrived = atomicAdd(&bf[0], 1u);
+        if (arrived == uint32_t(g.G) - 1) {
+            atomicExch(&bf[0], 0u);
+            atomicAdd(&bf[1], 1u);
         } else if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&g.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&bf[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > 20000000ull) {       // 0.2 s of the 100 MHz counter
                     atomicExch(g.err, 1);
                     break;
                 }
             }
         }
-        __threadfence();
         ++gen;
     }
     __syncthreads();
@@ -918,26 +941,41 @@ __device__ __forceinline__ void grid_sync(const GridArgs& g, uint32_t& gen)
 template <typename M, typename S, int ALGO, int MAXD, bool WU>
 __global__ __launch_bounds__(kTile, kGridPerCu) void k_grid_qc(DecArgs a, GridArgs g)
 {
+    __shared__ int s_place[2];
+    if (threadIdx.x == 0) {
+        uint32_t xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        int xcd = int(xcc & 0xf);
+        if (xcd >= kXcds) {
+            atomicExch(g.err, 2);
+            xcd = 0;
+        }
+        s_place[0] = xcd;
+        s_place[1] = int(atomicAdd(&g.ticket[xcd], 1u));
+    }
+    __syncthreads();
+    const int xcd = s_place[0], slot = s_place[1];
+    const int member = slot % g.G;
+    const int f = (slot / g.G) * kXcds + xcd;
+    if (f >= g.F) return;                               // a surplus place: no frame
+    const int c0 = g.cn_off[f], c1 = g.cn_off[f + 1];
+    const int v0 = g.vn_off[f], v1 = g.vn_off[f + 1];
     uint32_t gen = 0;
     for (int t = 0;; ++t) {
         a.t = t;
-        for (int64_t ti = blockIdx.x; ti < g.n_cn; ti += gridDim.x) check_tile<M, S, ALGO, MAXD, WU>(a, g.cn_tiles[ti]);
-        grid_sync(g, gen);
-        for (int64_t ti = blockIdx.x; ti < g.n_vn; ti += gridDim.x) var_tile<M, S, WU>(a, g.vn_tiles[ti]);
-        grid_sync(g, gen);
-        const int left = __hip_atomic_load(a.n_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (left == 0 || t >= a.T) break;
+        for (int ti = c0 + member; ti < c1; ti += g.G) check_tile<M, S, ALGO, MAXD, WU, true>(a, g.cn_tiles[ti]);
+        group_sync(g, f, gen);
+        for (int ti = v0 + member; ti < v1; ti += g.G) var_tile<M, S, WU, true>(a, g.vn_tiles[ti]);
+        group_sync(g, f, gen);
+        if (!ldc<true>(&a.active[f]) || t >= a.T) break;
     }
 }
 
-__global__ __launch_bounds__(64) static void k_grid_init(uint32_t* bar, int32_t* n_active, int32_t F)
+__global__ __launch_bounds__(256) static void k_grid_init(uint32_t* bar, uint32_t* ticket, int32_t* err, int32_t F)
 {
-    if (threadIdx.x == 0) {
-        bar[0] = 0;
-        bar[1] = 0;
-        bar[2] = 0;     // err
-        *n_active = F;
-    }
+    for (int q = int(threadIdx.x); q < 2 * F; q += 256) bar[q] = 0;
+    if (threadIdx.x < kXcds) ticket[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *err = 0;
 }
 
 // Loads the LDS tables of code cd (see LdsMap) and assigns the posterior cache
@@ -1220,39 +1258,38 @@ static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hi
     }
 }
 
-// Grid schedule (QC codes with packed tables): set-up, one launch of resident
-// workgroups for all iterations, output.
+// Grid schedule (QC codes with packed tables): set-up, one launch, output.
+// ws: [0] error flag, [4 ..) per-XCD place tickets, then [F][2] barrier words.
 template <typename M, typename S, int ALGO, int MAXD>
-static cvr_status run_grid(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* qbase)
+static cvr_status run_grid(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws)
 {
-    uint32_t* bar = reinterpret_cast<uint32_t*>(qbase + 4);
-    a.n_active = qbase + 8;
+    const int slots = (b->F + kXcds - 1) / kXcds;                 // frames per XCD
+    const int per_xcd = std::max(1, device_cus() / kXcds) * kGridPerCu;
+    if (slots > per_xcd)
+        return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the grid schedule takes at most " +
+                                          std::to_string(per_xcd * kXcds) + " frames");
+    const int G = std::max(1, std::min(per_xcd / slots, b->max_frame_tiles));
+    int32_t* err = ws;
+    uint32_t* ticket = reinterpret_cast<uint32_t*>(ws + 4);
+    uint32_t* bar = reinterpret_cast<uint32_t*>(ws + 4 + kXcds);
     const int64_t nvt = b->n_vn_tiles;
     a.tiles = b->d_vn_tiles;
     {
         ProfScope prof(CVR_PROF_DEC_SETUP, s);
         hipLaunchKernelGGL(k_dec_init<M>, dim3(nvt), dim3(kTile), 0, s, a);
-        hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(64), 0, s, bar, a.n_active, b->F);
+        hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(256), 0, s, bar, ticket, err, b->F);
     }
     if (cvr_status st = check_launch("decode init")) return st;
-    GridArgs g{b->d_qcn_tiles, b->d_qvn_tiles, b->n_qcn_tiles, b->n_qvn_tiles, bar,
-               reinterpret_cast<int32_t*>(bar + 2)};
+    GridArgs g{b->d_qcn_tiles, b->d_qvn_tiles, b->d_qcn_off, b->d_qvn_off, bar, ticket, err, b->F, G};
     const bool wu = wave_uniform(b);
     auto kern = wu ? k_grid_qc<M, S, ALGO, MAXD, true> : k_grid_qc<M, S, ALGO, MAXD, false>;
-    // every workgroup must be resident for the grid barrier: kGridPerCu per CU,
-    // which the kernel's launch bounds guarantee (the occupancy query can
-    // overstate residency: it does not see the scalar-register limit)
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTile, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-    per_cu = std::min(per_cu, kGridPerCu);
-    const int grid = int(std::min<int64_t>(std::max(b->n_qcn_tiles, b->n_qvn_tiles), int64_t(device_cus()) * per_cu));
     {
         ProfScope prof(CVR_PROF_FRAMES, s);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kTile), 0, s, a, g);
+        hipLaunchKernelGGL(kern, dim3(kXcds * slots * G), dim3(kTile), 0, s, a, g);
     }
     if (cvr_status st = check_launch("decode (grid)")) return st;
     a.tiles = b->d_vn_tiles;
-    a.grid_err = g.err;
+    a.grid_err = err;
     {
         ProfScope prof(CVR_PROF_DEC_SETUP, s);
         hipLaunchKernelGGL(k_dec_final<M>, dim3(nvt), dim3(kTile), 0, s, a);
@@ -1263,7 +1300,7 @@ static cvr_status run_grid(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32
 // mode: 0 per-pass launches, 1 persistent frame-per-workgroup, 2 grid
 template <typename M, typename S, int ALGO>
 static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, int mode, int32_t* queue,
-                               const LaunchShape& sh)
+                               int32_t* gridws, const LaunchShape& sh)
 {
     if (mode == 1) {
         if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, sh);
@@ -1271,9 +1308,9 @@ static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, b
         return run_frames<M, S, ALGO, 32>(b, a, queue, s, sh);
     }
     if (mode == 2) {
-        if (b->max_row_deg <= 8) return run_grid<M, S, ALGO, 8>(b, a, s, queue);
-        if (b->max_row_deg <= 16) return run_grid<M, S, ALGO, 16>(b, a, s, queue);
-        return run_grid<M, S, ALGO, 32>(b, a, s, queue);
+        if (b->max_row_deg <= 8) return run_grid<M, S, ALGO, 8>(b, a, s, gridws);
+        if (b->max_row_deg <= 16) return run_grid<M, S, ALGO, 16>(b, a, s, gridws);
+        return run_grid<M, S, ALGO, 32>(b, a, s, gridws);
     }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
@@ -1289,7 +1326,7 @@ static inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 static inline size_t msize(int32_t p) { return p == CVR_F64 ? 8 : (p == CVR_F32 ? 4 : 2); }
 
 struct WsLayout {
-    size_t c2v, post, active, unsat, queue, total;
+    size_t c2v, post, active, unsat, queue, grid, total;
 };
 
 static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
@@ -1304,8 +1341,10 @@ static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
     off = align256(off + size_t(b->F) * 4);
     w.unsat = off;
     off = align256(off + size_t(b->F) * 8);
-    w.queue = off;              // persistent queue [0]; grid barrier [4..6]; active frames [8]
-    off = align256(off + 64);
+    w.queue = off;              // persistent decoder's frame queue
+    off = align256(off + 4);
+    w.grid = off;               // grid schedule: error flag, XCD tickets, [F][2] barrier words
+    off = align256(off + 16 + 4 * kXcds + size_t(b->F) * 8);
     w.total = off;
     return w;
 }
@@ -1333,7 +1372,7 @@ static inline bool frames_fit(const cvr_batch_s* b)
 // One instantiation per (math, store, rule); each lives in its own translation unit.
 #define CVR_DECL_DISPATCH(NAME)                                                                      \
     cvr_status NAME(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, int mode, int32_t* queue, \
-                    const LaunchShape& sh)
+                    int32_t* gridws, const LaunchShape& sh)
 CVR_DECL_DISPATCH(decode_f64_sp);
 CVR_DECL_DISPATCH(decode_f64_nms);
 CVR_DECL_DISPATCH(decode_f32_sp);
