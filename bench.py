@@ -63,7 +63,9 @@ def parse():
     ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
                     "(weights/<prefix>_slice<j>.json per coded slice); iterations past their T reuse "
                     "the last learned row up to --max-iter")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent", "grid"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent", "group"])
+    ap.add_argument("--group-wgs", dest="group_wgs", type=int, default=0,
+                    help="workgroups per frame of the group schedule (0 = auto)")
     ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
     ap.add_argument("--min-waves", dest="min_waves", type=int, default=0, help="0 or 8 resident waves per SIMD")
     ap.add_argument("--lds-cache", dest="lds_cache_kb", type=int, default=0,
@@ -204,10 +206,10 @@ def recon(args, wl, dev):
     algo = api.SP if args.decoder == "sp" else api.NMS
     store = api.F32 if args.decoder == "sp" else api.F16
     sched = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT,
-             "grid": api.SCHED_GRID}[args.schedule]
+             "group": api.SCHED_GROUP}[args.schedule]
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
                         schedule=sched, wg_threads=args.wg, min_waves=args.min_waves,
-                        lds_cache_kb=args.lds_cache_kb)
+                        lds_cache_kb=args.lds_cache_kb, group_wgs=args.group_wgs)
     stage_params = {2: params, 3: params}
     if args.weights:
         if algo != api.NMS:
@@ -300,8 +302,8 @@ def recon(args, wl, dev):
         if persistent:
             inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
                     f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
-        else:                                   # grid schedule (one launch, all frames' rows)
-            inst = f"void cvr::k_grid_qc<{mt}, {0 if algo == api.SP else 1}, 8, true>"
+        else:                                   # group schedule (workgroups per frame on one XCD)
+            inst = f"void cvr::k_group_qc<{mt}, {0 if algo == api.SP else 1}, 8, 1024, true>"
         roof_kernel = inst
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
@@ -332,7 +334,7 @@ def recon(args, wl, dev):
             "decoder": ("sum-product" if algo == api.SP else
                         (f"learned normalized min-sum ({args.weights})" if args.weights else
                          f"normalized min-sum alpha={args.alpha}")),
-            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "min_waves": args.min_waves, "lds_cache_kb": args.lds_cache_kb,
+            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "min_waves": args.min_waves, "lds_cache_kb": args.lds_cache_kb, "group_wgs": args.group_wgs,
             "parallelism": "single GPU",
         },
         "roofline": {

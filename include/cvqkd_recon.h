@@ -179,14 +179,15 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            frames (any code); CVR_SCHED_PERSISTENT: one persistent launch in
  *            which each workgroup iterates whole frames to their stop (QC codes
  *            with <= 2048 circulants, <= 512 block rows/columns and Z <= 65535, else
- *            CVR_EUNSUPPORTED); CVR_SCHED_GRID: one launch of resident
- *            workgroups that sweep the rows (variables) of all frames, with a
- *            grid-wide barrier between the passes and an early end when every
- *            frame has stopped (QC codes with Z <= 65535 and <= 512 block
- *            columns, else CVR_EUNSUPPORTED; slower than passes on MI355X,
- *            where each barrier writes back and invalidates the per-XCD L2
- *            caches); CVR_SCHED_AUTO: persistent when possible and the batch
- *            has at least one frame per compute unit, else passes.
+ *            CVR_EUNSUPPORTED); CVR_SCHED_GROUP: one launch with a workgroup
+ *            per compute unit, in groups of workgroups on one XCD (accelerator
+ *            complex die: its compute units share an L2 cache), each group
+ *            decoding one frame at a time with barriers between the passes (the
+ *            same codes as persistent; every compute unit must be free for the
+ *            launch, else a barrier gives up after 0.2 s and the frames are
+ *            reported with ok = 0); CVR_SCHED_AUTO: for the codes of the
+ *            persistent schedule, persistent when the batch has at least one
+ *            frame per compute unit and group below that; passes otherwise.
  *  wg_threads, min_waves  tuning knobs of the persistent decoder that do
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
@@ -195,8 +196,11 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *  lds_cache_kb  posteriors of the highest-degree block columns that the
  *            persistent decoder keeps in LDS (results unchanged): 0 = as much
  *            as fits without fewer resident workgroups, -1 = none, > 0 = that
- *            many KiB (capped by the LDS size).                               */
-enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2, CVR_SCHED_GRID = 3 };
+ *            many KiB (capped by the LDS size).
+ *  group_wgs workgroups per frame of the group schedule (results unchanged):
+ *            0 = the compute units of an XCD divided by its frames, at least 1;
+ *            capped by the compute units of an XCD.                          */
+enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2, CVR_SCHED_GROUP = 3 };
 
 typedef struct {
     int32_t algo;
@@ -210,6 +214,7 @@ typedef struct {
     int32_t wg_threads;
     int32_t min_waves;
     int32_t lds_cache_kb;
+    int32_t group_wgs;
     const float* weights;
     void* trace;
 } cvr_decode_params;

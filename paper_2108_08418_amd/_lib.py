@@ -25,7 +25,7 @@ class Frame(C.Structure):
 class DecodeParams(C.Structure):
     _fields_ = [("algo", C.c_int32), ("max_iter", C.c_int32), ("early_stop", C.c_int32),
                 ("math", C.c_int32), ("store", C.c_int32), ("alpha", C.c_float),
-                ("msg_clamp", C.c_float), ("schedule", C.c_int32), ("wg_threads", C.c_int32), ("min_waves", C.c_int32), ("lds_cache_kb", C.c_int32),
+                ("msg_clamp", C.c_float), ("schedule", C.c_int32), ("wg_threads", C.c_int32), ("min_waves", C.c_int32), ("lds_cache_kb", C.c_int32), ("group_wgs", C.c_int32),
                 ("weights", C.c_void_p),
                 ("trace", C.c_void_p)]
 

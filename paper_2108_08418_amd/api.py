@@ -19,7 +19,7 @@ from ._lib import DecodeParams, Frame, check, load
 GRAY, BINARY = 0, 1
 SP, NMS = 0, 1
 F64, F32, F16 = 0, 1, 2
-SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT, SCHED_GRID = 0, 1, 2, 3
+SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT, SCHED_GROUP = 0, 1, 2, 3
 
 _TORCH_OF = {F64: torch.float64, F32: torch.float32}
 
@@ -151,6 +151,7 @@ class Params:
     wg_threads: int = 0
     min_waves: int = 0
     lds_cache_kb: int = 0
+    group_wgs: int = 0
 
     def c_struct(self, trace: torch.Tensor | None = None) -> DecodeParams:
         p = DecodeParams()
@@ -160,6 +161,7 @@ class Params:
         p.wg_threads = int(self.wg_threads)
         p.min_waves = int(self.min_waves)
         p.lds_cache_kb = int(self.lds_cache_kb)
+        p.group_wgs = int(self.group_wgs)
         if self.weights is not None:
             if self.weights.dtype != torch.float32:
                 raise ValueError("weights must be float32")

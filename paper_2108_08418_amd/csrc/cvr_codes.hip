@@ -289,8 +289,6 @@ static void free_batch(cvr_batch_s* b)
     (void)hipFree(b->d_vn_tiles);
     (void)hipFree(b->d_qcn_tiles);
     (void)hipFree(b->d_qvn_tiles);
-    (void)hipFree(b->d_qcn_off);
-    (void)hipFree(b->d_qvn_off);
     delete b;
 }
 
@@ -370,11 +368,8 @@ extern "C" cvr_status cvr_batch_create(const cvr_code_t* codes, int32_t n_codes,
     }
     // work lists
     std::vector<Tile> cn, vn, qcn, qvn;
-    std::vector<int32_t> qcn_off(static_cast<size_t>(F) + 1, 0), qvn_off(static_cast<size_t>(F) + 1, 0);
     for (int32_t f = 0; f < F; ++f) {
         const DevCode& d = dc[b->frames_host[f].code];
-        qcn_off[size_t(f)] = int32_t(qcn.size());
-        qvn_off[size_t(f)] = int32_t(qvn.size());
         for (int32_t r = 0; r < d.m; r += kTile) cn.push_back(Tile{f, r, 0, std::min(kTile, d.m - r)});
         for (int32_t v = 0; v < d.n; v += kTile)
             vn.push_back(Tile{f, v, 0, std::min(kTile, d.n - v) | (v == 0 ? kFirstTile : 0)});
@@ -386,11 +381,6 @@ extern "C" cvr_status cvr_batch_create(const cvr_code_t* codes, int32_t n_codes,
                     qvn.push_back(Tile{f, j, u, std::min(kTile, d.Z - u) | (j == 0 && u == 0 ? kFirstTile : 0)});
         }
     }
-    qcn_off[size_t(F)] = int32_t(qcn.size());
-    qvn_off[size_t(F)] = int32_t(qvn.size());
-    for (int32_t f = 0; f < F; ++f)
-        b->max_frame_tiles = std::max({b->max_frame_tiles, qcn_off[size_t(f) + 1] - qcn_off[size_t(f)],
-                                       qvn_off[size_t(f) + 1] - qvn_off[size_t(f)]});
     // the persistent decoder hands frames out largest first (longest-processing-
     // time order), so a few long frames do not trail at the end of a launch
     std::vector<int32_t> order(static_cast<size_t>(F));
@@ -406,8 +396,6 @@ extern "C" cvr_status cvr_batch_create(const cvr_code_t* codes, int32_t n_codes,
     if (!st) st = upload_vec(vn, &b->d_vn_tiles);
     if (!st && b->all_qc) st = upload_vec(qcn, &b->d_qcn_tiles);
     if (!st && b->all_qc) st = upload_vec(qvn, &b->d_qvn_tiles);
-    if (!st && b->all_qc) st = upload_vec(qcn_off, &b->d_qcn_off);
-    if (!st && b->all_qc) st = upload_vec(qvn_off, &b->d_qvn_off);
     if (st) {
         free_batch(b);
         return st;

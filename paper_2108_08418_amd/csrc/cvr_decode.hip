@@ -65,11 +65,12 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
     if (p->math == CVR_F64 && p->store != CVR_F64)
         return fail(CVR_EUNSUPPORTED, "decode: F64 math is implemented with F64 storage only");
     if (p->algo == CVR_SP && !(p->msg_clamp > 0.0f)) return fail(CVR_EINVAL, "decode: msg_clamp must be > 0");
-    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_GRID) return fail(CVR_EINVAL, "decode: bad schedule");
+    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_GROUP) return fail(CVR_EINVAL, "decode: bad schedule");
     if (p->wg_threads != 0 && p->wg_threads != 512 && p->wg_threads != 1024)
         return fail(CVR_EINVAL, "decode: wg_threads must be 0, 512 or 1024");
     if (p->min_waves != 0 && p->min_waves != 8) return fail(CVR_EINVAL, "decode: min_waves must be 0 or 8");
     if (p->lds_cache_kb < -1 || p->lds_cache_kb > 1024) return fail(CVR_EINVAL, "decode: lds_cache_kb must be in [-1, 1024]");
+    if (p->group_wgs < 0 || p->group_wgs > 1024) return fail(CVR_EINVAL, "decode: group_wgs must be in [0, 1024]");
     return CVR_OK;
 }
 
@@ -126,22 +127,20 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
             return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the persistent schedule needs QC codes with <= 2048 "
                                           "circulants, <= 512 block rows/columns and Z <= 65535");
         mode = 1;
-    } else if (params->schedule == CVR_SCHED_GRID) {
-        if (!packed_tables(batch))
-            return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the grid schedule needs QC codes with Z <= 65535 and "
-                                          "<= 512 block columns");
+    } else if (params->schedule == CVR_SCHED_GROUP) {
+        if (!frames_fit(batch))
+            return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the group schedule needs QC codes with <= 2048 "
+                                          "circulants, <= 512 block rows/columns and Z <= 65535");
         mode = 2;
     } else if (params->schedule == CVR_SCHED_AUTO) {
         // a workgroup per frame leaves compute units idle below one frame per
-        // CU; then the per-pass kernels spread every frame's rows over the chip
-        // (the grid schedule does the same in one launch, but its barriers,
-        // which write back and invalidate the per-XCD L2 caches, cost more
-        // than the launches they replace: 18.8 vs 6.0 ms for 16 frames of 2^16)
-        if (frames_fit(batch) && batch->F >= device_cus()) mode = 1;
+        // CU; then groups of workgroups share each frame (16 frames of 2^16:
+        // 1.1 ms for both coded slices, against 5.9 ms of per-pass launches)
+        if (frames_fit(batch)) mode = batch->F >= device_cus() ? 1 : 2;
     }
     int32_t* queue = reinterpret_cast<int32_t*>(ws + w.queue);
     int32_t* gridws = reinterpret_cast<int32_t*>(ws + w.grid);
-    const LaunchShape sh{params->wg_threads, params->min_waves, params->lds_cache_kb};
+    const LaunchShape sh{params->wg_threads, params->min_waves, params->lds_cache_kb, params->group_wgs};
     const bool sp = params->algo == CVR_SP;
     if (params->math == CVR_F64)
         return sp ? decode_f64_sp(batch, a, s, qc, mode, queue, gridws, sh) : decode_f64_nms(batch, a, s, qc, mode, queue, gridws, sh);

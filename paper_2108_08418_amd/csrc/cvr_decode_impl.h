@@ -165,7 +165,6 @@ struct DecArgs {
     int32_t T;
     int32_t early_stop;
     int32_t n_types;
-    const int32_t* grid_err;  // set when a grid barrier gave up (grid schedule) or NULL
     float* ckpt;              // [ceil(T / ckpt_every)][ckpt_stride] c2v(t) at t = 0, K, 2K, ... or NULL
     int64_t ckpt_stride;
     int32_t ckpt_every;
@@ -173,7 +172,7 @@ struct DecArgs {
 
 // Tuning knobs of the persistent decoder (none of them changes results).
 struct LaunchShape {
-    int32_t wg, min_waves, lds_kb;
+    int32_t wg, min_waves, lds_kb, group_wgs;
 };
 
 __device__ __forceinline__ void add_unsat(int32_t* slot, int pred)
@@ -635,16 +634,79 @@ __device__ __forceinline__ M var_sum_any(const FrameCtx<M, S>& c, int qa, int dv
     return acc;
 }
 
+// ---------------------------------------------------------------------------
+// frame groups: G workgroups resident on one XCD decode one frame together
+// ---------------------------------------------------------------------------
+// The group shares the XCD's L2, so its barrier is a pair of L2 atomics and
+// the loads of data that other members wrote are device-scope loads that read
+// that L2 (ldc<true>); no cache is written back or invalidated.
+constexpr int kXcds = 8;
+
+struct GroupCtx {
+    int member, G;
+    uint32_t* bar;      // [2] arrivals (monotonic), generation
+    int32_t* unsat;     // [2] unsatisfied checks after iterations t with t & 1 = 0 / 1
+    int32_t* err;       // set to 1 when a barrier wait gave up
+    uint32_t gen;       // barriers passed so far
+};
+
+// Barrier of the G workgroups of a group.  Each wave first waits for its own
+// stores to complete (they are then in the L2), the workgroup meets, and one
+// thread arrives; the G-th arrival of a generation advances it, the others
+// wait for that, bounded in wall-clock time (0.2 s; once a wait has given up
+// no later one waits, so the launch always ends, and the frames are then
+// reported as not decoded).
+__device__ __forceinline__ void group_sync(GroupCtx& g)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t arrived = atomicAdd(&g.bar[0], 1u);
+        if (arrived == (g.gen + 1u) * uint32_t(g.G) - 1u) {
+            __hip_atomic_store(&g.bar[1], g.gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&g.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g.gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > 20000000ull) {       // 0.2 s of the 100 MHz counter
+                    atomicExch(g.err, 1);
+                    break;
+                }
+            }
+        }
+    }
+    ++g.gen;
+    __syncthreads();
+}
+
 // One frame, all iterations.  With WU every wavefront's rows (variables) share
 // one block row (column), so the degree is wave-uniform and each step runs
 // the straight-line body of its exact degree (1..8); larger degrees and
 // codes with Z % 64 != 0 take the masked bodies.  The per-iteration min-sum
 // weights are staged in LDS.
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, bool CACHE>
+//
+// GRP: the workgroup is member gc->member of a group of gc->G that decode the
+// frame together (rows and variables interleaved by workgroup), with group
+// barriers between the passes and the stop decision taken from the group's
+// count; no posterior cache and no checkpoints.
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, bool CACHE, bool GRP = false>
 __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm, int32_t* dsm, int32_t (&s_unsat)[2],
-                                             float (&s_w)[kMaxTypes], int f, const DevFrame& fr, const DevCode& cd)
+                                             float (&s_w)[kMaxTypes], int f, const DevFrame& fr, const DevCode& cd,
+                                             GroupCtx* gc = nullptr)
 {
+    static_assert(!(GRP && CACHE), "frame groups keep no posterior cache");
     const int tid = int(threadIdx.x);
+    int first = tid, stride = NT;
+    bool lead = true;                       // writes the frame's iteration count and status
+    if constexpr (GRP) {
+        first = gc->member * NT + tid;
+        stride = gc->G * NT;
+        lead = gc->member == 0;
+    }
+    auto sync = [&]() {
+        if constexpr (GRP) group_sync(*gc);
+        else __syncthreads();
+    };
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
@@ -668,7 +730,7 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
     auto column = [&](int v) { return uni<WU>(zsh >= 0 ? (v >> zsh) : v / Z); };
     auto slot_of = [&](int j) { return CACHE ? uni<WU>(c.s_cslot[j]) : -1; };
-    for (int v = tid; v < n; v += NT) {
+    for (int v = first; v < n; v += stride) {
         const int j = column(v);
         const int slot = slot_of(j);
         const M l = at(c.Lc, v);
@@ -681,19 +743,21 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         s_unsat[1] = 0;
     }
     if (a.weights && a.T > 0 && tid < a.n_types) s_w[tid] = a.weights[tid];
-    __syncthreads();
+    sync();
     for (int t = 0;; ++t) {
         c.t = t;
-        if (a.ckpt && t < a.T && t % a.ckpt_every == 0) {
-            // checkpoint c2v(t) (all zero at t = 0) before the check pass overwrites it
-            float* ck = a.ckpt + int64_t(t / a.ckpt_every) * a.ckpt_stride + fr.msg_off;
-            const int ef = cd.NB * Z;
-            for (int e = tid; e < ef; e += NT) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(c.msg[e]));
-            __syncthreads();
+        if constexpr (!GRP) {
+            if (a.ckpt && t < a.T && t % a.ckpt_every == 0) {
+                // checkpoint c2v(t) (all zero at t = 0) before the check pass overwrites it
+                float* ck = a.ckpt + int64_t(t / a.ckpt_every) * a.ckpt_stride + fr.msg_off;
+                const int ef = cd.NB * Z;
+                for (int e = tid; e < ef; e += NT) ck[e] = (t == 0) ? 0.0f : float(StoreT<S>::get(c.msg[e]));
+                __syncthreads();
+            }
         }
         // check pass: syndrome test of Lpost(t) and c2v(t+1)
         int bad = 0;
-        for (int r = tid; r < m; r += NT) {
+        for (int r = first; r < m; r += stride) {
             const int i = uni<WU>(zsh >= 0 ? (r >> zsh) : r / Z);
             const int k = r - i * Z;
             const int q0 = uni<WU>(s_rptr[i]);
@@ -701,38 +765,48 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
             const int sraw = syn ? int(at(syn, r)) : 0;
             if constexpr (WU) {
                 switch (d) {
-                case 1: bad += check_row<M, S, ALGO, 1, WU, CACHE>(c, q0, k, sraw); break;
-                case 2: bad += check_row<M, S, ALGO, 2, WU, CACHE>(c, q0, k, sraw); break;
-                case 3: bad += check_row<M, S, ALGO, 3, WU, CACHE>(c, q0, k, sraw); break;
-                case 4: bad += check_row<M, S, ALGO, 4, WU, CACHE>(c, q0, k, sraw); break;
-                case 5: bad += check_row<M, S, ALGO, 5, WU, CACHE>(c, q0, k, sraw); break;
-                case 6: bad += check_row<M, S, ALGO, 6, WU, CACHE>(c, q0, k, sraw); break;
-                case 7: bad += check_row<M, S, ALGO, 7, WU, CACHE>(c, q0, k, sraw); break;
-                case 8: bad += check_row<M, S, ALGO, 8, WU, CACHE>(c, q0, k, sraw); break;
+                case 1: bad += check_row<M, S, ALGO, 1, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 2: bad += check_row<M, S, ALGO, 2, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 3: bad += check_row<M, S, ALGO, 3, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 4: bad += check_row<M, S, ALGO, 4, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 5: bad += check_row<M, S, ALGO, 5, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 6: bad += check_row<M, S, ALGO, 6, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 7: bad += check_row<M, S, ALGO, 7, WU, CACHE, GRP>(c, q0, k, sraw); break;
+                case 8: bad += check_row<M, S, ALGO, 8, WU, CACHE, GRP>(c, q0, k, sraw); break;
                 default:
-                    if constexpr (MAXD > 8) bad += check_row_any<M, S, ALGO, MAXD, WU, CACHE>(c, q0, d, k, sraw);
+                    if constexpr (MAXD > 8) bad += check_row_any<M, S, ALGO, MAXD, WU, CACHE, GRP>(c, q0, d, k, sraw);
                     break;
                 }
             } else {
-                bad += check_row_any<M, S, ALGO, MAXD, WU, CACHE>(c, q0, d, k, sraw);
+                bad += check_row_any<M, S, ALGO, MAXD, WU, CACHE, GRP>(c, q0, d, k, sraw);
             }
         }
         if (bad) atomicAdd(&s_unsat[t & 1], bad);
         __syncthreads();
-        const int u = s_unsat[t & 1];
+        int u = s_unsat[t & 1];
+        if constexpr (GRP) {
+            // the group's count is final after the barrier; its other slot was
+            // last read before the previous barrier, so the lead clears it
+            if (tid == 0 && u) atomicAdd(&gc->unsat[t & 1], u);
+            group_sync(*gc);
+            u = ldc<true>(&gc->unsat[t & 1]);
+        }
         if ((a.early_stop && u == 0) || t >= a.T) {
-            if (tid == 0) {
+            if (tid == 0 && lead) {
                 a.iters[f] = t;
                 a.ok[f] = uint8_t(u == 0);
             }
             break;
         }
         if (tid == 0) s_unsat[(t + 1) & 1] = 0;
+        if constexpr (GRP) {
+            if (tid == 0 && lead) __hip_atomic_store(&gc->unsat[(t + 1) & 1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         // the next iteration's weights: every read of s_w for iteration t
         // happened before the barrier above
         if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
         // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows ascending
-        for (int v = tid; v < n; v += NT) {
+        for (int v = first; v < n; v += stride) {
             const int j = column(v);
             const int uu = v - j * Z;
             const int qa = uni<WU>(s_cptr[j]);
@@ -741,27 +815,27 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
             M acc = at(c.Lc, v);
             if constexpr (WU) {
                 switch (dv) {
-                case 1: acc = var_sum<M, S, 1, WU>(c, qa, uu, acc); break;
-                case 2: acc = var_sum<M, S, 2, WU>(c, qa, uu, acc); break;
-                case 3: acc = var_sum<M, S, 3, WU>(c, qa, uu, acc); break;
-                case 4: acc = var_sum<M, S, 4, WU>(c, qa, uu, acc); break;
-                case 5: acc = var_sum<M, S, 5, WU>(c, qa, uu, acc); break;
-                case 6: acc = var_sum<M, S, 6, WU>(c, qa, uu, acc); break;
-                case 7: acc = var_sum<M, S, 7, WU>(c, qa, uu, acc); break;
-                case 8: acc = var_sum<M, S, 8, WU>(c, qa, uu, acc); break;
-                default: acc = var_sum_any<M, S, WU>(c, qa, dv, uu, acc); break;
+                case 1: acc = var_sum<M, S, 1, WU, GRP>(c, qa, uu, acc); break;
+                case 2: acc = var_sum<M, S, 2, WU, GRP>(c, qa, uu, acc); break;
+                case 3: acc = var_sum<M, S, 3, WU, GRP>(c, qa, uu, acc); break;
+                case 4: acc = var_sum<M, S, 4, WU, GRP>(c, qa, uu, acc); break;
+                case 5: acc = var_sum<M, S, 5, WU, GRP>(c, qa, uu, acc); break;
+                case 6: acc = var_sum<M, S, 6, WU, GRP>(c, qa, uu, acc); break;
+                case 7: acc = var_sum<M, S, 7, WU, GRP>(c, qa, uu, acc); break;
+                case 8: acc = var_sum<M, S, 8, WU, GRP>(c, qa, uu, acc); break;
+                default: acc = var_sum_any<M, S, WU, GRP>(c, qa, dv, uu, acc); break;
                 }
             } else {
-                acc = var_sum_any<M, S, WU>(c, qa, dv, uu, acc);
+                acc = var_sum_any<M, S, WU, GRP>(c, qa, dv, uu, acc);
             }
             if (slot >= 0) c.s_post[slot * Z + uu] = acc;
             else at(c.Lp, v) = acc;
             if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc;
         }
-        __syncthreads();
+        sync();
     }
     // hard decisions; cached posteriors go back to HBM
-    for (int v = tid; v < n; v += NT) {
+    for (int v = first; v < n; v += stride) {
         const int j = column(v);
         const int slot = slot_of(j);
         M l;
@@ -800,10 +874,10 @@ __device__ __forceinline__ FrameCtx<M, S> pass_ctx(const DecArgs& a, const DevFr
 }
 
 // The check step of tile tl (every thread of the workgroup calls it).
-template <typename M, typename S, int ALGO, int MAXD, bool WU, bool COH = false>
+template <typename M, typename S, int ALGO, int MAXD, bool WU>
 __device__ __forceinline__ void check_tile(const DecArgs& a, const Tile& tl)
 {
-    if (!ldc<COH>(&a.active[tl.frame])) return;
+    if (!a.active[tl.frame]) return;
     const DevFrame fr = a.frames[tl.frame];
     const DevCode& cd = a.codes[fr.code];
     const int count = tl.count & 0x7fffffff;
@@ -817,30 +891,30 @@ __device__ __forceinline__ void check_tile(const DecArgs& a, const Tile& tl)
         const int sraw = a.syn ? int(a.syn[fr.chk_off + int64_t(i) * cd.Z + k]) : 0;
         if constexpr (WU) {
             switch (d) {
-            case 1: bad = check_row<M, S, ALGO, 1, WU, false, COH>(c, q0, k, sraw); break;
-            case 2: bad = check_row<M, S, ALGO, 2, WU, false, COH>(c, q0, k, sraw); break;
-            case 3: bad = check_row<M, S, ALGO, 3, WU, false, COH>(c, q0, k, sraw); break;
-            case 4: bad = check_row<M, S, ALGO, 4, WU, false, COH>(c, q0, k, sraw); break;
-            case 5: bad = check_row<M, S, ALGO, 5, WU, false, COH>(c, q0, k, sraw); break;
-            case 6: bad = check_row<M, S, ALGO, 6, WU, false, COH>(c, q0, k, sraw); break;
-            case 7: bad = check_row<M, S, ALGO, 7, WU, false, COH>(c, q0, k, sraw); break;
-            case 8: bad = check_row<M, S, ALGO, 8, WU, false, COH>(c, q0, k, sraw); break;
+            case 1: bad = check_row<M, S, ALGO, 1, WU, false>(c, q0, k, sraw); break;
+            case 2: bad = check_row<M, S, ALGO, 2, WU, false>(c, q0, k, sraw); break;
+            case 3: bad = check_row<M, S, ALGO, 3, WU, false>(c, q0, k, sraw); break;
+            case 4: bad = check_row<M, S, ALGO, 4, WU, false>(c, q0, k, sraw); break;
+            case 5: bad = check_row<M, S, ALGO, 5, WU, false>(c, q0, k, sraw); break;
+            case 6: bad = check_row<M, S, ALGO, 6, WU, false>(c, q0, k, sraw); break;
+            case 7: bad = check_row<M, S, ALGO, 7, WU, false>(c, q0, k, sraw); break;
+            case 8: bad = check_row<M, S, ALGO, 8, WU, false>(c, q0, k, sraw); break;
             default:
-                if constexpr (MAXD > 8) bad = check_row_any<M, S, ALGO, MAXD, WU, false, COH>(c, q0, d, k, sraw);
+                if constexpr (MAXD > 8) bad = check_row_any<M, S, ALGO, MAXD, WU, false>(c, q0, d, k, sraw);
                 break;
             }
         } else {
-            bad = check_row_any<M, S, ALGO, MAXD, WU, false, COH>(c, q0, d, k, sraw);
+            bad = check_row_any<M, S, ALGO, MAXD, WU, false>(c, q0, d, k, sraw);
         }
     }
     add_unsat(&a.unsat[2 * tl.frame + (a.t & 1)], bad);
 }
 
 // The variable step of tile tl, after the frame's stop decision.
-template <typename M, typename S, bool WU, bool COH = false>
+template <typename M, typename S, bool WU>
 __device__ __forceinline__ void var_tile(const DecArgs& a, const Tile& tl)
 {
-    if (!ldc<COH>(&a.active[tl.frame])) return;
+    if (!a.active[tl.frame]) return;
     if (frame_stops(a, tl)) return;
     const DevFrame fr = a.frames[tl.frame];
     const DevCode& cd = a.codes[fr.code];
@@ -855,18 +929,18 @@ __device__ __forceinline__ void var_tile(const DecArgs& a, const Tile& tl)
     M acc = at(c.Lc, v);
     if constexpr (WU) {
         switch (dv) {
-        case 1: acc = var_sum<M, S, 1, WU, COH>(c, qa, u, acc); break;
-        case 2: acc = var_sum<M, S, 2, WU, COH>(c, qa, u, acc); break;
-        case 3: acc = var_sum<M, S, 3, WU, COH>(c, qa, u, acc); break;
-        case 4: acc = var_sum<M, S, 4, WU, COH>(c, qa, u, acc); break;
-        case 5: acc = var_sum<M, S, 5, WU, COH>(c, qa, u, acc); break;
-        case 6: acc = var_sum<M, S, 6, WU, COH>(c, qa, u, acc); break;
-        case 7: acc = var_sum<M, S, 7, WU, COH>(c, qa, u, acc); break;
-        case 8: acc = var_sum<M, S, 8, WU, COH>(c, qa, u, acc); break;
-        default: acc = var_sum_any<M, S, WU, COH>(c, qa, dv, u, acc); break;
+        case 1: acc = var_sum<M, S, 1, WU>(c, qa, u, acc); break;
+        case 2: acc = var_sum<M, S, 2, WU>(c, qa, u, acc); break;
+        case 3: acc = var_sum<M, S, 3, WU>(c, qa, u, acc); break;
+        case 4: acc = var_sum<M, S, 4, WU>(c, qa, u, acc); break;
+        case 5: acc = var_sum<M, S, 5, WU>(c, qa, u, acc); break;
+        case 6: acc = var_sum<M, S, 6, WU>(c, qa, u, acc); break;
+        case 7: acc = var_sum<M, S, 7, WU>(c, qa, u, acc); break;
+        case 8: acc = var_sum<M, S, 8, WU>(c, qa, u, acc); break;
+        default: acc = var_sum_any<M, S, WU>(c, qa, dv, u, acc); break;
         }
     } else {
-        acc = var_sum_any<M, S, WU, COH>(c, qa, dv, u, acc);
+        acc = var_sum_any<M, S, WU>(c, qa, dv, u, acc);
     }
     at(c.Lp, v) = acc;
     if (a.trace) static_cast<M*>(a.trace)[int64_t(a.t + 1) * a.total_n + fr.vn_off + v] = acc;
@@ -882,100 +956,6 @@ template <typename M, typename S, bool WU>
 __global__ __launch_bounds__(kTile) void k_var_qc_pk(DecArgs a)
 {
     var_tile<M, S, WU>(a, a.tiles[blockIdx.x]);
-}
-
-// ---------------------------------------------------------------------------
-// grid schedule: all iterations of all frames in one launch.  Each frame is
-// worked on by a group of G resident workgroups on one XCD, so the group
-// shares one L2: its barrier needs only atomics, and the loads of data that
-// other members write read that L2 directly; no cache is written back or
-// invalidated.  A workgroup learns its XCD from the XCC_ID register and takes
-// the next place on that XCD (frames f with f % 8 == XCD, G places each), so
-// nothing depends on how the dispatcher numbers workgroups across XCDs.
-// ---------------------------------------------------------------------------
-constexpr int kGridPerCu = 4;      // workgroups per CU of the launch (guaranteed by its launch bounds)
-constexpr int kXcds = 8;
-
-struct GridArgs {
-    const Tile* cn_tiles;
-    const Tile* vn_tiles;
-    const int32_t* cn_off;    // [F + 1] each frame's row tiles
-    const int32_t* vn_off;    // [F + 1] each frame's variable tiles
-    uint32_t* bar;            // [F][2] arrivals, generation; zero at launch
-    uint32_t* ticket;         // [kXcds] places taken on each XCD; zero at launch
-    int32_t* err;             // 1: a barrier wait gave up; 2: an XCC_ID outside 0..kXcds-1
-    int32_t F, G;
-};
-
-// Barrier of the G workgroups of frame f.  The last to arrive resets the count
-// and advances the generation; the others wait for it, bounded in wall-clock
-// time (0.2 s; after a wait has given up no later one waits, so the launch
-// always ends and the frames are reported as not decoded).  Stores before the
-// barrier have reached the XCD's L2 (the workgroup barrier waits for them),
-// and every load of data that other workgroups write is a device-scope load
-// that reads the L2 (ldc), so no cache has to be written back or invalidated.
-__device__ __forceinline__ void group_sync(const GridArgs& g, int f, uint32_t& gen)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t* bf = g.bar + 2 * f;
-        const uint32_t arrived = atomicAdd(&bf[0], 1u);
-        if (arrived == uint32_t(g.G) - 1) {
-            atomicExch(&bf[0], 0u);
-            atomicAdd(&bf[1], 1u);
-        } else if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&bf[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (wall_clock64() - t0 > 20000000ull) {       // 0.2 s of the 100 MHz counter
-                    atomicExch(g.err, 1);
-                    break;
-                }
-            }
-        }
-        ++gen;
-    }
-    __syncthreads();
-}
-
-template <typename M, typename S, int ALGO, int MAXD, bool WU>
-__global__ __launch_bounds__(kTile, kGridPerCu) void k_grid_qc(DecArgs a, GridArgs g)
-{
-    __shared__ int s_place[2];
-    if (threadIdx.x == 0) {
-        uint32_t xcc;
-        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-        int xcd = int(xcc & 0xf);
-        if (xcd >= kXcds) {
-            atomicExch(g.err, 2);
-            xcd = 0;
-        }
-        s_place[0] = xcd;
-        s_place[1] = int(atomicAdd(&g.ticket[xcd], 1u));
-    }
-    __syncthreads();
-    const int xcd = s_place[0], slot = s_place[1];
-    const int member = slot % g.G;
-    const int f = (slot / g.G) * kXcds + xcd;
-    if (f >= g.F) return;                               // a surplus place: no frame
-    const int c0 = g.cn_off[f], c1 = g.cn_off[f + 1];
-    const int v0 = g.vn_off[f], v1 = g.vn_off[f + 1];
-    uint32_t gen = 0;
-    for (int t = 0;; ++t) {
-        a.t = t;
-        for (int ti = c0 + member; ti < c1; ti += g.G) check_tile<M, S, ALGO, MAXD, WU, true>(a, g.cn_tiles[ti]);
-        group_sync(g, f, gen);
-        for (int ti = v0 + member; ti < v1; ti += g.G) var_tile<M, S, WU, true>(a, g.vn_tiles[ti]);
-        group_sync(g, f, gen);
-        if (!ldc<true>(&a.active[f]) || t >= a.T) break;
-    }
-}
-
-__global__ __launch_bounds__(256) static void k_grid_init(uint32_t* bar, uint32_t* ticket, int32_t* err, int32_t F)
-{
-    for (int q = int(threadIdx.x); q < 2 * F; q += 256) bar[q] = 0;
-    if (threadIdx.x < kXcds) ticket[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *err = 0;
 }
 
 // Loads the LDS tables of code cd (see LdsMap) and assigns the posterior cache
@@ -1036,6 +1016,91 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, in
     }
 }
 
+// Frame groups.  A workgroup reads its XCD from the XCC_ID register and takes
+// the next place of that XCD: places [g G, (g + 1) G) form group g.  Each
+// group takes the XCD's frames (order[q * 8 + XCD], q = 0, 1, ...: largest
+// first) from that XCD's queue and decodes them together; nothing depends on
+// how the dispatcher numbers workgroups across XCDs.  The launch has one
+// workgroup per CU (all resident) and the same number of places per XCD.
+// Group workspace, in 32-bit words:
+//   [0] error flag (1: a barrier wait gave up; 2: an XCC_ID outside 0..7)
+//   [4, 12) place tickets, [12, 20) frame queues, one per XCD
+//   [32 + 8 g, ...) group g: arrivals, generation, unsatisfied [2], frame
+constexpr int kGwErr = 0, kGwTicket = 4, kGwQueue = 12, kGwGroups = 32, kGwGroupWords = 8;
+constexpr int kMaxGroups = 1024;
+constexpr size_t kGroupWsBytes = size_t(kGwGroups + kMaxGroups * kGwGroupWords) * 4;
+
+struct GroupArgs {
+    const int32_t* order;     // [F] frames, largest first
+    int32_t* ws;              // group workspace, zeroed by k_group_init
+    int32_t F, G, NG;         // frames, workgroups per group, groups per XCD
+};
+
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU>
+__global__ __launch_bounds__(NT, 1) void k_group_qc(DecArgs a, LdsMap lm, GroupArgs g)
+{
+    extern __shared__ __align__(16) int32_t dsm[];
+    __shared__ int32_t s_place[2];
+    __shared__ int32_t s_unsat[2];
+    __shared__ float s_w[kMaxTypes];
+    const int tid = int(threadIdx.x);
+    int32_t* err = g.ws + kGwErr;
+    if (tid == 0) {
+        uint32_t xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        int xcd = int(xcc & 0xf);
+        if (xcd >= kXcds) {
+            atomicExch(err, 2);
+            xcd = 0;
+        }
+        s_place[0] = xcd;
+        s_place[1] = atomicAdd(g.ws + kGwTicket + xcd, 1);
+    }
+    __syncthreads();
+    const int xcd = s_place[0], place = s_place[1];
+    const int gi = place / g.G;
+    if (gi >= g.NG) return;                                  // a surplus place
+    int32_t* gw = g.ws + kGwGroups + (xcd * g.NG + gi) * kGwGroupWords;
+    GroupCtx gc{place % g.G, g.G, reinterpret_cast<uint32_t*>(gw), gw + 2, err, 0u};
+    int cur = -1;
+    for (;;) {
+        if (gc.member == 0 && tid == 0) {
+            // every member read the previous frame and its counts before the
+            // barrier that ended that frame
+            const int q = atomicAdd(g.ws + kGwQueue + xcd, 1);
+            const int64_t o = int64_t(q) * kXcds + xcd;
+            const int f = o < g.F ? g.order[o] : g.F;
+            __hip_atomic_store(gw + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gw + 3, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gw + 4, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        group_sync(gc);
+        const int f = __builtin_amdgcn_readfirstlane(ldc<true>(gw + 4));
+        if (f >= g.F) break;
+        const DevFrame fr = a.frames[f];
+        const DevCode& cd = a.codes[fr.code];
+        if (fr.code != cur) {
+            load_code_tables<M, NT>(lm, dsm, cd);
+            cur = fr.code;
+        }
+        decode_frame<M, S, ALGO, MAXD, NT, WU, false, true>(a, lm, dsm, s_unsat, s_w, f, fr, cd, &gc);
+        group_sync(gc);
+    }
+}
+
+[[maybe_unused]] __global__ __launch_bounds__(256) static void k_group_init(int32_t* ws, int32_t words)
+{
+    for (int q = int(threadIdx.x); q < words; q += 256) ws[q] = 0;
+}
+
+// A barrier that gave up leaves the frames' results unreliable: report every
+// frame as not decoded.
+[[maybe_unused]] __global__ __launch_bounds__(256) static void k_group_final(uint8_t* ok, const int32_t* ws, int32_t F)
+{
+    const int f = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (f < F && ws[kGwErr]) ok[f] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // set-up and output passes (over the generic variable tiles)
 // ---------------------------------------------------------------------------
@@ -1065,7 +1130,6 @@ __global__ __launch_bounds__(kTile) void k_dec_final(DecArgs a)
     const Tile tl = a.tiles[blockIdx.x];
     const DevFrame fr = a.frames[tl.frame];
     const int count = tl.count & 0x7fffffff;
-    if (a.grid_err && *a.grid_err && (tl.count & kFirstTile) && threadIdx.x == 0) a.ok[tl.frame] = 0;
     if (int(threadIdx.x) >= count) return;
     const int64_t v = fr.vn_off + tl.a + int(threadIdx.x);
     a.bits[v] = static_cast<const M*>(a.post)[v] < M(0) ? 1 : 0;
@@ -1258,46 +1322,66 @@ static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hi
     }
 }
 
-// Grid schedule (QC codes with packed tables): set-up, one launch, output.
-// ws: [0] error flag, [4 ..) per-XCD place tickets, then [F][2] barrier words.
-template <typename M, typename S, int ALGO, int MAXD>
-static cvr_status run_grid(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws)
+// Group schedule (QC codes whose tables fit in LDS): one workgroup per CU,
+// G per frame (group_wgs, or as many as the frames per XCD leave), at most
+// one group per frame of the XCD.
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU>
+static cvr_status launch_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws, int group_wgs)
 {
-    const int slots = (b->F + kXcds - 1) / kXcds;                 // frames per XCD
-    const int per_xcd = std::max(1, device_cus() / kXcds) * kGridPerCu;
-    if (slots > per_xcd)
-        return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the grid schedule takes at most " +
-                                          std::to_string(per_xcd * kXcds) + " frames");
-    const int G = std::max(1, std::min(per_xcd / slots, b->max_frame_tiles));
-    int32_t* err = ws;
-    uint32_t* ticket = reinterpret_cast<uint32_t*>(ws + 4);
-    uint32_t* bar = reinterpret_cast<uint32_t*>(ws + 4 + kXcds);
-    const int64_t nvt = b->n_vn_tiles;
-    a.tiles = b->d_vn_tiles;
+    auto kern = k_group_qc<M, S, ALGO, MAXD, NT, WU>;
+    static int lds_blk = 0, static_lds = 0;
+    if (lds_blk == 0) {
+        lds_blk = std::min(device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 65536),
+                           device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536));
+        hipFuncAttributes fa{};
+        static_lds = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)) == hipSuccess
+                         ? int(fa.sharedSizeBytes) : 1024;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds_blk - static_lds);
+    }
+    const LdsMap lm = lds_map(b, 0);
+    const int dyn = lm.cache * 4;
+    if (dyn > lds_blk - static_lds) return fail(CVR_EUNSUPPORTED, "decode (group): code tables exceed LDS");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, size_t(dyn)) != hipSuccess || per_cu < 1)
+        return fail(CVR_EUNSUPPORTED, "decode (group): a workgroup does not fit on a CU");
+    const int cap = std::max(1, device_cus() / kXcds);           // places per XCD
+    const int fx = (b->F + kXcds - 1) / kXcds;                   // frames per XCD
+    const int G = group_wgs > 0 ? std::min(group_wgs, cap) : std::max(1, cap / std::min(fx, cap));
+    const int NG = std::min(cap / G, fx);
+    if (NG * kXcds > kMaxGroups) return fail(CVR_EUNSUPPORTED, "decode (group): too many groups");
     {
         ProfScope prof(CVR_PROF_DEC_SETUP, s);
-        hipLaunchKernelGGL(k_dec_init<M>, dim3(nvt), dim3(kTile), 0, s, a);
-        hipLaunchKernelGGL(k_grid_init, dim3(1), dim3(256), 0, s, bar, ticket, err, b->F);
+        hipLaunchKernelGGL(k_group_init, dim3(1), dim3(256), 0, s, ws, int32_t(kGwGroups + NG * kXcds * kGwGroupWords));
     }
-    if (cvr_status st = check_launch("decode init")) return st;
-    GridArgs g{b->d_qcn_tiles, b->d_qvn_tiles, b->d_qcn_off, b->d_qvn_off, bar, ticket, err, b->F, G};
-    const bool wu = wave_uniform(b);
-    auto kern = wu ? k_grid_qc<M, S, ALGO, MAXD, true> : k_grid_qc<M, S, ALGO, MAXD, false>;
+    if (cvr_status st = check_launch("decode (group) init")) return st;
+    const GroupArgs g{b->d_order, ws, b->F, G, NG};
     {
         ProfScope prof(CVR_PROF_FRAMES, s);
-        hipLaunchKernelGGL(kern, dim3(kXcds * slots * G), dim3(kTile), 0, s, a, g);
+        hipLaunchKernelGGL(kern, dim3(kXcds * NG * G), dim3(NT), size_t(dyn), s, a, lm, g);
     }
-    if (cvr_status st = check_launch("decode (grid)")) return st;
-    a.tiles = b->d_vn_tiles;
-    a.grid_err = err;
+    if (cvr_status st = check_launch("decode (group)")) return st;
     {
         ProfScope prof(CVR_PROF_DEC_SETUP, s);
-        hipLaunchKernelGGL(k_dec_final<M>, dim3(nvt), dim3(kTile), 0, s, a);
+        hipLaunchKernelGGL(k_group_final, dim3((b->F + 255) / 256), dim3(256), 0, s, a.ok, ws, b->F);
     }
-    return check_launch("decode final");
+    return check_launch("decode (group) final");
 }
 
-// mode: 0 per-pass launches, 1 persistent frame-per-workgroup, 2 grid
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws, int group_wgs)
+{
+    const bool wu = wave_uniform(b);
+    if constexpr (MAXD > 8 || sizeof(M) == 8) {
+        if (wu) return launch_group<M, S, ALGO, MAXD, 512, true>(b, a, s, ws, group_wgs);
+        return launch_group<M, S, ALGO, MAXD, 512, false>(b, a, s, ws, group_wgs);
+    } else {
+        if (wu) return launch_group<M, S, ALGO, MAXD, 1024, true>(b, a, s, ws, group_wgs);
+        return launch_group<M, S, ALGO, MAXD, 512, false>(b, a, s, ws, group_wgs);
+    }
+}
+
+// mode: 0 per-pass launches, 1 persistent frame-per-workgroup, 2 frame groups
 template <typename M, typename S, int ALGO>
 static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, int mode, int32_t* queue,
                                int32_t* gridws, const LaunchShape& sh)
@@ -1308,9 +1392,9 @@ static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, b
         return run_frames<M, S, ALGO, 32>(b, a, queue, s, sh);
     }
     if (mode == 2) {
-        if (b->max_row_deg <= 8) return run_grid<M, S, ALGO, 8>(b, a, s, gridws);
-        if (b->max_row_deg <= 16) return run_grid<M, S, ALGO, 16>(b, a, s, gridws);
-        return run_grid<M, S, ALGO, 32>(b, a, s, gridws);
+        if (b->max_row_deg <= 8) return run_group<M, S, ALGO, 8>(b, a, s, gridws, sh.group_wgs);
+        if (b->max_row_deg <= 16) return run_group<M, S, ALGO, 16>(b, a, s, gridws, sh.group_wgs);
+        return run_group<M, S, ALGO, 32>(b, a, s, gridws, sh.group_wgs);
     }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);
@@ -1343,22 +1427,13 @@ static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
     off = align256(off + size_t(b->F) * 8);
     w.queue = off;              // persistent decoder's frame queue
     off = align256(off + 4);
-    w.grid = off;               // grid schedule: error flag, XCD tickets, [F][2] barrier words
-    off = align256(off + 16 + 4 * kXcds + size_t(b->F) * 8);
+    w.grid = off;               // group schedule: see k_group_qc
+    off = align256(off + kGroupWsBytes);
     w.total = off;
     return w;
 }
 
-// The grid schedule needs packed tables for every code of the batch.
-static inline bool packed_tables(const cvr_batch_s* b)
-{
-    if (!b->all_qc) return false;
-    for (const cvr_code_t c : b->codes)
-        if (!c->dev.qrow_pk || !c->dev.qcol_pk) return false;
-    return true;
-}
-
-// The persistent path needs a quasi-cyclic batch whose protograph tables fit in LDS.
+// The persistent and group paths need a quasi-cyclic batch whose protograph tables fit in LDS.
 static inline bool frames_fit(const cvr_batch_s* b)
 {
     if (!b->all_qc) return false;

@@ -123,9 +123,6 @@ struct cvr_batch_s {
     cvr::DevCode* d_codes = nullptr;
     cvr::DevFrame* d_frames = nullptr;
     int32_t* d_order = nullptr;           // processing order of the persistent decoder: largest frames first
-    int32_t* d_qcn_off = nullptr;         // [F + 1] first QC row tile of each frame
-    int32_t* d_qvn_off = nullptr;         // [F + 1] first QC variable tile of each frame
-    int32_t max_frame_tiles = 0;          // most QC row or variable tiles of one frame
     cvr::Tile* d_cn_tiles = nullptr;     // generic rows
     cvr::Tile* d_vn_tiles = nullptr;     // generic variables
     cvr::Tile* d_qcn_tiles = nullptr;    // QC rows (within a block row)

@@ -25,7 +25,6 @@
 
 namespace cvr {
 
-constexpr int kGradThreads = 512;
 constexpr int kGradTypes = 4;
 constexpr int kGradMaxT = 128;
 
@@ -463,7 +462,7 @@ extern "C" cvr_status nms_unrolled_fwd(cvr_batch_t batch, int32_t T, int32_t ckp
     a.ckpt_stride = batch->total_E;
     a.ckpt_every = ckpt_every;
     return decode_f32_nms(batch, a, hipStream_t(stream), true, 1, reinterpret_cast<int32_t*>(dws + w.queue),
-                          reinterpret_cast<int32_t*>(dws + w.grid), LaunchShape{1024, 0, 0});
+                          reinterpret_cast<int32_t*>(dws + w.grid), LaunchShape{1024, 0, 0, 0});
 }
 
 extern "C" cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckpt_every, const float* weights,

@@ -93,11 +93,12 @@ def test_slice_stage_sp_fp32_qc(j):
     p = api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32, schedule=api.SCHED_PERSISTENT)
     code = api.Code.from_qc(qc)
     res = _decode_gpu(code, F, L, syn, p, trace=True)
-    # 16 frames: the default schedule runs the per-pass kernels; bit-identical
-    res_auto = _decode_gpu(code, F, L, syn, api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32),
-                           trace=True)
-    for k in ("bits", "post", "iters", "ok", "trace"):
-        np.testing.assert_array_equal(res[k], res_auto[k])
+    # 16 frames: the default schedule runs frame groups; every schedule is bit-identical
+    for sched in (api.SCHED_AUTO, api.SCHED_PASSES):
+        other = _decode_gpu(code, F, L, syn, api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32,
+                                                        schedule=sched), trace=True)
+        for k in ("bits", "post", "iters", "ok", "trace"):
+            np.testing.assert_array_equal(res[k], other[k])
     Ft = 4
     ref = oracle.decode(csr, L[:Ft], syn[:Ft], algo=oracle.SP, max_iter=100, trace=True)
     sub = {k: (v.reshape(F, -1)[:Ft] if k in ("bits",) else v[:Ft]) for k, v in res.items() if v is not None and k != "post"}
@@ -121,19 +122,21 @@ def test_layouts_and_schedules_are_bit_identical():
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8),
                  dict(algo=api.NMS, store=api.F32, alpha=0.7)):
         runs = []
-        # (code, schedule, workgroup, min waves, LDS posterior cache KiB)
-        for code, sched, wg, mw, lk in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, 0),
-                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, -1),
-                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 0, 5),
-                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 0, 0),
-                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 8, 0),
-                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 0),
-                                        (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 150),
-                                        (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0, 0),
-                                        (api.Code.from_qc(qc), api.SCHED_GRID, 0, 0, 0),
-                                        (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0)):
+        # (code, schedule, workgroup, min waves, LDS posterior cache KiB, workgroups per frame)
+        for code, sched, wg, mw, lk, gw in ((api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, 0, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 0, 0, -1, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 0, 5, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 0, 0, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 512, 8, 0, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 0, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PERSISTENT, 1024, 8, 150, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_PASSES, 0, 0, 0, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 0, 0, 0),
+                                            (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 0, 0, 1),
+                                            (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 0, 0, 3),
+                                            (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0, 0)):
             p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, min_waves=mw,
-                           lds_cache_kb=lk, **base)
+                           lds_cache_kb=lk, group_wgs=gw, **base)
             runs.append(_decode_gpu(code, F, L, syn, p, trace=True))
         for r in runs[1:]:
             for k in ("bits", "post", "iters", "ok", "trace"):
@@ -147,7 +150,7 @@ def test_persistent_schedule_rejects_explicit_codes():
         _decode_gpu(api.Code.from_csr(csr), 2, np.zeros((2, 1024)), None, p)
 
 
-@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GRID])
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GROUP])
 @pytest.mark.parametrize("store", [api.F32, api.F16])
 def test_nms_bit_exact_against_binary32_oracle(store, sched):
     """Min-sum uses only +, -, x, min and the binary16 rounding: with the oracle
@@ -194,14 +197,33 @@ def test_nms_uniform_weights_equal_alpha():
         np.testing.assert_array_equal(a[k], b[k])
 
 
+@pytest.mark.parametrize("gw", [0, 2, 5])
+def test_group_schedule_frames_from_queue(gw):
+    """More frames than groups (37 frames: a ragged count over the 8 XCDs) so
+    that each group takes several frames from its XCD's queue: the results
+    equal the persistent decoder's bit for bit, trace included."""
+    print(f"[decode group queue gw={gw}]", flush=True)
+    n, F = 8192, 37
+    qc, csr, L, syn, _ = _slice_stage(2, n, F, seed=123)
+    code = api.Code.from_qc(qc)
+    for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8)):
+        ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_PERSISTENT, **base),
+                          trace=True)
+        got = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_GROUP,
+                                                      group_wgs=gw, **base), trace=True)
+        for k in ("bits", "post", "iters", "ok", "trace"):
+            np.testing.assert_array_equal(np.nan_to_num(ref[k], nan=1e30), np.nan_to_num(got[k], nan=1e30))
+        assert ref["ok"].any() and ref["iters"].min() > 0
+
+
 @pytest.mark.parametrize("sizes,sched,lds_kb", [
     ((4096, 8192, 4096), api.SCHED_PERSISTENT, 0),        # Z = 32 / 64: lane-varying block rows
     ((8192, 16384, 8192), api.SCHED_PERSISTENT, 0),       # Z % 64 == 0: wave-uniform kernel
     ((8192, 16384, 8192), api.SCHED_PERSISTENT, 20),      # a few cached columns, a different number per code
     ((8192, 16384, 8192), api.SCHED_PERSISTENT, -1),
     ((4096, 8192, 4096), api.SCHED_PASSES, 0),
-    ((4096, 8192, 4096), api.SCHED_GRID, 0),             # lane-varying block rows
-    ((8192, 16384, 8192), api.SCHED_GRID, 0),            # wave-uniform
+    ((4096, 8192, 4096), api.SCHED_GROUP, 0),             # lane-varying block rows
+    ((8192, 16384, 8192), api.SCHED_GROUP, 0),            # wave-uniform
 ])
 def test_ragged_batch_mixed_codes_and_gaps(sizes, sched, lds_kb):
     """Frames of different codes and lengths at scattered offsets: each frame
@@ -242,7 +264,7 @@ def test_ragged_batch_mixed_codes_and_gaps(sizes, sched, lds_kb):
         assert int(out["iters"][i]) == int(solo["iters"][0])
 
 
-@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GRID])
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GROUP])
 def test_failure_injection_and_edge_cases(sched):
     print(f"[decode edge cases schedule={sched}]", flush=True)
     qc = inputs.lambda_half_rate_spec(4096)
@@ -290,7 +312,7 @@ def test_repeat_runs_are_bit_identical():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GRID])
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_GROUP])
 def test_graph_capture_replays_match_eager(sched):
     """The decode (queue reset + persistent kernel, or the per-pass launches;
     no memset) captured in a HIP graph: every replay, with unrelated eager work
