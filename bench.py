@@ -245,16 +245,21 @@ def recon(args, wl, dev):
     tuned = None
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     persistent = args.schedule == "persistent" or (args.schedule == "auto" and batches[2].F >= cus)
-    if not args.no_tune and args.wg == 0 and persistent:
+    group = args.schedule == "group" or (args.schedule == "auto" and batches[2].F < cus)
+    if not args.no_tune and ((persistent and args.wg == 0) or (group and args.min_waves == 0 and args.group_wgs == 0)):
         # pick the launch shape on this workload's own slice-2 decode (untimed)
         step()
         api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
-        from paper_2108_08418_amd.tune import tune_decode
-        best, tim = tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2])
+        from paper_2108_08418_amd import tune
+        knobs = tune.KNOBS if persistent else tune.GROUP_KNOBS
+        best, tim = tune.tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2],
+                                     candidates=tune.CANDIDATES if persistent else tune.GROUP_CANDIDATES, knobs=knobs)
         for pp in {id(v): v for v in (params, *stage_params.values())}.values():
-            pp.wg_threads, pp.min_waves, pp.lds_cache_kb = best
-        args.wg, args.min_waves, args.lds_cache_kb = best
-        tuned = {f"{k[0]}w{k[1]}c{k[2]}": round(v, 3) for k, v in tim.items()}
+            for k, v in zip(knobs, best):
+                setattr(pp, k, v)
+        for k, v in zip(knobs, best):
+            setattr(args, "wg" if k == "wg_threads" else k, v)
+        tuned = {"/".join(f"{k}={v}" for k, v in zip(knobs, c)): round(t, 3) for c, t in tim.items()}
         print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -303,7 +308,7 @@ def recon(args, wl, dev):
             inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
                     f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
         else:                                   # group schedule (workgroups per frame on one XCD)
-            inst = f"void cvr::k_group_qc<{mt}, {0 if algo == api.SP else 1}, 8, 1024, true>"
+            inst = f"void cvr::k_group_qc<{mt}, {0 if algo == api.SP else 1}, 8, 1024, true, {8 if args.min_waves == 8 else 1}>"
         roof_kernel = inst
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
@@ -375,7 +380,6 @@ def ragged(args, wl, dev):
     """Uneven batch: every sub-block of the batch in one decode call."""
     import torch
 
-    import oracle
     from paper_2108_08418_amd import api, inputs
 
     sizes, counts = wl["sizes"], wl["counts"]
@@ -424,7 +428,7 @@ def ragged(args, wl, dev):
         best, tim = tune_decode(batch, params, llr, syn, ws, out)
         params.wg_threads, params.min_waves, params.lds_cache_kb = best
         args.wg, args.min_waves, args.lds_cache_kb = best
-        tuned = {f"{k[0]}w{k[1]}c{k[2]}": round(v, 3) for k, v in tim.items()}
+        tuned = {f"wg_threads={k[0]}/min_waves={k[1]}/lds_cache_kb={k[2]}": round(v, 3) for k, v in tim.items()}
         print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()

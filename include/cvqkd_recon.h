@@ -192,14 +192,16 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
  *            compiler choose.  Binary64 math and batches with a check row of
- *            more than 8 edges always run 512 threads.
+ *            more than 8 edges always run 512 threads.  The group schedule
+ *            runs 1024 threads (512 in those cases) and takes min_waves too:
+ *            8 puts two workgroups on each compute unit.
  *  lds_cache_kb  posteriors of the highest-degree block columns that the
  *            persistent decoder keeps in LDS (results unchanged): 0 = as much
  *            as fits without fewer resident workgroups, -1 = none, > 0 = that
  *            many KiB (capped by the LDS size).
  *  group_wgs workgroups per frame of the group schedule (results unchanged):
- *            0 = the compute units of an XCD divided by its frames, at least 1;
- *            capped by the compute units of an XCD.                          */
+ *            0 = the workgroups an XCD holds divided by its frames, at least
+ *            1; capped by the workgroups an XCD holds.                        */
 enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2, CVR_SCHED_GROUP = 3 };
 
 typedef struct {

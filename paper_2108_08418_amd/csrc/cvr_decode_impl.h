@@ -1020,8 +1020,9 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, in
 // the next place of that XCD: places [g G, (g + 1) G) form group g.  Each
 // group takes the XCD's frames (order[q * 8 + XCD], q = 0, 1, ...: largest
 // first) from that XCD's queue and decodes them together; nothing depends on
-// how the dispatcher numbers workgroups across XCDs.  The launch has one
-// workgroup per CU (all resident) and the same number of places per XCD.
+// how the dispatcher numbers workgroups across XCDs.  The launch has as many
+// workgroups per CU as the launch bounds guarantee resident (MINW waves per
+// SIMD) and the same number of places per XCD.
 // Group workspace, in 32-bit words:
 //   [0] error flag (1: a barrier wait gave up; 2: an XCC_ID outside 0..7)
 //   [4, 12) place tickets, [12, 20) frame queues, one per XCD
@@ -1036,8 +1037,8 @@ struct GroupArgs {
     int32_t F, G, NG;         // frames, workgroups per group, groups per XCD
 };
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU>
-__global__ __launch_bounds__(NT, 1) void k_group_qc(DecArgs a, LdsMap lm, GroupArgs g)
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, GroupArgs g)
 {
     extern __shared__ __align__(16) int32_t dsm[];
     __shared__ int32_t s_place[2];
@@ -1322,13 +1323,13 @@ static cvr_status run_frames(const cvr_batch_s* b, DecArgs a, int32_t* queue, hi
     }
 }
 
-// Group schedule (QC codes whose tables fit in LDS): one workgroup per CU,
-// G per frame (group_wgs, or as many as the frames per XCD leave), at most
-// one group per frame of the XCD.
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU>
+// Group schedule (QC codes whose tables fit in LDS): the workgroups per CU
+// that the launch bounds guarantee, G per frame (group_wgs, or as many as the
+// frames per XCD leave), at most one group per frame of the XCD.
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
 static cvr_status launch_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws, int group_wgs)
 {
-    auto kern = k_group_qc<M, S, ALGO, MAXD, NT, WU>;
+    auto kern = k_group_qc<M, S, ALGO, MAXD, NT, WU, MINW>;
     static int lds_blk = 0, static_lds = 0;
     if (lds_blk == 0) {
         lds_blk = std::min(device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 65536),
@@ -1345,7 +1346,10 @@ static cvr_status launch_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, i
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, size_t(dyn)) != hipSuccess || per_cu < 1)
         return fail(CVR_EUNSUPPORTED, "decode (group): a workgroup does not fit on a CU");
-    const int cap = std::max(1, device_cus() / kXcds);           // places per XCD
+    // the runtime's count can exceed what fits (it does not see the scalar
+    // register limit); the launch bounds guarantee MINW waves on each of the 4 SIMDs
+    per_cu = std::min(per_cu, std::max(1, MINW * 4 * 64 / NT));
+    const int cap = std::max(1, device_cus() / kXcds) * per_cu;  // places per XCD
     const int fx = (b->F + kXcds - 1) / kXcds;                   // frames per XCD
     const int G = group_wgs > 0 ? std::min(group_wgs, cap) : std::max(1, cap / std::min(fx, cap));
     const int NG = std::min(cap / G, fx);
@@ -1369,15 +1373,16 @@ static cvr_status launch_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, i
 }
 
 template <typename M, typename S, int ALGO, int MAXD>
-static cvr_status run_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws, int group_wgs)
+static cvr_status run_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int32_t* ws, const LaunchShape& sh)
 {
     const bool wu = wave_uniform(b);
     if constexpr (MAXD > 8 || sizeof(M) == 8) {
-        if (wu) return launch_group<M, S, ALGO, MAXD, 512, true>(b, a, s, ws, group_wgs);
-        return launch_group<M, S, ALGO, MAXD, 512, false>(b, a, s, ws, group_wgs);
+        if (wu) return launch_group<M, S, ALGO, MAXD, 512, true, 1>(b, a, s, ws, sh.group_wgs);
+        return launch_group<M, S, ALGO, MAXD, 512, false, 1>(b, a, s, ws, sh.group_wgs);
     } else {
-        if (wu) return launch_group<M, S, ALGO, MAXD, 1024, true>(b, a, s, ws, group_wgs);
-        return launch_group<M, S, ALGO, MAXD, 512, false>(b, a, s, ws, group_wgs);
+        if (!wu) return launch_group<M, S, ALGO, MAXD, 512, false, 1>(b, a, s, ws, sh.group_wgs);
+        if (sh.min_waves == 8) return launch_group<M, S, ALGO, MAXD, 1024, true, 8>(b, a, s, ws, sh.group_wgs);
+        return launch_group<M, S, ALGO, MAXD, 1024, true, 1>(b, a, s, ws, sh.group_wgs);
     }
 }
 
@@ -1392,9 +1397,9 @@ static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, b
         return run_frames<M, S, ALGO, 32>(b, a, queue, s, sh);
     }
     if (mode == 2) {
-        if (b->max_row_deg <= 8) return run_group<M, S, ALGO, 8>(b, a, s, gridws, sh.group_wgs);
-        if (b->max_row_deg <= 16) return run_group<M, S, ALGO, 16>(b, a, s, gridws, sh.group_wgs);
-        return run_group<M, S, ALGO, 32>(b, a, s, gridws, sh.group_wgs);
+        if (b->max_row_deg <= 8) return run_group<M, S, ALGO, 8>(b, a, s, gridws, sh);
+        if (b->max_row_deg <= 16) return run_group<M, S, ALGO, 16>(b, a, s, gridws, sh);
+        return run_group<M, S, ALGO, 32>(b, a, s, gridws, sh);
     }
     if (b->max_row_deg <= 8) return run_decode<M, S, ALGO, 8>(b, a, s, qc);
     if (b->max_row_deg <= 16) return run_decode<M, S, ALGO, 16>(b, a, s, qc);

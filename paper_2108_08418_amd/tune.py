@@ -1,9 +1,11 @@
-"""Autotuner of the persistent decoder's launch shape.
+"""Autotuner of the decoder's launch shape.
 
-Times ``ldpc_decode_batch`` for every (workgroup size, minimum waves per
-SIMD, LDS posterior cache) candidate on the caller's own batch and inputs with HIP events on the launch stream (the library's launch
-timing) and returns the fastest.  The knobs change the launch configuration
-only, never the results.
+Times ``ldpc_decode_batch`` for every candidate on the caller's own batch and
+inputs with HIP events on the launch stream (the library's launch timing) and
+returns the fastest.  Persistent schedule: (workgroup size, minimum waves per
+SIMD, LDS posterior cache); group schedule: (minimum waves per SIMD, which
+sets the workgroups per CU, and workgroups per frame).  The knobs change the
+launch configuration only, never the results.
 """
 from __future__ import annotations
 
@@ -13,16 +15,20 @@ from . import api
 # 150 = nearly all of a CU's LDS (one workgroup per CU)
 CANDIDATES = [(512, 0, 0), (1024, 0, 0), (512, 8, 0), (1024, 8, 0), (1024, 8, -1), (1024, 0, 150)]
 KNOBS = ("wg_threads", "min_waves", "lds_cache_kb")
+# group_wgs: 0 = the workgroups an XCD holds divided by its frames
+GROUP_CANDIDATES = [(0, 0), (8, 0), (0, 8)]
+GROUP_KNOBS = ("min_waves", "group_wgs")
 
 
-def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, candidates=CANDIDATES):
-    """Returns (best candidate as a tuple in KNOBS order, {candidate: ms per decode})."""
+def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, candidates=CANDIDATES,
+                knobs=KNOBS):
+    """Returns (best candidate as a tuple in ``knobs`` order, {candidate: ms per decode})."""
     import torch
     timings = {}
-    saved = tuple(getattr(params, k) for k in KNOBS)
+    saved = tuple(getattr(params, k) for k in knobs)
     try:
         for cand in candidates:
-            for k, v in zip(KNOBS, cand):
+            for k, v in zip(knobs, cand):
                 setattr(params, k, v)
             api.ldpc_decode_batch(batch, params, llr, syndrome, workspace=workspace, out=out)   # warm
             torch.cuda.synchronize()
@@ -35,7 +41,7 @@ def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, 
             ms, cnt = api.profile_read(api.PROF_FRAMES, reset=True)
             timings[tuple(cand)] = ms / max(cnt, 1)
     finally:
-        for k, v in zip(KNOBS, saved):
+        for k, v in zip(knobs, saved):
             setattr(params, k, v)
         api.profile_enable(False)
     best = min(timings, key=timings.get)

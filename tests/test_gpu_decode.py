@@ -134,6 +134,7 @@ def test_layouts_and_schedules_are_bit_identical():
                                             (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 0, 0, 0),
                                             (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 0, 0, 1),
                                             (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 0, 0, 3),
+                                            (api.Code.from_qc(qc), api.SCHED_GROUP, 0, 8, 0, 0),
                                             (api.Code.from_csr(csr), api.SCHED_PASSES, 0, 0, 0, 0)):
             p = api.Params(max_iter=40, math=api.F32, schedule=sched, wg_threads=wg, min_waves=mw,
                            lds_cache_kb=lk, group_wgs=gw, **base)
@@ -197,12 +198,12 @@ def test_nms_uniform_weights_equal_alpha():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("gw", [0, 2, 5])
-def test_group_schedule_frames_from_queue(gw):
+@pytest.mark.parametrize("gw,mw", [(0, 0), (2, 0), (5, 0), (0, 8), (3, 8)])
+def test_group_schedule_frames_from_queue(gw, mw):
     """More frames than groups (37 frames: a ragged count over the 8 XCDs) so
     that each group takes several frames from its XCD's queue: the results
     equal the persistent decoder's bit for bit, trace included."""
-    print(f"[decode group queue gw={gw}]", flush=True)
+    print(f"[decode group queue gw={gw} mw={mw}]", flush=True)
     n, F = 8192, 37
     qc, csr, L, syn, _ = _slice_stage(2, n, F, seed=123)
     code = api.Code.from_qc(qc)
@@ -210,10 +211,45 @@ def test_group_schedule_frames_from_queue(gw):
         ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_PERSISTENT, **base),
                           trace=True)
         got = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_GROUP,
-                                                      group_wgs=gw, **base), trace=True)
+                                                      group_wgs=gw, min_waves=mw, **base), trace=True)
         for k in ("bits", "post", "iters", "ok", "trace"):
             np.testing.assert_array_equal(np.nan_to_num(ref[k], nan=1e30), np.nan_to_num(got[k], nan=1e30))
         assert ref["ok"].any() and ref["iters"].min() > 0
+
+
+def test_degree_one_variables_all_schedules():
+    """A code with degree-1 variables (the MET code: 48 of 64 block columns):
+    every schedule and launch shape, with and without a trace and the
+    posterior output, with and without the LDS posterior cache, gives the
+    per-pass kernels' results bit for bit."""
+    print("[decode degree-1 variables]", flush=True)
+    qc = inputs.met_low_rate_spec(4096)
+    csr = qc.to_csr()
+    code = api.Code.from_qc(qc)
+    F = 12
+    bits = inputs.random_bits((F, qc.n), seed=31)
+    llr = inputs.bpsk_llr(bits, 1.0 / 0.16, seed=32).astype(np.float32)      # SNR 0.16
+    syn, _ = oracle.syndrome(csr, bits)
+    for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.75)):
+        ref = _decode_gpu(code, F, llr, syn, api.Params(max_iter=40, math=api.F32, schedule=api.SCHED_PASSES, **base),
+                          trace=True)
+        assert ref["ok"].any() and (ref["iters"] > 0).all()
+        for sched, lk, mw in ((api.SCHED_PERSISTENT, -1, 0), (api.SCHED_PERSISTENT, 150, 0),
+                              (api.SCHED_PERSISTENT, 0, 8), (api.SCHED_GROUP, 0, 0), (api.SCHED_GROUP, 0, 8)):
+            p = api.Params(max_iter=40, math=api.F32, schedule=sched, lds_cache_kb=lk, wg_threads=1024,
+                           min_waves=mw, **base)
+            # with a trace (plain kernels), with the posteriors, with decisions only
+            got = _decode_gpu(code, F, llr, syn, p, trace=True)
+            for k in ("bits", "post", "iters", "ok", "trace"):
+                np.testing.assert_array_equal(np.nan_to_num(ref[k], nan=1e30), np.nan_to_num(got[k], nan=1e30))
+            got = _decode_gpu(code, F, llr, syn, p)
+            for k in ("bits", "post", "iters", "ok"):
+                np.testing.assert_array_equal(np.nan_to_num(ref[k], nan=1e30), np.nan_to_num(got[k], nan=1e30))
+            batch = api.Batch.uniform(code, F)
+            out = api.ldpc_decode_batch(batch, p, _g(llr.reshape(-1)), _g(syn.reshape(-1)), want_post=False)
+            torch.cuda.synchronize()
+            for k in ("bits", "iters", "ok"):
+                np.testing.assert_array_equal(ref[k], out[k].cpu().numpy())
 
 
 @pytest.mark.parametrize("sizes,sched,lds_kb", [
