@@ -355,6 +355,9 @@ def recon(args, wl, dev):
             "traffic_over_algorithmic": (traffic / (launch_bytes / launches)) if (traffic and launches) else None,
             "avg_launch_us": 1e3 * launch_ms / launches if launches else None,
             "algorithmic_bytes_per_launch": launch_bytes / launches if launches else None,
+            "note": ("group schedule: the decoder state stays in the L2 / Infinity Cache (HBM traffic far "
+                     "below the algorithmic bytes), so an iteration is bound by barrier and pass latency, "
+                     "not HBM" if (per_ms > 0 and not persistent) else None),
         },
         "decode_iteration": {
             "algorithmic_GBs": iter_gbs,
