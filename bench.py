@@ -83,6 +83,17 @@ def parse():
     return ap.parse_args()
 
 
+# The paper's own measurements (Sec. V), other hardware and codes: context only.
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA GTX 1060, one decoder per GPU thread",
+    "slice_bits_per_s": 1.6e7,
+    "edge_updates_per_s": 4.46e7,
+    "source": "Sec. V: 310 s to decode the m N = 5e9 slice bits of N = 1e9 at N_R = 1e9; "
+              "3.2e-9 s per operation at 7 operations per edge and iteration (Sec. III-C), "
+              "i.e. 1 / (7 x 3.2e-9) edge updates per second",
+}
+
+
 def csrc_hash() -> str:
     """Hash of the sources the decoder kernels are built from (a recorded
     traffic figure is valid while it is unchanged)."""
@@ -359,6 +370,7 @@ def recon(args, wl, dev):
                      "below the algorithmic bytes), so an iteration is bound by barrier and pass latency, "
                      "not HBM" if (per_ms > 0 and not persistent) else None),
         },
+        "paper_context": PAPER_CONTEXT,
         "decode_iteration": {
             "algorithmic_GBs": iter_gbs,
             "frac_of_hbm_peak": (iter_gbs / HBM_PEAK_GBS) if iter_gbs else None,
