@@ -637,46 +637,53 @@ __device__ __forceinline__ M var_sum_any(const FrameCtx<M, S>& c, int qa, int dv
 // ---------------------------------------------------------------------------
 // frame groups: G workgroups resident on one XCD decode one frame together
 // ---------------------------------------------------------------------------
-// The group shares the XCD's L2, so its barrier is a pair of L2 atomics and
-// the loads of data that other members wrote are device-scope loads that read
-// that L2 (ldc<true>); no cache is written back or invalidated.
+// The group shares the XCD's L2, so its barrier is one L2 atomic per member
+// and the loads of data that other members wrote are device-scope loads that
+// read that L2 (ldc<true>); no cache is written back or invalidated.
 constexpr int kXcds = 8;
 
 struct GroupCtx {
     int member, G;
-    uint32_t* bar;      // [2] arrivals (monotonic), generation
-    int32_t* unsat;     // [2] unsatisfied checks after iterations t with t & 1 = 0 / 1
-    int32_t* err;       // set to 1 when a barrier wait gave up
-    uint32_t gen;       // barriers passed so far
+    uint64_t* word;         // arrivals (low half) and added counts (high half), both cumulative
+    int32_t* err;           // set to 1 when a barrier wait gave up
+    uint32_t gen;           // barriers passed so far
+    uint32_t unsat_seen;    // high half at the last check-pass barrier
 };
 
-// Barrier of the G workgroups of a group.  Each wave first waits for its own
-// stores to complete (they are then in the L2), the workgroup meets, and one
-// thread arrives; the G-th arrival of a generation advances it, the others
-// wait for that, bounded in wall-clock time (0.2 s; once a wait has given up
-// no later one waits, so the launch always ends, and the frames are then
-// reported as not decoded).
-__device__ __forceinline__ void group_sync(GroupCtx& g)
+// Barrier of the G workgroups of a group, which also sums `add` over them.
+// Each wave first waits for its own stores to complete (they are then in the
+// L2), the workgroup meets, and one thread adds (add << 32) + 1 to the group
+// word and reads it until the arrivals of this generation are complete,
+// bounded in wall-clock time (0.2 s; once a wait has given up no later one
+// waits, so the launch always ends, and the frames are then reported as not
+// decoded).  Returns the high half read then: every member's adds up to this
+// barrier.  A member that has passed it can arrive at the next barrier first,
+// so a barrier that follows one with adds must add 0.
+__device__ __forceinline__ uint32_t group_sync(GroupCtx& g, uint32_t add = 0)
 {
+    __shared__ uint32_t s_hi;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t arrived = atomicAdd(&g.bar[0], 1u);
-        if (arrived == (g.gen + 1u) * uint32_t(g.G) - 1u) {
-            __hip_atomic_store(&g.bar[1], g.gen + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (__hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        __hip_atomic_fetch_add(g.word, (uint64_t(add) << 32) | 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (g.gen + 1u) * uint32_t(g.G);
+        uint64_t v = __hip_atomic_load(g.word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (int32_t(uint32_t(v) - target) < 0 && __hip_atomic_load(g.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&g.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g.gen) {
+            do {
                 __builtin_amdgcn_s_sleep(1);
+                v = __hip_atomic_load(g.word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (wall_clock64() - t0 > 20000000ull) {       // 0.2 s of the 100 MHz counter
                     atomicExch(g.err, 1);
                     break;
                 }
-            }
+            } while (int32_t(uint32_t(v) - target) < 0);
         }
+        s_hi = uint32_t(v >> 32);
     }
     ++g.gen;
     __syncthreads();
+    return s_hi;
 }
 
 // One frame, all iterations.  With WU every wavefront's rows (variables) share
@@ -785,11 +792,11 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         __syncthreads();
         int u = s_unsat[t & 1];
         if constexpr (GRP) {
-            // the group's count is final after the barrier; its other slot was
-            // last read before the previous barrier, so the lead clears it
-            if (tid == 0 && u) atomicAdd(&gc->unsat[t & 1], u);
-            group_sync(*gc);
-            u = ldc<true>(&gc->unsat[t & 1]);
+            // the group's count: the barrier's sum since the previous check
+            // pass (the barriers in between add nothing)
+            const uint32_t hi = group_sync(*gc, uint32_t(u));
+            u = int(hi - gc->unsat_seen);
+            gc->unsat_seen = hi;
         }
         if ((a.early_stop && u == 0) || t >= a.T) {
             if (tid == 0 && lead) {
@@ -799,9 +806,6 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
             break;
         }
         if (tid == 0) s_unsat[(t + 1) & 1] = 0;
-        if constexpr (GRP) {
-            if (tid == 0 && lead) __hip_atomic_store(&gc->unsat[(t + 1) & 1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         // the next iteration's weights: every read of s_w for iteration t
         // happened before the barrier above
         if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
@@ -1026,7 +1030,7 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, in
 // Group workspace, in 32-bit words:
 //   [0] error flag (1: a barrier wait gave up; 2: an XCC_ID outside 0..7)
 //   [4, 12) place tickets, [12, 20) frame queues, one per XCD
-//   [32 + 8 g, ...) group g: arrivals, generation, unsatisfied [2], frame
+//   [32 + 8 g, ...) group g: barrier word (64 bits), [+ 4] frame
 constexpr int kGwErr = 0, kGwTicket = 4, kGwQueue = 12, kGwGroups = 32, kGwGroupWords = 8;
 constexpr int kMaxGroups = 1024;
 constexpr size_t kGroupWsBytes = size_t(kGwGroups + kMaxGroups * kGwGroupWords) * 4;
@@ -1062,17 +1066,15 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
     const int gi = place / g.G;
     if (gi >= g.NG) return;                                  // a surplus place
     int32_t* gw = g.ws + kGwGroups + (xcd * g.NG + gi) * kGwGroupWords;
-    GroupCtx gc{place % g.G, g.G, reinterpret_cast<uint32_t*>(gw), gw + 2, err, 0u};
+    GroupCtx gc{place % g.G, g.G, reinterpret_cast<uint64_t*>(gw), err, 0u, 0u};
     int cur = -1;
     for (;;) {
         if (gc.member == 0 && tid == 0) {
-            // every member read the previous frame and its counts before the
-            // barrier that ended that frame
+            // every member read the previous frame's index before the barrier
+            // that ended that frame
             const int q = atomicAdd(g.ws + kGwQueue + xcd, 1);
             const int64_t o = int64_t(q) * kXcds + xcd;
             const int f = o < g.F ? g.order[o] : g.F;
-            __hip_atomic_store(gw + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(gw + 3, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(gw + 4, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         group_sync(gc);
