@@ -499,48 +499,70 @@ struct FrameCtx {
     float alpha, clamp;
 };
 
-// Check row k of the block row whose table entries start at q0, with exactly D
-// edges (D and the entries wave-uniform): the D posteriors and, for t > 0, the
-// D stored messages are loaded before any arithmetic; the code is straight-line.
-// Returns 1 when the row's syndrome test fails on Lpost(t).
-template <typename M, typename S, int ALGO, int D, bool WU, bool CACHE, bool COH = false>
-__device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k, int sraw)
+// Check rows k[0..R) of the block row whose table entries start at q0, with
+// exactly D edges (D and the entries wave-uniform): the R x D posteriors and,
+// for t > 0, the R x D stored messages are loaded before any arithmetic, so
+// they are in flight together; the code is straight-line.  Returns the number
+// of the R rows whose syndrome test fails on Lpost(t).
+template <typename M, typename S, int ALGO, int D, bool WU, bool CACHE, bool COH, int R>
+__device__ __forceinline__ int check_rows(const FrameCtx<M, S>& c, int q0, const int (&k)[R], const int (&sraw)[R])
 {
     int32_t e[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) e[q] = uni<WU>(c.s_row[q0 + q]);
-    M lr[D];
-    S mr[D];
+    M lr[R][D];
+    S mr[R][D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-        int uu = k + (e[q] & 0xffff);
-        uu = uu >= c.Z ? uu - c.Z : uu;
-        const int idx = ((e[q] >> 16) & 0x1ff) * c.Z + uu;
-        if (CACHE && (e[q] & kCached)) lr[q] = lds_read(c.s_post + idx);
-        else lr[q] = ldc<COH>(&at(c.Lp, uint32_t(idx)));
+    for (int h = 0; h < R; ++h) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            int uu = k[h] + (e[q] & 0xffff);
+            uu = uu >= c.Z ? uu - c.Z : uu;
+            const int idx = ((e[q] >> 16) & 0x1ff) * c.Z + uu;
+            if (CACHE && (e[q] & kCached)) lr[h][q] = lds_read(c.s_post + idx);
+            else lr[h][q] = ldc<COH>(&at(c.Lp, uint32_t(idx)));
+        }
     }
     if (c.t > 0) {
 #pragma unroll
-        for (int q = 0; q < D; ++q) mr[q] = ldc<COH>(&at(c.msg, uint32_t((q0 + q) * c.Z + k)));
+        for (int h = 0; h < R; ++h) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) mr[h][q] = ldc<COH>(&at(c.msg, uint32_t((q0 + q) * c.Z + k[h])));
+        }
     } else {
 #pragma unroll
-        for (int q = 0; q < D; ++q) mr[q] = S(0);      // c2v(0) = 0
-    }
-    M x[D];
-    int par = sraw & 1;
-    bool nan = false;
+        for (int h = 0; h < R; ++h) {
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-        par ^= (lr[q] < M(0)) ? 1 : 0;
-        nan |= (lr[q] != lr[q]);
-        x[q] = lr[q] - M(StoreT<S>::get(mr[q]));
+            for (int q = 0; q < D; ++q) mr[h][q] = S(0);      // c2v(0) = 0
+        }
     }
-    if (c.t < c.T) {
-        auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
-        auto emit = [&](int q, M v) { at(c.msg, uint32_t((q0 + q) * c.Z + k)) = StoreT<S>::put(v); };
-        check_rule<M, ALGO, D>(x, D, sraw & 1, M(c.clamp), weight, emit);
+    int bad = 0;
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+        M x[D];
+        int par = sraw[h] & 1;
+        bool nan = false;
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            par ^= (lr[h][q] < M(0)) ? 1 : 0;
+            nan |= (lr[h][q] != lr[h][q]);
+            x[q] = lr[h][q] - M(StoreT<S>::get(mr[h][q]));
+        }
+        if (c.t < c.T) {
+            auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
+            auto emit = [&](int q, M v) { at(c.msg, uint32_t((q0 + q) * c.Z + k[h])) = StoreT<S>::put(v); };
+            check_rule<M, ALGO, D>(x, D, sraw[h] & 1, M(c.clamp), weight, emit);
+        }
+        bad += par | (nan ? 1 : 0);
     }
-    return par | (nan ? 1 : 0);
+    return bad;
+}
+
+template <typename M, typename S, int ALGO, int D, bool WU, bool CACHE, bool COH = false>
+__device__ __forceinline__ int check_row(const FrameCtx<M, S>& c, int q0, int k, int sraw)
+{
+    const int kk[1] = {k}, ss[1] = {sraw};
+    return check_rows<M, S, ALGO, D, WU, CACHE, COH, 1>(c, q0, kk, ss);
 }
 
 // The same for any degree d <= MAXD (masked; entries may differ across lanes).
@@ -588,24 +610,39 @@ __device__ __forceinline__ int check_row_any(const FrameCtx<M, S>& c, int q0, in
     return par | (nan ? 1 : 0);
 }
 
-// Lch + the D messages of variable u of the block column whose table entries
-// start at qa, summed in table order (block rows ascending); D wave-uniform.
-template <typename M, typename S, int D, bool WU, bool COH = false>
-__device__ __forceinline__ M var_sum(const FrameCtx<M, S>& c, int qa, int u, M acc)
+// Lch + the D messages of variables u[0..R) of the block column whose table
+// entries start at qa, each summed in table order (block rows ascending); D
+// wave-uniform; the R x D loads are issued before any sum.
+template <typename M, typename S, int D, bool WU, bool COH, int R>
+__device__ __forceinline__ void var_sums(const FrameCtx<M, S>& c, int qa, const int (&u)[R], M (&acc)[R])
 {
     int32_t e[D];
-    S m[D];
+    S m[R][D];
 #pragma unroll
     for (int q = 0; q < D; ++q) e[q] = uni<WU>(c.s_col[qa + q]);
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-        int k = u - (e[q] & 0xffff);
-        k = k < 0 ? k + c.Z : k;
-        m[q] = ldc<COH>(&at(c.msg, uint32_t((e[q] >> 16) * c.Z + k)));
+    for (int h = 0; h < R; ++h) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            int k = u[h] - (e[q] & 0xffff);
+            k = k < 0 ? k + c.Z : k;
+            m[h][q] = ldc<COH>(&at(c.msg, uint32_t((e[q] >> 16) * c.Z + k)));
+        }
     }
 #pragma unroll
-    for (int q = 0; q < D; ++q) acc += M(StoreT<S>::get(m[q]));
-    return acc;
+    for (int h = 0; h < R; ++h) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) acc[h] += M(StoreT<S>::get(m[h][q]));
+    }
+}
+
+template <typename M, typename S, int D, bool WU, bool COH = false>
+__device__ __forceinline__ M var_sum(const FrameCtx<M, S>& c, int qa, int u, M acc)
+{
+    const int uu[1] = {u};
+    M a[1] = {acc};
+    var_sums<M, S, D, WU, COH, 1>(c, qa, uu, a);
+    return a[0];
 }
 
 // The same for any degree (8 loads at a time, masked).
@@ -717,6 +754,13 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
+    // group kernels at Z % 128 == 0 (and rows of at most 8 edges) give each
+    // thread two rows (variables) of one block row (column) per body, so twice
+    // the loads are in flight: the passes of a shared frame are latency-bound
+    constexpr bool kPairs = GRP && WU && MAXD <= 8;
+    const bool paired = kPairs && (Z % 128) == 0;
+    const int hz = Z >> 1;
+    const int hsh = zsh > 0 ? zsh - 1 : -1;
     const int32_t* s_rptr = dsm + lm.rptr;
     const int32_t* s_cptr = dsm + lm.cptr;
     FrameCtx<M, S> c;
@@ -764,7 +808,31 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         }
         // check pass: syndrome test of Lpost(t) and c2v(t+1)
         int bad = 0;
-        for (int r = first; r < m; r += stride) {
+        if constexpr (kPairs) {
+            if (paired) {
+                // rows k and k + Z/2 of a block row in one body
+                for (int p = first; p < (m >> 1); p += stride) {
+                    const int i = uni<WU>(hsh >= 0 ? (p >> hsh) : p / hz);
+                    const int k0 = p - i * hz;
+                    const int q0 = uni<WU>(s_rptr[i]);
+                    const int d = uni<WU>(s_rptr[i + 1]) - q0;
+                    const int kk[2] = {k0, k0 + hz};
+                    const int ss[2] = {syn ? int(at(syn, i * Z + k0)) : 0, syn ? int(at(syn, i * Z + k0 + hz)) : 0};
+                    switch (d) {
+                    case 1: bad += check_rows<M, S, ALGO, 1, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 2: bad += check_rows<M, S, ALGO, 2, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 3: bad += check_rows<M, S, ALGO, 3, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 4: bad += check_rows<M, S, ALGO, 4, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 5: bad += check_rows<M, S, ALGO, 5, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 6: bad += check_rows<M, S, ALGO, 6, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 7: bad += check_rows<M, S, ALGO, 7, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 8: bad += check_rows<M, S, ALGO, 8, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    default: break;
+                    }
+                }
+            }
+        }
+        for (int r = first; !paired && r < m; r += stride) {
             const int i = uni<WU>(zsh >= 0 ? (r >> zsh) : r / Z);
             const int k = r - i * Z;
             const int q0 = uni<WU>(s_rptr[i]);
@@ -810,7 +878,38 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         // happened before the barrier above
         if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
         // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows ascending
-        for (int v = first; v < n; v += stride) {
+        if constexpr (kPairs) {
+            if (paired) {
+                // variables u and u + Z/2 of a block column in one body
+                for (int p = first; p < (n >> 1); p += stride) {
+                    const int j = uni<WU>(hsh >= 0 ? (p >> hsh) : p / hz);
+                    const int u0 = p - j * hz;
+                    const int qa = uni<WU>(s_cptr[j]);
+                    const int dv = uni<WU>(s_cptr[j + 1]) - qa;
+                    const int uu[2] = {u0, u0 + hz};
+                    M acc[2] = {at(c.Lc, j * Z + u0), at(c.Lc, j * Z + u0 + hz)};
+                    switch (dv) {
+                    case 1: var_sums<M, S, 1, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 2: var_sums<M, S, 2, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 3: var_sums<M, S, 3, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 4: var_sums<M, S, 4, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 5: var_sums<M, S, 5, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 6: var_sums<M, S, 6, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 7: var_sums<M, S, 7, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 8: var_sums<M, S, 8, WU, GRP, 2>(c, qa, uu, acc); break;
+                    default:
+                        for (int h = 0; h < 2; ++h) acc[h] = var_sum_any<M, S, WU, GRP>(c, qa, dv, uu[h], acc[h]);
+                        break;
+                    }
+                    for (int h = 0; h < 2; ++h) {
+                        const int v = j * Z + uu[h];
+                        at(c.Lp, v) = acc[h];
+                        if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc[h];
+                    }
+                }
+            }
+        }
+        for (int v = first; !paired && v < n; v += stride) {
             const int j = column(v);
             const int uu = v - j * Z;
             const int qa = uni<WU>(s_cptr[j]);
@@ -838,7 +937,9 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         }
         sync();
     }
-    // hard decisions; cached posteriors go back to HBM
+    // hard decisions; cached posteriors go back to HBM.  In a group the last
+    // posteriors may come from another member (the paired bodies map threads
+    // differently), so they are read past this CU's L1.
     for (int v = first; v < n; v += stride) {
         const int j = column(v);
         const int slot = slot_of(j);
@@ -847,7 +948,7 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
             l = c.s_post[slot * Z + (v - j * Z)];
             at(c.Lp, v) = l;
         } else {
-            l = at(c.Lp, v);
+            l = ldc<GRP>(&at(c.Lp, v));
         }
         a.bits[fr.vn_off + v] = l < M(0) ? 1 : 0;
     }
@@ -1030,8 +1131,10 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, in
 // Group workspace, in 32-bit words:
 //   [0] error flag (1: a barrier wait gave up; 2: an XCC_ID outside 0..7)
 //   [4, 12) place tickets, [12, 20) frame queues, one per XCD
-//   [32 + 8 g, ...) group g: barrier word (64 bits), [+ 4] frame
-constexpr int kGwErr = 0, kGwTicket = 4, kGwQueue = 12, kGwGroups = 32, kGwGroupWords = 8;
+//   [64 + 64 g, ...) group g: barrier word (64 bits), [+ 4] frame; 256 bytes
+//   apart, so groups never share a cache line (with two groups of 16 on an
+//   XCD polling words in one line, a barrier took 3.3 us instead of 0.7 us)
+constexpr int kGwErr = 0, kGwTicket = 4, kGwQueue = 12, kGwGroups = 64, kGwGroupWords = 64;
 constexpr int kMaxGroups = 1024;
 constexpr size_t kGroupWsBytes = size_t(kGwGroups + kMaxGroups * kGwGroupWords) * 4;
 

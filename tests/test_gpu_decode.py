@@ -204,13 +204,13 @@ def test_group_schedule_frames_from_queue(gw, mw):
     that each group takes several frames from its XCD's queue: the results
     equal the persistent decoder's bit for bit, trace included."""
     print(f"[decode group queue gw={gw} mw={mw}]", flush=True)
-    n, F = 8192, 37
-    qc, csr, L, syn, _ = _slice_stage(2, n, F, seed=123)
+    n, F = 16384, 37                  # Z = 128: two rows (variables) per thread and body
+    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=123)
     code = api.Code.from_qc(qc)
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8)):
-        ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_PERSISTENT, **base),
+        ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=40, math=api.F32, schedule=api.SCHED_PERSISTENT, **base),
                           trace=True)
-        got = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_GROUP,
+        got = _decode_gpu(code, F, L, syn, api.Params(max_iter=40, math=api.F32, schedule=api.SCHED_GROUP,
                                                       group_wgs=gw, min_waves=mw, **base), trace=True)
         for k in ("bits", "post", "iters", "ok", "trace"):
             np.testing.assert_array_equal(np.nan_to_num(ref[k], nan=1e30), np.nan_to_num(got[k], nan=1e30))
