@@ -94,6 +94,17 @@ PAPER_CONTEXT = {
 }
 
 
+def wilson95(k: int, F: int):
+    """Wilson score interval (95 %) of a frame-error rate with k failures in F frames."""
+    if F <= 0:
+        return None
+    z, p = 1.959963984540054, k / F
+    den = 1.0 + z * z / F
+    mid = (p + z * z / (2 * F)) / den
+    half = z * math.sqrt(p * (1 - p) / F + z * z / (4 * F * F)) / den
+    return [max(0.0, mid - half), min(1.0, mid + half)]
+
+
 def csrc_hash() -> str:
     """Hash of the sources the decoder kernels are built from (a recorded
     traffic figure is valid while it is unchanged)."""
@@ -102,8 +113,8 @@ def csrc_hash() -> str:
     h = hashlib.sha256()
     csrc = Path(ROOT) / "paper_2108_08418_amd" / "csrc"
     for p in sorted(csrc.glob("*")):
-        if p.name in ("cvr_decode_impl.h", "cvr_internal.h", "cvr_decode.hip", "cvr_codes.hip") or \
-                p.name.startswith("cvr_dec_"):
+        if p.name in ("cvr_decode_impl.h", "cvr_internal.h", "cvr_decode.hip", "cvr_codes.hip",
+                      "cvr_nms_grad.hip") or p.name.startswith("cvr_dec_"):
             h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
@@ -375,12 +386,16 @@ def recon(args, wl, dev):
             "algorithmic_GBs": iter_gbs,
             "frac_of_hbm_peak": (iter_gbs / HBM_PEAK_GBS) if iter_gbs else None,
             "edge_updates_per_s": edge_updates / (t_total / args.steps),
+            # the paper's figure of merit: seconds per arithmetic operation at 7
+            # operations per edge and iteration (Sec. III-C), whole step
+            "c_h_equivalent_s": (t_total / args.steps) / (7.0 * edge_updates) if edge_updates else None,
             "decode_ms_per_step": (per_ms + chk_ms + var_ms) / args.steps,
         },
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
         "autotune_ms_per_decode": tuned,
         "dominant_kernel": dom,
         "fer": {str(j): float(1.0 - ok[j].mean()) for j in (2, 3)},
+        "fer_wilson95": {str(j): wilson95(int((ok[j] == 0).sum()), len(ok[j])) for j in (2, 3)},
         "mean_iters": {str(j): float(iters[j].mean()) for j in (2, 3)},
         "bit_errors_vs_bob": bit_err,
         "reconciled_pairs_per_s": N / (t_total / args.steps),
@@ -568,6 +583,8 @@ def train_step(args, wl, dev):
     E = qc.n_edges
     adj_bytes = adjoint_bytes(F, E, n, T, K)
     achieved = adj_bytes * adj_n / (adj_ms * 1e-3) / 1e9 if adj_ms > 0 else None
+    adj_kernel = "void cvr::k_nms_bwd_qc<8, true, 1024>"
+    traffic, traffic_src = recorded_traffic(adj_kernel, args.workload, "adjoint", "")
     step_s = t_total / args.steps
     result = {
         "metric": "unrolled min-sum training: bits/s through forward + adjoint",
@@ -576,9 +593,13 @@ def train_step(args, wl, dev):
         "dtype": "f32", "data": "synthetic: seeded random words and BPSK/AWGN, Eb/N0 uniform in [1.5, 3] dB",
         "config": {"workload": args.workload, "frames": F, "n": n, "T": T, "ckpt_every": K,
                    "code": qc.name, "n_types": qc.n_types, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "void cvr::k_nms_bwd_qc<8, true, 1024>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": adj_kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-                     "traffic": None, "avg_launch_us": 1e3 * adj_ms / adj_n if adj_n else None,
+                     "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_source": traffic_src,
+                     "traffic_over_algorithmic": traffic / adj_bytes if traffic else None,
+                     "avg_launch_us": 1e3 * adj_ms / adj_n if adj_n else None,
                      "algorithmic_bytes_per_launch": adj_bytes},
         "forward_ms": fwd_ms / max(fwd_n, 1), "adjoint_ms": adj_ms / max(adj_n, 1),
         "edge_iterations_per_s": 2.0 * F * E * T / step_s,
@@ -597,6 +618,7 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
     csr = {j: qcs[j].to_csr() for j in (2, 3)}
     algo = oracle.SP if args.decoder == "sp" else oracle.NMS
     t0 = time.perf_counter()
+    edge_updates = 0
     S = oracle.quantize(ys, th, M_BITS)
     syn = {j: oracle.syndrome(csr[j], S[j].reshape(Fs, n))[0] for j in (2, 3)}
     A = np.zeros_like(S)
@@ -608,10 +630,11 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
         r = oracle.decode(csr[j], L.reshape(Fs, n), syn[j], algo=algo, max_iter=sp.max_iter,
                           alpha=args.alpha, weights=w, store_half=(algo == oracle.NMS))
         A[j] = r["bits"].reshape(-1)
+        edge_updates += int(np.asarray(r["iters"]).astype(np.int64).sum()) * csr[j].n_edges
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 2 * Ns / dt, "unit": "bits/s", "cores": min(cores, os.cpu_count() or cores),
-            "kind": "oracle", "seconds": dt,
+            "kind": "oracle", "seconds": dt, "edge_updates_per_s": edge_updates / dt,
             "sample": f"first {Fs} of the {len(x_np) // n} sub-blocks of {n} bits of both coded slices: fp64 "
                       f"quantiser, syndromes, slice LLRs and decoding; decode threads across sub-blocks"}
 

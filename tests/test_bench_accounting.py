@@ -30,3 +30,16 @@ def test_stage_bytes_check_pass_split():
     expect = (4 * (4 * n + m) + (4 + 3) * s * E) + (11 * (4 * n + m) + (10 + 9) * s * E)
     assert chk == expect
     assert full == (3 + 10) * (2 * s * E + 12 * n)
+
+
+def test_wilson_interval_closed_forms():
+    """No failures: the upper end is z^2 / (F + z^2); the interval of F - k
+    failures mirrors that of k; it contains the point estimate."""
+    z2 = 1.959963984540054 ** 2
+    lo, hi = bench.wilson95(0, 2048)
+    assert lo == 0.0 and abs(hi - z2 / (2048 + z2)) < 1e-15
+    for k, F in ((3, 17), (35, 100), (1, 2)):
+        a, b = bench.wilson95(k, F)
+        c, d = bench.wilson95(F - k, F)
+        assert abs(a - (1 - d)) < 1e-12 and abs(b - (1 - c)) < 1e-12
+        assert a <= k / F <= b
