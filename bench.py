@@ -516,7 +516,9 @@ def ragged(args, wl, dev):
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": inst, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_source": traffic_src,
+                     "traffic_over_algorithmic": traffic / dec_bytes if (traffic and dec_bytes) else None,
                      "avg_launch_us": 1e3 * per_ms / per_n if per_n else None,
                      "algorithmic_bytes_per_launch": dec_bytes},
         "fer": fer,
@@ -612,7 +614,7 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
     """The fp64 oracle on a bounded sample of the same workload (the first
     ``cpu_frames`` sub-blocks of both coded slices), all host threads."""
     import oracle
-    Fs = args.cpu_frames
+    Fs = min(args.cpu_frames, len(x_np) // n)
     Ns = Fs * n
     xs, ys = x_np[:Ns], y_np[:Ns]
     csr = {j: qcs[j].to_csr() for j in (2, 3)}
