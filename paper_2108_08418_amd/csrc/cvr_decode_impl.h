@@ -733,7 +733,7 @@ __device__ __forceinline__ uint32_t group_sync(GroupCtx& g, uint32_t add = 0)
 // frame together (rows and variables interleaved by workgroup), with group
 // barriers between the passes and the stop decision taken from the group's
 // count; no posterior cache and no checkpoints.
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, bool CACHE, bool GRP = false>
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, bool CACHE, bool GRP = false, bool PAIR = false>
 __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm, int32_t* dsm, int32_t (&s_unsat)[2],
                                              float (&s_w)[kMaxTypes], int f, const DevFrame& fr, const DevCode& cd,
                                              GroupCtx* gc = nullptr)
@@ -754,10 +754,10 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
-    // group kernels at Z % 128 == 0 (and rows of at most 8 edges) give each
-    // thread two rows (variables) of one block row (column) per body, so twice
-    // the loads are in flight: the passes of a shared frame are latency-bound
-    constexpr bool kPairs = GRP && WU && MAXD <= 8;
+    // group kernels, and persistent ones built for it, at Z % 128 == 0 (and
+    // rows of at most 8 edges) give each thread two rows (variables) of one
+    // block row (column) per body, so twice the loads are in flight
+    constexpr bool kPairs = (GRP || PAIR) && WU && MAXD <= 8;
     const bool paired = kPairs && (Z % 128) == 0;
     const int hz = Z >> 1;
     const int hsh = zsh > 0 ? zsh - 1 : -1;
@@ -819,14 +819,14 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
                     const int kk[2] = {k0, k0 + hz};
                     const int ss[2] = {syn ? int(at(syn, i * Z + k0)) : 0, syn ? int(at(syn, i * Z + k0 + hz)) : 0};
                     switch (d) {
-                    case 1: bad += check_rows<M, S, ALGO, 1, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 2: bad += check_rows<M, S, ALGO, 2, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 3: bad += check_rows<M, S, ALGO, 3, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 4: bad += check_rows<M, S, ALGO, 4, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 5: bad += check_rows<M, S, ALGO, 5, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 6: bad += check_rows<M, S, ALGO, 6, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 7: bad += check_rows<M, S, ALGO, 7, WU, false, GRP, 2>(c, q0, kk, ss); break;
-                    case 8: bad += check_rows<M, S, ALGO, 8, WU, false, GRP, 2>(c, q0, kk, ss); break;
+                    case 1: bad += check_rows<M, S, ALGO, 1, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 2: bad += check_rows<M, S, ALGO, 2, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 3: bad += check_rows<M, S, ALGO, 3, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 4: bad += check_rows<M, S, ALGO, 4, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 5: bad += check_rows<M, S, ALGO, 5, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 6: bad += check_rows<M, S, ALGO, 6, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 7: bad += check_rows<M, S, ALGO, 7, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 8: bad += check_rows<M, S, ALGO, 8, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
                     default: break;
                     }
                 }
@@ -901,9 +901,11 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
                         for (int h = 0; h < 2; ++h) acc[h] = var_sum_any<M, S, WU, GRP>(c, qa, dv, uu[h], acc[h]);
                         break;
                     }
+                    const int slot = slot_of(j);
                     for (int h = 0; h < 2; ++h) {
                         const int v = j * Z + uu[h];
-                        at(c.Lp, v) = acc[h];
+                        if (slot >= 0) c.s_post[slot * Z + uu[h]] = acc[h];
+                        else at(c.Lp, v) = acc[h];
                         if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc[h];
                     }
                 }
@@ -1117,7 +1119,10 @@ __global__ __launch_bounds__(NT, MINW) void k_frames_qc(DecArgs a, LdsMap lm, in
             load_code_tables<M, NT>(lm, dsm, cd);
             cur = fr.code;
         }
-        decode_frame<M, S, ALGO, MAXD, NT, WU, CACHE>(a, lm, dsm, s_unsat, s_w, f, fr, cd);
+        // the 1024-thread shape without the 8-wave register bound (one
+        // workgroup per CU, the most LDS for the posterior cache) runs the
+        // paired bodies to keep as many loads in flight as two workgroups would
+        decode_frame<M, S, ALGO, MAXD, NT, WU, CACHE, false, NT == 1024 && MINW == 1>(a, lm, dsm, s_unsat, s_w, f, fr, cd);
     }
 }
 
