@@ -24,6 +24,7 @@
 #include "cvr_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace cvr {
 
@@ -754,13 +755,13 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
-    // group kernels, and persistent ones built for it, at Z % 128 == 0 (and
-    // rows of at most 8 edges) give each thread two rows (variables) of one
-    // block row (column) per body, so twice the loads are in flight
+    // group kernels, and persistent ones built for it, give each thread R rows
+    // (variables) of one block row (column) per body, k0 + h Z / R, so R times
+    // the loads are in flight: R = 2 at Z % 128 == 0, and for the persistent
+    // shape R = 4 at Z % 256 == 0 (rows of at most 8 edges)
     constexpr bool kPairs = (GRP || PAIR) && WU && MAXD <= 8;
-    const bool paired = kPairs && (Z % 128) == 0;
-    const int hz = Z >> 1;
-    const int hsh = zsh > 0 ? zsh - 1 : -1;
+    const int rows_per_body = !kPairs ? 1 : (PAIR && !GRP && Z % 256 == 0) ? 4 : (Z % 128 == 0 ? 2 : 1);
+    const bool paired = rows_per_body > 1;
     const int32_t* s_rptr = dsm + lm.rptr;
     const int32_t* s_cptr = dsm + lm.cptr;
     FrameCtx<M, S> c;
@@ -809,28 +810,39 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         // check pass: syndrome test of Lpost(t) and c2v(t+1)
         int bad = 0;
         if constexpr (kPairs) {
-            if (paired) {
-                // rows k and k + Z/2 of a block row in one body
-                for (int p = first; p < (m >> 1); p += stride) {
-                    const int i = uni<WU>(hsh >= 0 ? (p >> hsh) : p / hz);
-                    const int k0 = p - i * hz;
+            // rows k0 + h Z / R, h < R, of a block row in one body
+            auto check_multi = [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                const int qz = Z / R;
+                const int qsh = zsh >= 0 ? zsh - (R == 4 ? 2 : 1) : -1;
+                for (int p = first; p < m / R; p += stride) {
+                    const int i = uni<WU>(qsh >= 0 ? (p >> qsh) : p / qz);
+                    const int k0 = p - i * qz;
                     const int q0 = uni<WU>(s_rptr[i]);
                     const int d = uni<WU>(s_rptr[i + 1]) - q0;
-                    const int kk[2] = {k0, k0 + hz};
-                    const int ss[2] = {syn ? int(at(syn, i * Z + k0)) : 0, syn ? int(at(syn, i * Z + k0 + hz)) : 0};
+                    int kk[R], ss[R];
+#pragma unroll
+                    for (int h = 0; h < R; ++h) {
+                        kk[h] = k0 + h * qz;
+                        ss[h] = syn ? int(at(syn, i * Z + kk[h])) : 0;
+                    }
                     switch (d) {
-                    case 1: bad += check_rows<M, S, ALGO, 1, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 2: bad += check_rows<M, S, ALGO, 2, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 3: bad += check_rows<M, S, ALGO, 3, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 4: bad += check_rows<M, S, ALGO, 4, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 5: bad += check_rows<M, S, ALGO, 5, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 6: bad += check_rows<M, S, ALGO, 6, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 7: bad += check_rows<M, S, ALGO, 7, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
-                    case 8: bad += check_rows<M, S, ALGO, 8, WU, CACHE, GRP, 2>(c, q0, kk, ss); break;
+                    case 1: bad += check_rows<M, S, ALGO, 1, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 2: bad += check_rows<M, S, ALGO, 2, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 3: bad += check_rows<M, S, ALGO, 3, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 4: bad += check_rows<M, S, ALGO, 4, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 5: bad += check_rows<M, S, ALGO, 5, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 6: bad += check_rows<M, S, ALGO, 6, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 7: bad += check_rows<M, S, ALGO, 7, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 8: bad += check_rows<M, S, ALGO, 8, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
                     default: break;
                     }
                 }
+            };
+            if constexpr (PAIR && !GRP) {
+                if (rows_per_body == 4) check_multi(std::integral_constant<int, 4>{});
             }
+            if (rows_per_body == 2) check_multi(std::integral_constant<int, 2>{});
         }
         for (int r = first; !paired && r < m; r += stride) {
             const int i = uni<WU>(zsh >= 0 ? (r >> zsh) : r / Z);
@@ -879,37 +891,50 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
         if (a.weights && t + 1 < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t + 1) * a.n_types + tid];
         // variable pass: Lpost(t+1) = Lch + sum of c2v(t+1) over block rows ascending
         if constexpr (kPairs) {
-            if (paired) {
-                // variables u and u + Z/2 of a block column in one body
-                for (int p = first; p < (n >> 1); p += stride) {
-                    const int j = uni<WU>(hsh >= 0 ? (p >> hsh) : p / hz);
-                    const int u0 = p - j * hz;
+            // variables u0 + h Z / R, h < R, of a block column in one body
+            auto var_multi = [&](auto rc) {
+                constexpr int R = decltype(rc)::value;
+                const int qz = Z / R;
+                const int qsh = zsh >= 0 ? zsh - (R == 4 ? 2 : 1) : -1;
+                for (int p = first; p < n / R; p += stride) {
+                    const int j = uni<WU>(qsh >= 0 ? (p >> qsh) : p / qz);
+                    const int u0 = p - j * qz;
                     const int qa = uni<WU>(s_cptr[j]);
                     const int dv = uni<WU>(s_cptr[j + 1]) - qa;
-                    const int uu[2] = {u0, u0 + hz};
-                    M acc[2] = {at(c.Lc, j * Z + u0), at(c.Lc, j * Z + u0 + hz)};
+                    int uu[R];
+                    M acc[R];
+#pragma unroll
+                    for (int h = 0; h < R; ++h) {
+                        uu[h] = u0 + h * qz;
+                        acc[h] = at(c.Lc, j * Z + uu[h]);
+                    }
                     switch (dv) {
-                    case 1: var_sums<M, S, 1, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 2: var_sums<M, S, 2, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 3: var_sums<M, S, 3, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 4: var_sums<M, S, 4, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 5: var_sums<M, S, 5, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 6: var_sums<M, S, 6, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 7: var_sums<M, S, 7, WU, GRP, 2>(c, qa, uu, acc); break;
-                    case 8: var_sums<M, S, 8, WU, GRP, 2>(c, qa, uu, acc); break;
+                    case 1: var_sums<M, S, 1, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 2: var_sums<M, S, 2, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 3: var_sums<M, S, 3, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 4: var_sums<M, S, 4, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 5: var_sums<M, S, 5, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 6: var_sums<M, S, 6, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 7: var_sums<M, S, 7, WU, GRP, R>(c, qa, uu, acc); break;
+                    case 8: var_sums<M, S, 8, WU, GRP, R>(c, qa, uu, acc); break;
                     default:
-                        for (int h = 0; h < 2; ++h) acc[h] = var_sum_any<M, S, WU, GRP>(c, qa, dv, uu[h], acc[h]);
+                        for (int h = 0; h < R; ++h) acc[h] = var_sum_any<M, S, WU, GRP>(c, qa, dv, uu[h], acc[h]);
                         break;
                     }
                     const int slot = slot_of(j);
-                    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int h = 0; h < R; ++h) {
                         const int v = j * Z + uu[h];
                         if (slot >= 0) c.s_post[slot * Z + uu[h]] = acc[h];
                         else at(c.Lp, v) = acc[h];
                         if (tr) tr[int64_t(t + 1) * a.total_n + v] = acc[h];
                     }
                 }
+            };
+            if constexpr (PAIR && !GRP) {
+                if (rows_per_body == 4) var_multi(std::integral_constant<int, 4>{});
             }
+            if (rows_per_body == 2) var_multi(std::integral_constant<int, 2>{});
         }
         for (int v = first; !paired && v < n; v += stride) {
             const int j = column(v);
