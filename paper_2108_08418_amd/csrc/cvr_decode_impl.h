@@ -755,12 +755,12 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
-    // group kernels, and persistent ones built for it, give each thread R rows
-    // (variables) of one block row (column) per body, k0 + h Z / R, so R times
-    // the loads are in flight: R = 2 at Z % 128 == 0, and for the persistent
-    // shape R = 4 at Z % 256 == 0 (rows of at most 8 edges)
+    // group kernels, and the one-workgroup-per-CU shapes (PAIR), give each
+    // thread R rows (variables) of one block row (column) per body,
+    // k0 + h Z / R, so R times the loads are in flight: R = 2 at Z % 128 == 0,
+    // and with PAIR R = 4 at Z % 256 == 0 (rows of at most 8 edges)
     constexpr bool kPairs = (GRP || PAIR) && WU && MAXD <= 8;
-    const int rows_per_body = !kPairs ? 1 : (PAIR && !GRP && Z % 256 == 0) ? 4 : (Z % 128 == 0 ? 2 : 1);
+    const int rows_per_body = !kPairs ? 1 : (PAIR && Z % 256 == 0) ? 4 : (Z % 128 == 0 ? 2 : 1);
     const bool paired = rows_per_body > 1;
     const int32_t* s_rptr = dsm + lm.rptr;
     const int32_t* s_cptr = dsm + lm.cptr;
@@ -839,7 +839,7 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
                     }
                 }
             };
-            if constexpr (PAIR && !GRP) {
+            if constexpr (PAIR) {
                 if (rows_per_body == 4) check_multi(std::integral_constant<int, 4>{});
             }
             if (rows_per_body == 2) check_multi(std::integral_constant<int, 2>{});
@@ -931,7 +931,7 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
                     }
                 }
             };
-            if constexpr (PAIR && !GRP) {
+            if constexpr (PAIR) {
                 if (rows_per_body == 4) var_multi(std::integral_constant<int, 4>{});
             }
             if (rows_per_body == 2) var_multi(std::integral_constant<int, 2>{});
@@ -1219,7 +1219,7 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
             load_code_tables<M, NT>(lm, dsm, cd);
             cur = fr.code;
         }
-        decode_frame<M, S, ALGO, MAXD, NT, WU, false, true>(a, lm, dsm, s_unsat, s_w, f, fr, cd, &gc);
+        decode_frame<M, S, ALGO, MAXD, NT, WU, false, true, NT == 1024 && MINW == 1>(a, lm, dsm, s_unsat, s_w, f, fr, cd, &gc);
         group_sync(gc);
     }
 }
