@@ -826,15 +826,30 @@ __device__ __forceinline__ void decode_frame(const DecArgs& a, const LdsMap& lm,
                         kk[h] = k0 + h * qz;
                         ss[h] = syn ? int(at(syn, i * Z + kk[h])) : 0;
                     }
+                    // wide rows take R = 4 as two bodies of 2 where the registers of
+                    // four such rows would spill (measured: sum-product in the
+                    // persistent kernel does better with all four at once)
+                    constexpr int kSplitD = (ALGO == CVR_SP && !GRP) ? MAXD + 1 : 7;
+                    auto body = [&](auto dc) {
+                        constexpr int D = decltype(dc)::value;
+                        if constexpr (R == 4 && D >= kSplitD) {
+                            const int ka[2] = {kk[0], kk[1]}, sa[2] = {ss[0], ss[1]};
+                            const int kb[2] = {kk[2], kk[3]}, sb[2] = {ss[2], ss[3]};
+                            bad += check_rows<M, S, ALGO, D, WU, CACHE, GRP, 2>(c, q0, ka, sa);
+                            bad += check_rows<M, S, ALGO, D, WU, CACHE, GRP, 2>(c, q0, kb, sb);
+                        } else {
+                            bad += check_rows<M, S, ALGO, D, WU, CACHE, GRP, R>(c, q0, kk, ss);
+                        }
+                    };
                     switch (d) {
-                    case 1: bad += check_rows<M, S, ALGO, 1, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 2: bad += check_rows<M, S, ALGO, 2, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 3: bad += check_rows<M, S, ALGO, 3, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 4: bad += check_rows<M, S, ALGO, 4, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 5: bad += check_rows<M, S, ALGO, 5, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 6: bad += check_rows<M, S, ALGO, 6, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 7: bad += check_rows<M, S, ALGO, 7, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
-                    case 8: bad += check_rows<M, S, ALGO, 8, WU, CACHE, GRP, R>(c, q0, kk, ss); break;
+                    case 1: body(std::integral_constant<int, 1>{}); break;
+                    case 2: body(std::integral_constant<int, 2>{}); break;
+                    case 3: body(std::integral_constant<int, 3>{}); break;
+                    case 4: body(std::integral_constant<int, 4>{}); break;
+                    case 5: body(std::integral_constant<int, 5>{}); break;
+                    case 6: body(std::integral_constant<int, 6>{}); break;
+                    case 7: body(std::integral_constant<int, 7>{}); break;
+                    case 8: body(std::integral_constant<int, 8>{}); break;
                     default: break;
                     }
                 }
