@@ -191,10 +191,13 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *  wg_threads, min_waves  tuning knobs of the persistent decoder that do
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
- *            compiler choose.  Binary64 math and batches with a check row of
- *            more than 8 edges always run 512 threads.  The group schedule
- *            runs 1024 threads (512 in those cases) and takes min_waves too:
- *            8 puts two workgroups on each compute unit.
+ *            compiler choose.  1024 threads with min_waves 0 (one workgroup
+ *            per compute unit) give each thread 4 rows of a block row per step
+ *            when Z % 256 == 0, 2 when Z % 128 == 0.  Binary64 math and
+ *            batches with a check row of more than 8 edges always run 512
+ *            threads.  The group schedule runs 1024 threads (512 in those
+ *            cases) and takes min_waves too: 8 puts two workgroups on each
+ *            compute unit.
  *  lds_cache_kb  posteriors of the highest-degree block columns that the
  *            persistent decoder keeps in LDS (results unchanged): 0 = as much
  *            as fits without fewer resident workgroups, -1 = none, > 0 = that
