@@ -299,6 +299,18 @@ cvr_status cvr_profile_enable(int32_t on);
  * number of launches of one kind since the last reset; reset != 0 clears them. */
 cvr_status cvr_profile_read(int32_t kind, double* total_ms, int64_t* launches, int32_t reset);
 
+/* ------------------------------------------------------------------------- */
+/* Testing hook                                                               */
+/* ------------------------------------------------------------------------- */
+/* Bounds every wait at a barrier of the group schedule (CVR_SCHED_GROUP) to
+ * `ticks` of the 100 MHz device wall clock, for later launches of this
+ * process; the default is 20,000,000 (0.2 s).  With 0 a barrier that is not
+ * complete when a workgroup arrives gives up at once: the launch still ends,
+ * and every frame of that decode is reported with ok = 0 (the path a barrier
+ * takes when a group's workgroups are not all resident).  For tests of that
+ * failure path.  ticks > 1e10 returns CVR_EINVAL. */
+cvr_status cvr_debug_group_wait_ticks(uint64_t ticks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,6 +52,7 @@ SIGNATURES = {
     "nms_unrolled_bwd": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int),
     "cvr_profile_enable": ([_I32], C.c_int),
     "cvr_profile_read": ([_I32, _P, _P, _I32], C.c_int),
+    "cvr_debug_group_wait_ticks": ([C.c_uint64], C.c_int),
 }
 
 _lib = None

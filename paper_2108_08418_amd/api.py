@@ -273,6 +273,14 @@ def version() -> int:
     return int(load().cvr_version())
 
 
+GROUP_WAIT_TICKS_DEFAULT = 20_000_000
+
+
+def debug_group_wait_ticks(ticks: int = GROUP_WAIT_TICKS_DEFAULT) -> None:
+    """Testing hook: bound of one group-barrier wait in 100 MHz ticks (0: give up at once)."""
+    check(load().cvr_debug_group_wait_ticks(int(ticks)), "cvr_debug_group_wait_ticks")
+
+
 # ---------------------------------------------------------------------------
 # launch timing
 # ---------------------------------------------------------------------------

@@ -22,6 +22,8 @@
 // Both sum in the same order, so they give bit-identical results.
 #include "cvr_decode_impl.h"
 
+#include <atomic>
+
 namespace cvr {
 
 // ---------------------------------------------------------------------------
@@ -76,7 +78,19 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
 
 }  // namespace cvr
 
+namespace cvr {
+static std::atomic<uint64_t> g_group_wait_ticks{kGroupWaitTicks};
+uint64_t group_wait_ticks() { return g_group_wait_ticks.load(std::memory_order_relaxed); }
+}  // namespace cvr
+
 using namespace cvr;
+
+extern "C" cvr_status cvr_debug_group_wait_ticks(uint64_t ticks)
+{
+    if (ticks > 10000000000ull) return fail(CVR_EINVAL, "cvr_debug_group_wait_ticks: ticks > 1e10");
+    g_group_wait_ticks.store(ticks, std::memory_order_relaxed);
+    return CVR_OK;
+}
 
 extern "C" cvr_status cvr_decode_workspace_size(cvr_batch_t batch, const cvr_decode_params* params, size_t* bytes)
 {

@@ -686,15 +686,18 @@ struct GroupCtx {
     int32_t* err;           // set to 1 when a barrier wait gave up
     uint32_t gen;           // barriers passed so far
     uint32_t unsat_seen;    // high half at the last check-pass barrier
+    uint64_t wait_ticks;    // bound of one wait, 100 MHz wall-clock ticks
 };
+
+constexpr uint64_t kGroupWaitTicks = 20000000ull;   // 0.2 s
 
 // Barrier of the G workgroups of a group, which also sums `add` over them.
 // Each wave first waits for its own stores to complete (they are then in the
 // L2), the workgroup meets, and one thread adds (add << 32) + 1 to the group
 // word and reads it until the arrivals of this generation are complete,
-// bounded in wall-clock time (0.2 s; once a wait has given up no later one
-// waits, so the launch always ends, and the frames are then reported as not
-// decoded).  Returns the high half read then: every member's adds up to this
+// bounded in wall-clock time (g.wait_ticks, 0.2 s by default; once a wait has
+// given up no later one waits, so the launch always ends, and the frames are
+// then reported as not decoded).  Returns the high half read then: every member's adds up to this
 // barrier.  A member that has passed it can arrive at the next barrier first,
 // so a barrier that follows one with adds must add 0.
 __device__ __forceinline__ uint32_t group_sync(GroupCtx& g, uint32_t add = 0)
@@ -711,7 +714,7 @@ __device__ __forceinline__ uint32_t group_sync(GroupCtx& g, uint32_t add = 0)
             do {
                 __builtin_amdgcn_s_sleep(1);
                 v = __hip_atomic_load(g.word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (wall_clock64() - t0 > 20000000ull) {       // 0.2 s of the 100 MHz counter
+                if (wall_clock64() - t0 > g.wait_ticks) {
                     atomicExch(g.err, 1);
                     break;
                 }
@@ -1187,7 +1190,11 @@ struct GroupArgs {
     const int32_t* order;     // [F] frames, largest first
     int32_t* ws;              // group workspace, zeroed by k_group_init
     int32_t F, G, NG;         // frames, workgroups per group, groups per XCD
+    uint64_t wait_ticks;      // bound of one barrier wait
 };
+
+// The bound of a barrier wait for later launches (cvr_debug_group_wait_ticks).
+uint64_t group_wait_ticks();
 
 template <typename M, typename S, int ALGO, int MAXD, int NT, bool WU, int MINW>
 __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, GroupArgs g)
@@ -1214,7 +1221,7 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
     const int gi = place / g.G;
     if (gi >= g.NG) return;                                  // a surplus place
     int32_t* gw = g.ws + kGwGroups + (xcd * g.NG + gi) * kGwGroupWords;
-    GroupCtx gc{place % g.G, g.G, reinterpret_cast<uint64_t*>(gw), err, 0u, 0u};
+    GroupCtx gc{place % g.G, g.G, reinterpret_cast<uint64_t*>(gw), err, 0u, 0u, g.wait_ticks};
     int cur = -1;
     for (;;) {
         if (gc.member == 0 && tid == 0) {
@@ -1509,7 +1516,7 @@ static cvr_status launch_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, i
         hipLaunchKernelGGL(k_group_init, dim3(1), dim3(256), 0, s, ws, int32_t(kGwGroups + NG * kXcds * kGwGroupWords));
     }
     if (cvr_status st = check_launch("decode (group) init")) return st;
-    const GroupArgs g{b->d_order, ws, b->F, G, NG};
+    const GroupArgs g{b->d_order, ws, b->F, G, NG, group_wait_ticks()};
     {
         ProfScope prof(CVR_PROF_FRAMES, s);
         hipLaunchKernelGGL(kern, dim3(kXcds * NG * G), dim3(NT), size_t(dyn), s, a, lm, g);

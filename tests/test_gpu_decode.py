@@ -338,6 +338,30 @@ def test_failure_injection_and_edge_cases(sched):
     api.ldpc_decode_batch(empty, p, _g(np.zeros(1, np.float32)))
 
 
+def test_group_barrier_time_out_reports_every_frame_failed():
+    """Forced from the host: with a zero wait bound, a group barrier that is not
+    complete when a workgroup arrives gives up at once; the launch still ends and
+    every frame of that decode is reported with ok = 0.  With the default bound
+    restored the next decode equals the persistent decoder's."""
+    print("[decode group barrier time-out]", flush=True)
+    n, F = 16384, 12
+    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=321)
+    code = api.Code.from_qc(qc)
+    p = api.Params(algo=api.SP, max_iter=30, early_stop=False, math=api.F32, store=api.F32,
+                   schedule=api.SCHED_GROUP)
+    try:
+        api.debug_group_wait_ticks(0)
+        failed = _decode_gpu(code, F, L, syn, p)
+    finally:
+        api.debug_group_wait_ticks()
+    assert (failed["ok"] == 0).all()
+    good = _decode_gpu(code, F, L, syn, p)
+    ref = _decode_gpu(code, F, L, syn, api.Params(algo=api.SP, max_iter=30, early_stop=False, math=api.F32,
+                                                  store=api.F32, schedule=api.SCHED_PERSISTENT))
+    for k in ("bits", "post", "iters", "ok"):
+        np.testing.assert_array_equal(ref[k], good[k])
+
+
 def test_repeat_runs_are_bit_identical():
     qc, csr, L, syn, _ = _slice_stage(2, 16384, 4, seed=8)
     p = api.Params(algo=api.SP, max_iter=60, math=api.F32, store=api.F32)
