@@ -36,6 +36,7 @@ struct SynArgs {
     uint8_t* out;
     int32_t* n_unsat;
     int32_t F;
+    int32_t fpt;              // frames per thread (k_syndrome_qc)
 };
 
 __global__ __launch_bounds__(256) void k_syndrome(SynArgs a)
@@ -53,6 +54,54 @@ __global__ __launch_bounds__(256) void k_syndrome(SynArgs a)
         bad = par != ref;
     }
     if (a.n_unsat) add_unsat(&a.n_unsat[f], bad);
+}
+
+// Quasi-cyclic codes: row i Z + k XORs the bits (k + shift) mod Z of its block
+// columns, so a wavefront's 64 rows read 64 consecutive bits of each block (no
+// index array); the packed row table gives shift | block column << 16.  A
+// thread takes its row in a.fpt <= kSynFrames frames, with all of their bits
+// of one table entry loaded before they are combined (with one row per thread,
+// a launch over thousands of frames was mostly workgroup dispatch).
+constexpr int kSynFrames = 8;
+
+__global__ __launch_bounds__(256) void k_syndrome_qc(SynArgs a)
+{
+    const int f0 = blockIdx.y * a.fpt;
+    const int nf = min(a.fpt, a.F - f0);                     // block-uniform, <= kSynFrames
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const DevCode& cd = a.code;
+    int par[kSynFrames];
+#pragma unroll
+    for (int h = 0; h < kSynFrames; ++h) par[h] = 0;
+    if (r < cd.m) {
+        const int Z = cd.Z;
+        const int i = r / Z;
+        const int k = r - i * Z;
+        const int q1 = cd.qrow_ptr[i + 1];
+        for (int q = cd.qrow_ptr[i]; q < q1; ++q) {
+            const int32_t e = cd.qrow_pk[q];
+            int u = k + (e & 0xffff);
+            u = u >= Z ? u - Z : u;
+            const uint8_t* b = a.bits + int64_t(f0) * cd.n + ((e >> 16) & 0x1ff) * Z + u;
+            uint8_t v[kSynFrames];
+#pragma unroll
+            for (int h = 0; h < kSynFrames; ++h) v[h] = (h < nf) ? b[int64_t(h) * cd.n] : uint8_t(0);
+#pragma unroll
+            for (int h = 0; h < kSynFrames; ++h) par[h] ^= v[h] & 1;
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < kSynFrames; ++h) {
+        if (h >= nf) break;
+        const int64_t f = f0 + h;
+        int bad = 0;
+        if (r < cd.m) {
+            const int ref = a.ref ? (a.ref[f * cd.m + r] & 1) : 0;
+            if (a.out) a.out[f * cd.m + r] = uint8_t(par[h]);
+            bad = par[h] != ref;
+        }
+        if (a.n_unsat) add_unsat(&a.n_unsat[f], bad);
+    }
 }
 
 static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
@@ -184,6 +233,12 @@ extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* 
     a.out = syndrome_out;
     a.n_unsat = n_unsat;
     a.F = F;
-    hipLaunchKernelGGL(k_syndrome, dim3((code->dev.m + 255) / 256, F), dim3(256), 0, s, a);
+    // several frames per thread only when the frames alone fill the chip
+    a.fpt = F >= 64 ? kSynFrames : 1;
+    if (code->dev.is_qc && code->dev.qrow_pk)
+        hipLaunchKernelGGL(k_syndrome_qc, dim3((code->dev.m + 255) / 256, (F + a.fpt - 1) / a.fpt), dim3(256), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL(k_syndrome, dim3((code->dev.m + 255) / 256, F), dim3(256), 0, s, a);
     return check_launch("syndrome_check");
 }

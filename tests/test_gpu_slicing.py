@@ -109,18 +109,25 @@ def test_slice_llr_one_bit_closed_form():
     np.testing.assert_allclose(Lg, ref, rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("which", ["regular", "qc2", "qc3"])
+@pytest.mark.parametrize("which", ["regular", "qc2", "qc3", "qc_z96", "qc_z32", "met_z64", "qc_z32_f77"])
 def test_syndrome_bit_exact(which):
+    """Explicit codes take the gather kernel, QC codes the circulant kernel
+    (Z = 512, 96: not a power of two, 32: below a wavefront, 64: MET); 77
+    frames take several frames per thread with a ragged last group."""
     print(f"[syndrome {which}]", flush=True)
     if which == "regular":
         csr = inputs.regular_code(1024, 3, 6, seed=1)
         code = api.Code.from_csr(csr)
         F = 200
     else:
-        qc = inputs.slice_code_spec(2 if which == "qc2" else 3, 65536)
+        qc = {"qc2": lambda: inputs.slice_code_spec(2, 65536), "qc3": lambda: inputs.slice_code_spec(3, 65536),
+              "qc_z96": lambda: inputs.slice_code_spec(2, 128 * 96),
+              "qc_z32": lambda: inputs.lambda_half_rate_spec(4096),
+              "qc_z32_f77": lambda: inputs.lambda_half_rate_spec(4096),
+              "met_z64": lambda: inputs.met_low_rate_spec(4096)}[which]()
         csr = qc.to_csr()
         code = api.Code.from_qc(qc)
-        F = 16
+        F = 77 if which.endswith("f77") else (16 if qc.Z >= 512 else 7)
     bits = inputs.random_bits((F, csr.n), seed=11)
     ref_s = inputs.random_bits((F, csr.m), seed=12)
     s_g, u_g = api.syndrome_check(code, _g(bits), _g(ref_s))
