@@ -217,19 +217,21 @@ def test_group_schedule_frames_from_queue(gw, mw):
         assert ref["ok"].any() and ref["iters"].min() > 0
 
 
-@pytest.mark.parametrize("Z", [384, 768])
+@pytest.mark.parametrize("Z", [384, 512, 768, 1536])
 def test_multi_row_bodies_at_non_power_of_two_Z(Z):
-    """Z = 384 (two rows per body) and 768 (four) take the division path of the
-    multi-row index arithmetic: the one-workgroup-per-CU persistent shape and
-    the group schedule equal the per-pass kernels bit for bit."""
+    """Two and four rows per body (1024 threads, one workgroup per CU: 4 at
+    Z % 256 == 0), with the division path of the index arithmetic at Z = 384,
+    768 and 1536: the persistent shapes (1024 and 512 threads) and the group
+    schedule equal the per-pass kernels bit for bit."""
     print(f"[decode multi-row Z={Z}]", flush=True)
-    n, F = 128 * Z, 5
+    n, F = 128 * Z, 3 if Z > 768 else 5
     qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=Z)
     code = api.Code.from_qc(qc)
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8)):
         ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_PASSES, **base))
         assert ref["ok"].any()
-        for sched, wg, lk in ((api.SCHED_PERSISTENT, 1024, 0), (api.SCHED_PERSISTENT, 1024, -1), (api.SCHED_GROUP, 0, 0)):
+        for sched, wg, lk in ((api.SCHED_PERSISTENT, 1024, 0), (api.SCHED_PERSISTENT, 1024, -1),
+                              (api.SCHED_PERSISTENT, 512, 0), (api.SCHED_PERSISTENT, 512, -1), (api.SCHED_GROUP, 0, 0)):
             got = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=sched, wg_threads=wg,
                                                           lds_cache_kb=lk, **base))
             for k in ("bits", "post", "iters", "ok"):

@@ -4,11 +4,15 @@ properties checked on every frame.
 
 * 2^27 Gaussian pairs at SNR 3 (16 equiprobable levels, 2048 sub-blocks of
   2^16 per coded slice), slice 2 decoded with sum-product by the persistent
-  kernel at 1024 threads, 8 waves per SIMD, automatic LDS posterior cache.
+  kernel at 1024 threads.
 * The uneven batch: 4096 sub-blocks of the rate-0.0625 MET code at SNR 0.16
   (2176 x 4096, 1024 x 16384, 640 x 65536, 256 x 262144 bits), min-sum
-  alpha 0.75 with binary16 messages, persistent kernel at 1024 threads, 8
-  waves per SIMD, no cache.
+  alpha 0.75 with binary16 messages, persistent kernel at 1024 threads.
+
+Each batch is decoded in every shape the autotuner may pick for it: one
+workgroup per CU (four rows per body), with and without the LDS posterior
+cache, and 8 waves per SIMD.  The shapes must agree bit for bit before the
+first one is checked against the oracle.
 
 Rules as in test_gpu_decode: quantiser, syndromes and decisions bit-exact;
 slice LLRs within one fp32 ulp of the fp64 oracle; SP posteriors within
@@ -33,8 +37,26 @@ def _g(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
+def _decode_in_shapes(batch, llr, syn, kw, shapes):
+    """Decode with the persistent kernel at 1024 threads in each (min_waves,
+    lds_cache_kb) shape; all outputs must be identical.  Returns the first."""
+    first = None
+    for mw, cache in shapes:
+        print(f"  shape 1024/{mw}/{cache}", flush=True)
+        p = api.Params(schedule=api.SCHED_PERSISTENT, wg_threads=1024, min_waves=mw, lds_cache_kb=cache, **kw)
+        out = api.ldpc_decode_batch(batch, p, llr, syn)
+        torch.cuda.synchronize()
+        out = {k: out[k].clone() for k in ("bits", "post", "iters", "ok")}
+        if first is None:
+            first = out
+            continue
+        for k in first:
+            assert torch.equal(out[k], first[k]), f"shape 1024/{mw}/{cache}: {k} differs from 1024/{shapes[0][0]}/{shapes[0][1]}"
+    return first
+
+
 def test_recon_2p27_pairs_sampled_against_oracle():
-    print("[full size: 2^27 pairs, slice 2, SP, persistent 1024/8/auto cache]", flush=True)
+    print("[full size: 2^27 pairs, slice 2, SP, persistent 1024 threads]", flush=True)
     snr = 3.0
     sig = math.sqrt(1.0 / snr)
     th = inputs.equiprobable_thresholds(4, 1.0 + 1.0 / snr)
@@ -69,11 +91,9 @@ def test_recon_2p27_pairs_sampled_against_oracle():
 
     assert within_ulp(llr[idx_g].cpu().numpy(), oracle.slice_llr(x[idx], sig, th, 4, oracle.GRAY, 2, 0b11, A_ref))
     # the decoder in the benchmark's launch configuration
-    p = api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32, schedule=api.SCHED_PERSISTENT,
-                   wg_threads=1024, min_waves=8, lds_cache_kb=0)
     batch = api.Batch.uniform(code, F)
-    out = api.ldpc_decode_batch(batch, p, llr, syn.view(-1))
-    torch.cuda.synchronize()
+    out = _decode_in_shapes(batch, llr, syn.view(-1), dict(algo=api.SP, max_iter=100, math=api.F32, store=api.F32),
+                            [(0, 0), (0, 150), (8, 0)])
     # every frame: ok <=> its decisions satisfy Bob's syndrome; iteration counts in range
     _, unsat = api.syndrome_check(code, out["bits"], syn.view(-1), want_syndrome=False)
     ok = out["ok"].cpu().numpy().astype(bool)
@@ -111,7 +131,7 @@ def test_recon_2p27_pairs_sampled_against_oracle():
 
 
 def test_uneven_met_batch_4096_frames_sampled_against_oracle():
-    print("[full size: 4096 uneven MET frames, min-sum f16, persistent 1024/8/no cache]", flush=True)
+    print("[full size: 4096 uneven MET frames, min-sum f16, persistent 1024 threads]", flush=True)
     sizes, counts = (4096, 16384, 65536, 262144), (2176, 1024, 640, 256)
     rng = np.random.default_rng(2108)
     order = rng.permutation(np.repeat(np.arange(len(sizes)), counts))
@@ -134,10 +154,9 @@ def test_uneven_met_batch_4096_frames_sampled_against_oracle():
         cidx = torch.cat([torch.arange(frames[i][2], frames[i][2] + q.m, device=DEV) for i in ids])
         s_c, _ = api.syndrome_check(codes[c], bits_g[vidx].contiguous(), want_unsat=False)
         syn[cidx] = s_c.view(-1)
-    p = api.Params(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75,
-                   schedule=api.SCHED_PERSISTENT, wg_threads=1024, min_waves=8, lds_cache_kb=-1)
-    out = api.ldpc_decode_batch(batch, p, _g(llr), syn)
-    torch.cuda.synchronize()
+    out = _decode_in_shapes(batch, _g(llr), syn,
+                            dict(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75),
+                            [(0, 0), (0, 150), (8, -1)])
     syn_np = syn.cpu().numpy()
     ok = out["ok"].cpu().numpy().astype(bool)
     iters = out["iters"].cpu().numpy()
