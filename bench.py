@@ -78,6 +78,9 @@ def parse():
                     help="block-size sweep: every recon-2^27 workload with SP and with learned min-sum "
                          "(--weights, default 'learned'); prints one JSON line per point")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (untimed)")
+    ap.add_argument("--llr-forms", action="store_true",
+                    help="only time Alice's three LLR forms for slice 3 at 2^27 pairs (hard lower slices, "
+                         "slice 2 as a soft prior, binary-symmetric hard LLR) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -187,6 +190,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes}))
         return
+    if args.llr_forms:
+        print(json.dumps(llr_forms(args, dev)))
+        return
     if args.sweep:
         import copy
         for name in sorted(k for k in WORKLOADS if k.startswith("recon-2^27")):
@@ -203,6 +209,56 @@ def main():
     if wl.get("kind") == "train":
         return train_step(args, wl, dev)
     print(json.dumps(recon(args, wl, dev)))
+
+
+def llr_forms(args, dev):
+    """Launch time of Alice's slice-3 LLR in its three forms over 2^27 pairs at
+    SNR 3 (16 equiprobable Gray levels):
+      hard  - slices 0, 1, 2 held as bits (multistage decoding),
+      prior - slices 0, 1 as bits, slice 2 as a soft prior (a scaled LLR row),
+      bsc   - ln((1 - p) / p) with the sign of Alice's own quantised bit.
+    Algorithmic bytes per sample: x (8) + the slice bytes and prior rows read
+    + the fp32 output (4)."""
+    import torch
+
+    from paper_2108_08418_amd import api, inputs
+    N = 1 << 27
+    snr = 3.0
+    sig = math.sqrt(1.0 / snr)
+    th = inputs.equiprobable_thresholds(M_BITS, 1.0 + 1.0 / snr)
+    x_np, y_np = inputs.gaussian_pairs(N, snr, seed=args.seed)
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.from_numpy(y_np).to(dev)
+    del x_np, y_np
+    S = api.slice_quantize(y, th, M_BITS)
+    prior = torch.zeros((M_BITS, N), dtype=torch.float32, device=dev)
+    api.slice_llr(x, sig, th, M_BITS, 2, 0b11, S, out=prior[2])
+    prior[2] *= 4.0
+    out = torch.empty(N, dtype=torch.float32, device=dev)
+    p3 = 0.15
+    forms = {
+        "hard": (lambda: api.slice_llr(x, sig, th, M_BITS, 3, 0b111, S, out=out), 8 + 3 + 4),
+        "prior": (lambda: api.slice_llr_prior(x, sig, th, M_BITS, 3, 0b11, S, 0b100, prior, out=out), 8 + 2 + 4 + 4),
+        "bsc": (lambda: api.slice_llr_bsc(x, th, M_BITS, 3, p3, out=out), 8 + 4),
+    }
+    res = {}
+    for name, (fn, bps) in forms.items():
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        api.profile_enable(True)
+        api.profile_read(1, reset=True)
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        api.profile_enable(False)
+        ms, launches = api.profile_read(1, reset=True)
+        avg = ms / max(launches, 1)
+        res[name] = {"ms": round(avg, 4), "samples_per_s": N / (avg * 1e-3),
+                     "bytes_per_sample": bps, "GB_s": round(N * bps / (avg * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(N * bps / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "launches": launches}
+        print(f"# {name}: {avg:.3f} ms per launch", file=sys.stderr, flush=True)
+    return {"llr_forms": res, "n": N, "slice": 3, "bsc_p": p3, "steps": args.steps, "warmup": args.warmup}
 
 
 def recon(args, wl, dev):

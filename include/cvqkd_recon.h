@@ -118,6 +118,38 @@ cvr_status slice_llr(const double* x, int64_t n, double sigma_n, const double* t
                      int32_t m_bits, int32_t labelling, int32_t j, uint32_t known_mask,
                      const uint8_t* slices, int32_t out_dtype, void* llr_out, void* stream);
 
+/* Sec. III-B step 4 read literally: the soft decoding output (the final LLR)
+ * of lower slices enters the LLR of slice j as an a-priori weight.  As
+ * slice_llr, with every interval k of K_b also weighted by
+ *   prod_{i in prior_mask} Pr(S_i = bit i of label k),
+ *   Pr(S_i = 0) = 1 / (1 + e^-lambda_i),  Pr(S_i = 1) = 1 / (1 + e^lambda_i),
+ * lambda_i = prior_llr[i][sample] (an LLR ln P(0)/P(1), e.g. the decoder's
+ * posterior of slice i).  Slices in known_mask are hard constraints as in
+ * slice_llr.  A prior of +-inf is a hard bit (the same result as holding the
+ * slice in known_mask); lambda = 0 for every prior slice gives slice_llr with
+ * those slices unknown.  Labels cover every bit pattern, so both sums keep a
+ * label and the result is finite for any priors other than NaN (NaN in gives
+ * NaN out).  Weights whose linear form underflows take the log-domain pass.
+ * prior_llr: device fp32 [m_bits][n] (only rows in prior_mask are read; may
+ * be NULL when prior_mask == 0).  Requires known_mask, prior_mask < 2^m_bits,
+ * disjoint, and neither containing j; otherwise as slice_llr.               */
+cvr_status slice_llr_prior(const double* x, int64_t n, double sigma_n, const double* thresholds,
+                           int32_t m_bits, int32_t labelling, int32_t j, uint32_t known_mask,
+                           const uint8_t* slices, uint32_t prior_mask, const float* prior_llr,
+                           int32_t out_dtype, void* llr_out, void* stream);
+
+/* Hard soft-information: Alice's LLR for slice j when she treats her own
+ * quantised bit as the output of a binary symmetric channel with crossover p
+ * (the bit error ratio p_j estimated in Sec. II Step 4):
+ *   L_j = (1 - 2 a_j) ln((1 - p) / p),
+ * a_j = bit j of the label of x under the same quantiser as slice_quantize
+ * (thresholds, labelling).  x: device fp64 [n]; llr_out: device [n] of
+ * out_dtype (CVR_F32 or CVR_F64).  Requires 0 < p < 1 and 0 <= j < m_bits;
+ * n = 0 is a no-op.                                                          */
+cvr_status slice_llr_bsc(const double* x, int64_t n, const double* thresholds, int32_t m_bits,
+                         int32_t labelling, int32_t j, double p, int32_t out_dtype, void* llr_out,
+                         void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Syndromes                                                                  */
 /* ------------------------------------------------------------------------- */

@@ -8,5 +8,5 @@ library and never imports it.
 * :mod:`oracle.bp`      -- syndrome, flooding sum-product / normalized min-sum,
   unrolled min-sum with its reverse-mode derivative (plain C, fp64, via ctypes).
 """
-from .slicing import GRAY, BINARY, quantize, slice_llr, log_interval_probs  # noqa: F401
+from .slicing import GRAY, BINARY, quantize, slice_llr, slice_llr_prior, slice_llr_bsc, log_interval_probs  # noqa: F401
 from .bp import syndrome, decode, nms_unrolled, round_half, build, SP, NMS  # noqa: F401

@@ -99,3 +99,53 @@ def slice_llr(x, sigma_n: float, thresholds, m_bits: int, labelling: int, j: int
         l0 = logsumexp(np.where(consistent & (bitj == 0), lp, -np.inf), axis=0)
         l1 = logsumexp(np.where(consistent & (bitj == 1), lp, -np.inf), axis=0)
     return l0 - l1
+
+
+def slice_llr_prior(x, sigma_n: float, thresholds, m_bits: int, labelling: int, j: int,
+                    known_mask: int, slices, prior_mask: int, prior_llr):
+    """Alice's LLR of Bob's slice j when lower slices enter as soft priors
+    (Sec. III-B step 4 read literally: the soft decoding output of a lower
+    slice is a-priori information on the next):
+
+        L_j(x) = ln sum_{k in K_j^0} P_k(x) W_k - ln sum_{k in K_j^1} P_k(x) W_k,
+        W_k = prod_{i in prior_mask} Pr(S_i = bit i of label k),
+        Pr(S_i = 0) = 1 / (1 + e^-lambda_i),  Pr(S_i = 1) = 1 / (1 + e^lambda_i),
+
+    lambda_i = prior_llr[i] (an LLR ln P(0)/P(1)); K_j^b as in ``slice_llr``
+    (labels agreeing with the hard slices in ``known_mask``).  ``prior_llr``
+    is [m_bits, N]; only rows in ``prior_mask`` are read.  Returns fp64 [N].
+    """
+    if (known_mask | prior_mask) >> j & 1:
+        raise ValueError("slice j is already known or has a prior")
+    if known_mask & prior_mask:
+        raise ValueError("a slice cannot be both known and a prior")
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    lp = log_interval_probs(x, sigma_n, thresholds)            # [K, N]
+    labels = label_of_index(np.arange(2 ** m_bits), labelling)  # [K]
+    consistent = np.ones((2 ** m_bits, N), dtype=bool)
+    for i in range(m_bits):
+        if known_mask >> i & 1:
+            row = np.asarray(slices[i], dtype=np.int64) & 1
+            consistent &= ((labels[:, None] >> i) & 1) == row[None, :]
+        if prior_mask >> i & 1:
+            lam = np.asarray(prior_llr[i], dtype=np.float64)[None, :]
+            one = ((labels[:, None] >> i) & 1) == 1
+            # ln Pr(S_i = b) = -ln(1 + e^{-lambda}) for b = 0, -ln(1 + e^{lambda}) for b = 1
+            lp = lp - np.logaddexp(0.0, np.where(one, lam, -lam))
+    bitj = ((labels >> j) & 1)[:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l0 = logsumexp(np.where(consistent & (bitj == 0), lp, -np.inf), axis=0)
+        l1 = logsumexp(np.where(consistent & (bitj == 1), lp, -np.inf), axis=0)
+        return l0 - l1
+
+
+def slice_llr_bsc(x, thresholds, m_bits: int, labelling: int, j: int, p: float):
+    """Alice's hard LLR of Bob's slice j, her own quantised bit seen through a
+    binary symmetric channel with crossover p (the bit error ratio p_j of
+    Sec. II Step 4):  L_j = (1 - 2 a_j) ln((1 - p) / p),  a_j = bit j of the
+    label of x under the same quantiser.  Returns fp64 [N]."""
+    if not 0.0 < p < 1.0:
+        raise ValueError("p must be in (0, 1)")
+    a = quantize(x, thresholds, m_bits, labelling)[j].astype(np.float64)
+    return (1.0 - 2.0 * a) * (np.log1p(-p) - np.log(p))

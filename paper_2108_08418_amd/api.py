@@ -204,6 +204,44 @@ def slice_llr(x: torch.Tensor, sigma_n: float, thresholds, m_bits: int, j: int, 
     return out
 
 
+def slice_llr_prior(x: torch.Tensor, sigma_n: float, thresholds, m_bits: int, j: int, known_mask: int,
+                    slices: torch.Tensor | None, prior_mask: int, prior_llr: torch.Tensor | None,
+                    labelling: int = GRAY, out_dtype: int = F32, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """Alice's LLRs of Bob's slice j given x, the hard slices in known_mask and
+    the soft priors (fp32 LLR rows [m_bits, n]) of the slices in prior_mask."""
+    if x.dtype != torch.float64:
+        raise ValueError("x must be float64")
+    n = x.numel()
+    if slices is not None and (slices.dtype != torch.uint8 or not slices.is_contiguous()
+                               or slices.numel() < m_bits * n):
+        raise ValueError("slices must be contiguous uint8 [m_bits, n]")
+    if prior_llr is not None and (prior_llr.dtype != torch.float32 or not prior_llr.is_contiguous()
+                                  or prior_llr.numel() < m_bits * n):
+        raise ValueError("prior_llr must be contiguous float32 [m_bits, n]")
+    if out is None:
+        out = torch.empty(n, dtype=_TORCH_OF[out_dtype], device=x.device)
+    th = _host(thresholds, np.float64)
+    check(load().slice_llr_prior(_ptr(x), n, float(sigma_n), th.ctypes.data, int(m_bits), int(labelling), int(j),
+                                 int(known_mask), _ptr(slices), int(prior_mask), _ptr(prior_llr), int(out_dtype),
+                                 _ptr(out), _stream(stream)), "slice_llr_prior")
+    return out
+
+
+def slice_llr_bsc(x: torch.Tensor, thresholds, m_bits: int, j: int, p: float, labelling: int = GRAY,
+                  out_dtype: int = F32, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Alice's hard LLRs (1 - 2 a_j) ln((1 - p) / p) from her own quantised bit a_j."""
+    if x.dtype != torch.float64:
+        raise ValueError("x must be float64")
+    n = x.numel()
+    if out is None:
+        out = torch.empty(n, dtype=_TORCH_OF[out_dtype], device=x.device)
+    th = _host(thresholds, np.float64)
+    check(load().slice_llr_bsc(_ptr(x), n, th.ctypes.data, int(m_bits), int(labelling), int(j), float(p),
+                               int(out_dtype), _ptr(out), _stream(stream)), "slice_llr_bsc")
+    return out
+
+
 def syndrome_check(code: Code, bits: torch.Tensor, syndrome: torch.Tensor | None = None,
                    want_syndrome: bool = True, want_unsat: bool = True, stream=None,
                    out_syndrome: torch.Tensor | None = None, out_unsat: torch.Tensor | None = None):

@@ -1,8 +1,13 @@
-// Bob's quantiser/slicer and Alice's slice LLRs (Sec. III-B steps 1, 2 and 4).
+// Bob's quantiser/slicer and Alice's slice LLRs (Sec. III-B steps 1, 2 and 4),
+// with two other forms of Alice's soft information: lower slices entered as
+// soft priors (the decoder's final LLRs, Sec. III-B step 4) and the hard
+// binary-symmetric-channel LLR from her own quantised bits and the bit error
+// ratio p_j of Sec. II Step 4.
 //
-// Both kernels are streaming passes over the quadratures: one fp64 load per
-// sample plus m_bits slice bytes (quantiser) or the known slice bytes and one
-// output (LLR).  The thresholds travel by value in the kernel arguments.
+// All kernels are streaming passes over the quadratures: one fp64 load per
+// sample plus m_bits slice bytes (quantiser) or the known slice bytes, the
+// prior rows and one output (LLR).  The thresholds travel by value in the
+// kernel arguments.
 #include "cvr_internal.h"
 
 #include <cmath>
@@ -33,6 +38,20 @@ struct LlrArgs {
     int32_t gray;
     int32_t j;
     uint32_t known;
+    int32_t out_f64;
+    const float* prior;    // [m_bits][n]; rows in prior_mask read (prior form only)
+    uint32_t prior_mask;
+    double t[kMaxThr];
+};
+
+struct BscArgs {
+    const double* x;
+    void* out;
+    int64_t n;
+    double p;
+    int32_t nthr;
+    int32_t gray;
+    int32_t j;
     int32_t out_f64;
     double t[kMaxThr];
 };
@@ -124,6 +143,12 @@ __device__ __forceinline__ double interval_prob(double lo, double hi)
     return (lo >= 0.0) ? 0.5 * (ea - eb) : 1.0 - 0.5 * (ea + eb);
 }
 
+// ln(1 + e^z) without overflow; +inf at z = +inf, 0 at z = -inf.
+__device__ __forceinline__ double softplus(double z)
+{
+    return fmax(z, 0.0) + log1p(exp(-fabs(z)));
+}
+
 // One thread per sample.  Only the 2^(m - |known|) labels that agree with the
 // sample's known slice bits are visited (a uniform trip count: the free bit
 // positions are the same for every sample), so wavefronts do not diverge over
@@ -133,6 +158,11 @@ __device__ __forceinline__ double interval_prob(double lo, double hi)
 // per interval, one log per sample); a sample whose smaller sum falls below
 // 1e-290, where erfc would lose relative accuracy or underflow, is redone in
 // the log domain (ln_interval and a running log-sum-exp).
+// PRIOR: each label is also weighted by prod_i Pr(S_i = bit i of the label)
+// over the slices i in prior_mask, with Pr(S_i = 0) = 1 / (1 + e^-lambda_i),
+// Pr(S_i = 1) = 1 / (1 + e^lambda_i) from the prior LLR lambda_i of the sample
+// (ln of the logistic factor, -softplus, in the log-domain pass).
+template <bool PRIOR>
 __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
 {
     __shared__ double bnd[kMaxThr + 2];
@@ -150,8 +180,10 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
         for (int q = 0; q < a.m_bits; ++q)
             if ((a.known >> q) & 1u) kb |= uint32_t(a.slices[int64_t(q) * a.n + i] & 1) << q;
         // interval index and bit j of the c-th label consistent with the known bits
-        auto label = [&](int c, uint32_t& k) {
-            uint32_t g = kb, fm = freemask;
+        // (g is the label's bit pattern, k its interval)
+        auto label = [&](int c, uint32_t& k, uint32_t& g) {
+            uint32_t fm = freemask;
+            g = kb;
             for (int b = 0; b < nfree; ++b) {
                 const uint32_t low = fm & (~fm + 1u);
                 if ((c >> b) & 1) g |= low;
@@ -162,11 +194,36 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
                 for (uint32_t sh = 1; sh < 8; sh <<= 1) k ^= k >> sh;
             return (g >> a.j) & 1u;
         };
+        // prior LLR of each slice in prior_mask (PRIOR only), by slice index, and
+        // its two logistic factors Pr(S_q = 0), Pr(S_q = 1) for the linear pass
+        double lam[8], pr0[8], pr1[8];
+        if constexpr (PRIOR) {
+            for (int q = 0; q < 8; ++q) {
+                const bool on = q < a.m_bits && ((a.prior_mask >> q) & 1u);
+                lam[q] = on ? double(a.prior[int64_t(q) * a.n + i]) : 0.0;
+                pr0[q] = on ? 1.0 / (1.0 + exp(-lam[q])) : 1.0;
+                pr1[q] = on ? 1.0 / (1.0 + exp(lam[q])) : 1.0;
+            }
+        }
+        // the label's prior weight, linear or logarithmic
+        auto prior_w = [&](uint32_t g) {
+            double w = 1.0;
+            for (int q = 0; q < 8; ++q)
+                if ((a.prior_mask >> q) & 1u) w *= ((g >> q) & 1u) ? pr1[q] : pr0[q];
+            return w;
+        };
+        auto prior_lnw = [&](uint32_t g) {
+            double w = 0.0;
+            for (int q = 0; q < 8; ++q)
+                if ((a.prior_mask >> q) & 1u) w -= softplus(((g >> q) & 1u) ? lam[q] : -lam[q]);
+            return w;
+        };
         double p0 = 0.0, p1 = 0.0;
         for (int c = 0; c < (1 << nfree); ++c) {
-            uint32_t k;
-            const uint32_t bit = label(c, k);
-            const double p = interval_prob((bnd[k] - x) * inv_sigma, (bnd[k + 1] - x) * inv_sigma);
+            uint32_t k, g;
+            const uint32_t bit = label(c, k, g);
+            double p = interval_prob((bnd[k] - x) * inv_sigma, (bnd[k + 1] - x) * inv_sigma);
+            if constexpr (PRIOR) p *= prior_w(g);
             if (bit) p1 += p;
             else p0 += p;
         }
@@ -176,14 +233,33 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
         } else {
             double m0 = -INFINITY, s0 = 0.0, m1 = -INFINITY, s1 = 0.0;
             for (int c = 0; c < (1 << nfree); ++c) {
-                uint32_t k;
-                const uint32_t bit = label(c, k);
-                const double lp = ln_interval((bnd[k] - x) / a.sigma, (bnd[k + 1] - x) / a.sigma);
+                uint32_t k, g;
+                const uint32_t bit = label(c, k, g);
+                double lp = ln_interval((bnd[k] - x) / a.sigma, (bnd[k + 1] - x) / a.sigma);
+                if constexpr (PRIOR) lp += prior_lnw(g);
                 if (bit) lse_push(m1, s1, lp);
                 else lse_push(m0, s0, lp);
             }
             L = (m0 + log(s0)) - (m1 + log(s1));
         }
+        if (a.out_f64) static_cast<double*>(a.out)[i] = L;
+        else static_cast<float*>(a.out)[i] = float(L);
+    }
+}
+
+// Hard LLR of a binary symmetric channel with crossover p: Alice quantises
+// her own x with the same thresholds and labelling, takes bit j of the label
+// (a_j), and outputs (1 - 2 a_j) ln((1 - p) / p).  One thread per sample.
+__global__ __launch_bounds__(256) void k_slice_llr_bsc(BscArgs a)
+{
+    const double mag = log1p(-a.p) - log(a.p);
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const double x = a.x[i];
+        int k = 0;
+        for (int q = 0; q < a.nthr; ++q) k += (a.t[q] <= x) ? 1 : 0;
+        const int g = a.gray ? (k ^ (k >> 1)) : k;
+        const double L = ((g >> a.j) & 1) ? -mag : mag;
         if (a.out_f64) static_cast<double*>(a.out)[i] = L;
         else static_cast<float*>(a.out)[i] = float(L);
     }
@@ -265,6 +341,76 @@ extern "C" cvr_status slice_llr(const double* x, int64_t n, double sigma_n, cons
     a.out_f64 = out_dtype == CVR_F64;
     for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
     ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
-    hipLaunchKernelGGL(k_slice_llr, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    hipLaunchKernelGGL(k_slice_llr<false>, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
     return check_launch("slice_llr");
+}
+
+extern "C" cvr_status slice_llr_prior(const double* x, int64_t n, double sigma_n, const double* thresholds,
+                                      int32_t m_bits, int32_t labelling, int32_t j, uint32_t known_mask,
+                                      const uint8_t* slices, uint32_t prior_mask, const float* prior_llr,
+                                      int32_t out_dtype, void* llr_out, void* stream)
+{
+    if (n < 0) return fail(CVR_EINVAL, "slice_llr_prior: n < 0");
+    if (labelling != CVR_GRAY && labelling != CVR_BINARY) return fail(CVR_EINVAL, "slice_llr_prior: bad labelling");
+    if (cvr_status st = check_thresholds("slice_llr_prior", thresholds, m_bits)) return st;
+    if (!(sigma_n > 0.0) || !std::isfinite(sigma_n))
+        return fail(CVR_EINVAL, "slice_llr_prior: sigma_n must be finite and > 0");
+    if (j < 0 || j >= m_bits) return fail(CVR_EINVAL, "slice_llr_prior: j out of range");
+    if ((known_mask >> m_bits) || (prior_mask >> m_bits))
+        return fail(CVR_EINVAL, "slice_llr_prior: known_mask or prior_mask has bits >= m_bits");
+    if (((known_mask | prior_mask) >> j) & 1u)
+        return fail(CVR_EINVAL, "slice_llr_prior: slice j is in known_mask or prior_mask");
+    if (known_mask & prior_mask) return fail(CVR_EINVAL, "slice_llr_prior: known_mask and prior_mask overlap");
+    if (out_dtype != CVR_F32 && out_dtype != CVR_F64)
+        return fail(CVR_EINVAL, "slice_llr_prior: out_dtype must be F32 or F64");
+    if (n == 0) return CVR_OK;
+    if (!x || !llr_out) return fail(CVR_EINVAL, "slice_llr_prior: NULL x or llr_out");
+    if (known_mask && !slices) return fail(CVR_EINVAL, "slice_llr_prior: known_mask set but slices is NULL");
+    if (prior_mask && !prior_llr) return fail(CVR_EINVAL, "slice_llr_prior: prior_mask set but prior_llr is NULL");
+    LlrArgs a{};
+    a.x = x;
+    a.slices = slices;
+    a.out = llr_out;
+    a.n = n;
+    a.sigma = sigma_n;
+    a.m_bits = m_bits;
+    a.nthr = (1 << m_bits) - 1;
+    a.gray = labelling == CVR_GRAY;
+    a.j = j;
+    a.known = known_mask;
+    a.out_f64 = out_dtype == CVR_F64;
+    a.prior = prior_llr;
+    a.prior_mask = prior_mask;
+    for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
+    ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
+    hipLaunchKernelGGL(k_slice_llr<true>, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    return check_launch("slice_llr_prior");
+}
+
+extern "C" cvr_status slice_llr_bsc(const double* x, int64_t n, const double* thresholds, int32_t m_bits,
+                                    int32_t labelling, int32_t j, double p, int32_t out_dtype, void* llr_out,
+                                    void* stream)
+{
+    if (n < 0) return fail(CVR_EINVAL, "slice_llr_bsc: n < 0");
+    if (labelling != CVR_GRAY && labelling != CVR_BINARY) return fail(CVR_EINVAL, "slice_llr_bsc: bad labelling");
+    if (cvr_status st = check_thresholds("slice_llr_bsc", thresholds, m_bits)) return st;
+    if (j < 0 || j >= m_bits) return fail(CVR_EINVAL, "slice_llr_bsc: j out of range");
+    if (!(p > 0.0 && p < 1.0)) return fail(CVR_EINVAL, "slice_llr_bsc: p must be in (0, 1)");
+    if (out_dtype != CVR_F32 && out_dtype != CVR_F64)
+        return fail(CVR_EINVAL, "slice_llr_bsc: out_dtype must be F32 or F64");
+    if (n == 0) return CVR_OK;
+    if (!x || !llr_out) return fail(CVR_EINVAL, "slice_llr_bsc: NULL x or llr_out");
+    BscArgs a{};
+    a.x = x;
+    a.out = llr_out;
+    a.n = n;
+    a.p = p;
+    a.nthr = (1 << m_bits) - 1;
+    a.gray = labelling == CVR_GRAY;
+    a.j = j;
+    a.out_f64 = out_dtype == CVR_F64;
+    for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
+    ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
+    hipLaunchKernelGGL(k_slice_llr_bsc, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    return check_launch("slice_llr_bsc");
 }

@@ -58,6 +58,18 @@ def test_host_side_argument_checks(lib):
     assert b"already" in lib.cvr_last_error()
     assert lib.slice_llr(None, 10, -1.0, th_ok.ctypes.data, 2, 0, 1, 0, None, 1, None, None) == -1
     assert lib.slice_llr(None, 10, 0.5, th_ok.ctypes.data, 2, 0, 1, 0, None, 7, None, None) == -1
+    # soft-prior and binary-symmetric forms
+    assert lib.slice_llr_prior(None, 10, 0.5, th_ok.ctypes.data, 2, 0, 1, 0b1, None, 0b1, None, 1, None, None) == -1
+    assert b"overlap" in lib.cvr_last_error()
+    assert lib.slice_llr_prior(None, 10, 0.5, th_ok.ctypes.data, 2, 0, 1, 0, None, 0b10, None, 1, None, None) == -1
+    assert b"slice j" in lib.cvr_last_error()
+    assert lib.slice_llr_prior(None, 10, 0.5, th_ok.ctypes.data, 2, 0, 0, 0, None, 0b100, None, 1, None, None) == -1
+    assert lib.slice_llr_prior(None, 0, 0.5, th_ok.ctypes.data, 2, 0, 0, 0, None, 0b10, None, 1, None, None) == 0
+    assert lib.slice_llr_bsc(None, 10, th_ok.ctypes.data, 2, 0, 0, 0.0, 1, None, None) == -1
+    assert b"p must be" in lib.cvr_last_error()
+    assert lib.slice_llr_bsc(None, 10, th_ok.ctypes.data, 2, 0, 0, 1.0, 1, None, None) == -1
+    assert lib.slice_llr_bsc(None, 10, th_ok.ctypes.data, 2, 0, 2, 0.1, 1, None, None) == -1
+    assert lib.slice_llr_bsc(None, 0, th_ok.ctypes.data, 2, 0, 1, 0.1, 1, None, None) == 0
     # malformed CSR: columns not ascending / out of range / degree 0
     h = C.c_void_p()
     rp = np.array([0, 2, 4], np.int32)

@@ -109,6 +109,94 @@ def test_slice_llr_one_bit_closed_form():
     np.testing.assert_allclose(Lg, ref, rtol=1e-12, atol=1e-12)
 
 
+def _same_nonfinite_then_rel(got, ref, rel):
+    """Non-finite outputs (+-inf, NaN) at the same places with the same value;
+    finite ones within rel * max(1, |ref|)."""
+    fin = np.isfinite(ref)
+    np.testing.assert_array_equal(np.isfinite(got), fin)
+    np.testing.assert_array_equal(got[~fin], ref[~fin])     # NaN == NaN under assert_array_equal
+    err = np.abs(got[fin] - ref[fin]) / np.maximum(1.0, np.abs(ref[fin]))
+    assert err.size == 0 or err.max() <= rel, (err.max(), int(np.nonzero(fin)[0][err.argmax()]))
+
+
+def _priors(rng, N):
+    """Prior LLR rows [4, N]: decoder-like magnitudes, zeros, values whose
+    logistic factor underflows in linear fp64 (|lambda| ~ 1e3) and +-inf."""
+    lam = rng.normal(0.0, 8.0, size=(4, N))
+    sel = rng.random((4, N))
+    lam[sel < 0.05] = 0.0
+    big = (sel >= 0.05) & (sel < 0.08)
+    lam[big] = np.sign(lam[big]) * rng.uniform(700.0, 3000.0, big.sum())
+    inf = (sel >= 0.08) & (sel < 0.09)
+    lam[inf] = np.where(rng.random(inf.sum()) < 0.5, np.inf, -np.inf)
+    return lam.astype(np.float32)
+
+
+@pytest.mark.parametrize("j,known,prior", [(3, 0b11, 0b100), (2, 0b1, 0b10), (1, 0, 0b1101), (3, 0, 0b111)])
+def test_slice_llr_prior_fp64_parity(j, known, prior):
+    print(f"[slice_llr_prior j={j} known={known:b} prior={prior:b}]", flush=True)
+    N = (1 << 18) + 13
+    x, y = inputs.gaussian_pairs(N, SNR, seed=60 + j)
+    x[:33] = np.linspace(-30, 30, 33)           # far tails: the log-domain pass
+    S = oracle.quantize(y, TH4, 4)
+    lam = _priors(np.random.default_rng(61 + j), N)
+    Lg = api.slice_llr_prior(_g(x), SIG, TH4, 4, j, known, _g(S), prior, _g(lam), out_dtype=api.F64)
+    torch.cuda.synchronize()
+    Lo = oracle.slice_llr_prior(x, SIG, TH4, 4, oracle.GRAY, j, known, S, prior, lam)
+    _same_nonfinite_then_rel(Lg.cpu().numpy(), Lo, 1e-12)
+
+
+def test_slice_llr_prior_chain_fp32_output():
+    """The literal chain at SNR 3: slices 0 and 1 disclosed, the soft output
+    of slice 2 (here its own LLR, scaled like a converged posterior) as the
+    prior of slice 3.  fp32 output is the fp64 value rounded (one ulp)."""
+    N = (1 << 20) + 7
+    x, y = inputs.gaussian_pairs(N, SNR, seed=62)
+    S = oracle.quantize(y, TH4, 4)
+    lam = np.zeros((4, N), np.float32)
+    lam[2] = (4.0 * oracle.slice_llr(x, SIG, TH4, 4, oracle.GRAY, 2, 0b11, S)).astype(np.float32)
+    L32 = api.slice_llr_prior(_g(x), SIG, TH4, 4, 3, 0b11, _g(S), 0b100, _g(lam), out_dtype=api.F32)
+    torch.cuda.synchronize()
+    ref = oracle.slice_llr_prior(x, SIG, TH4, 4, oracle.GRAY, 3, 0b11, S, 0b100, lam).astype(np.float32)
+    got = L32.cpu().numpy()
+    assert np.isfinite(ref).all()
+    ulp = np.spacing(np.abs(ref)).astype(np.float64)
+    assert (np.abs(got.astype(np.float64) - ref) <= ulp).all()
+
+
+def test_slice_llr_prior_hard_priors_equal_known_slices_on_gpu():
+    N = 50_001
+    x, y = inputs.gaussian_pairs(N, SNR, seed=63)
+    S = oracle.quantize(y, TH4, 4)
+    lam = np.where(S == 0, np.inf, -np.inf).astype(np.float32)
+    Lp = api.slice_llr_prior(_g(x), SIG, TH4, 4, 3, 0b11, _g(S), 0b100, _g(lam), out_dtype=api.F64)
+    Lk = api.slice_llr(_g(x), SIG, TH4, 4, 3, 0b111, _g(S), out_dtype=api.F64)
+    torch.cuda.synchronize()
+    err = np.abs(Lp.cpu().numpy() - Lk.cpu().numpy()) / np.maximum(1.0, np.abs(Lk.cpu().numpy()))
+    assert err.max() <= 1e-13
+
+
+@pytest.mark.parametrize("n", [(1 << 20) + 5, 1003, 1, 0])
+def test_slice_llr_bsc_parity(n):
+    print(f"[slice_llr_bsc n={n}]", flush=True)
+    x, _ = inputs.gaussian_pairs(max(n, 1), SNR, seed=64)
+    x = x[:n].copy()
+    if n > 100:
+        x[:15] = TH4                            # values on a threshold go up, as in the quantiser
+    xg = _g(x)
+    for j, p in [(0, 0.31), (1, 0.22), (2, 0.11), (3, 0.013)]:
+        L64 = api.slice_llr_bsc(xg, TH4, 4, j, p, out_dtype=api.F64)
+        L32 = api.slice_llr_bsc(xg, TH4, 4, j, p, out_dtype=api.F32)
+        torch.cuda.synchronize()
+        ref = oracle.slice_llr_bsc(x, TH4, 4, oracle.GRAY, j, p)
+        g64 = L64.cpu().numpy()
+        np.testing.assert_array_equal(np.signbit(g64), np.signbit(ref))
+        np.testing.assert_allclose(g64, ref, rtol=4.5e-16, atol=0)
+        r32 = ref.astype(np.float32)
+        ulp = np.spacing(np.abs(r32)).astype(np.float64)
+        assert (np.abs(L32.cpu().numpy().astype(np.float64) - r32) <= ulp).all()
+
+
 @pytest.mark.parametrize("which", ["regular", "qc2", "qc3", "qc_z96", "qc_z32", "met_z64", "qc_z32_f77"])
 def test_syndrome_bit_exact(which):
     """Explicit codes take the gather kernel, QC codes the circulant kernel

@@ -195,3 +195,87 @@ def test_slice_code_rates_respect_slepian_wolf(j, code_rate):
     q = I.slice_code_spec(j, 65536)
     assert abs((q.nb - q.mb) / q.nb - code_rate) < 1e-12
     assert 1 - code_rate >= _conditional_entropy_quadrature(j)
+
+
+# ---------------------------------------------------------------------------
+# soft priors from lower slices, and the binary-symmetric-channel hard LLR
+# ---------------------------------------------------------------------------
+def _mp_slice_llr_prior(x, j, known_bits, priors, sig, th):
+    """80-digit enumeration of the 16 intervals: P_k(x) from the normal CDF,
+    times Pr(S_i = b) = 1 / (1 + exp(-(1 - 2b) lambda_i)) for each prior slice."""
+    mp.mp.dps = 80
+    t = [None] + list(th) + [None]
+    num = mp.mpf(0)
+    den = mp.mpf(0)
+    for k in range(16):
+        g = _gray(k)
+        if any(((g >> i) & 1) != b for i, b in known_bits.items()):
+            continue
+        p = mp.e ** _mp_log_interval(x, t[k], t[k + 1], sig)
+        for i, lam in priors.items():
+            s = 1 - 2 * ((g >> i) & 1)
+            p *= 1 / (1 + mp.e ** (-s * mp.mpf(lam)))
+        if (g >> j) & 1:
+            den += p
+        else:
+            num += p
+    return float(mp.log(num) - mp.log(den))
+
+
+@pytest.mark.parametrize("j,known,prior", [(3, 0b11, 0b100), (2, 0b1, 0b10), (1, 0, 0b1101), (3, 0, 0b111)])
+def test_slice_llr_prior_matches_high_precision_enumeration(j, known, prior):
+    rng = np.random.default_rng(40 + j + known)
+    xs = np.concatenate([np.linspace(-6, 6, 7), rng.normal(0, 1.5, 4)])
+    slices = rng.integers(0, 2, size=(4, len(xs))).astype(np.uint8)
+    lam = (rng.normal(0, 6, size=(4, len(xs)))).astype(np.float32)
+    L = oracle.slice_llr_prior(xs, SIG, TH4, 4, oracle.GRAY, j, known, slices, prior, lam)
+    for i, x in enumerate(xs.tolist()):
+        kb = {b: int(slices[b, i]) for b in range(4) if known >> b & 1}
+        pr = {b: float(lam[b, i]) for b in range(4) if prior >> b & 1}
+        ref = _mp_slice_llr_prior(x, j, kb, pr, SIG, TH4)
+        assert abs(L[i] - ref) <= 1e-12 * max(1.0, abs(ref)), (x, L[i], ref)
+
+
+def test_hard_priors_equal_known_slices():
+    """A prior of +inf (bit 0 certain) or -inf (bit 1 certain) is the same as
+    holding that slice as a hard known bit."""
+    rng = np.random.default_rng(7)
+    xs = rng.normal(0, 1.2, 3000)
+    slices = rng.integers(0, 2, size=(4, xs.size)).astype(np.uint8)
+    lam = np.where(slices == 0, np.inf, -np.inf).astype(np.float32)
+    for j, hard in [(2, 0b11), (3, 0b111), (1, 0b1)]:
+        soft = 1 << (int(hard).bit_length() - 1)         # the highest known slice becomes a prior
+        Lp = oracle.slice_llr_prior(xs, SIG, TH4, 4, oracle.GRAY, j, hard & ~soft, slices, soft, lam)
+        Lk = oracle.slice_llr(xs, SIG, TH4, 4, oracle.GRAY, j, hard, slices)
+        np.testing.assert_allclose(Lp, Lk, rtol=1e-14, atol=0)
+
+
+def test_zero_priors_equal_unknown_slices():
+    """lambda = 0 is no information: every label gets the same factor 1/2."""
+    rng = np.random.default_rng(8)
+    xs = rng.normal(0, 1.2, 3000)
+    slices = rng.integers(0, 2, size=(4, xs.size)).astype(np.uint8)
+    lam = np.zeros((4, xs.size), np.float32)
+    Lp = oracle.slice_llr_prior(xs, SIG, TH4, 4, oracle.GRAY, 3, 0b1, slices, 0b110, lam)
+    Lu = oracle.slice_llr(xs, SIG, TH4, 4, oracle.GRAY, 3, 0b1, slices)
+    np.testing.assert_allclose(Lp, Lu, rtol=1e-12, atol=1e-12)
+
+
+def test_bsc_llr_closed_forms():
+    rng = np.random.default_rng(9)
+    xs = rng.normal(0, 1.0, 5000)
+    # sign: Alice's own quantised bit j (brute-force label below), magnitude ln((1-p)/p)
+    k = np.array([sum(1 for t in TH4 if t <= v) for v in xs])
+    for j in range(4):
+        bit = (_gray(k) >> j) & 1
+        for p in (0.03, 0.2, 0.45):
+            L = oracle.slice_llr_bsc(xs, TH4, 4, oracle.GRAY, j, p)
+            # d/dp of the binary entropy in nats is ln((1-p)/p): central difference
+            h = 1e-6
+            Hn = lambda q: -q * math.log(q) - (1 - q) * math.log(1 - q)
+            mag = (Hn(p + h) - Hn(p - h)) / (2 * h)
+            np.testing.assert_allclose(np.abs(L), mag, rtol=1e-8)
+            np.testing.assert_array_equal(L < 0, bit == 1)
+        np.testing.assert_array_equal(oracle.slice_llr_bsc(xs, TH4, 4, oracle.GRAY, j, 0.5), 0.0)
+        np.testing.assert_allclose(oracle.slice_llr_bsc(xs, TH4, 4, oracle.GRAY, j, 0.9),
+                                   -oracle.slice_llr_bsc(xs, TH4, 4, oracle.GRAY, j, 0.1), rtol=1e-15)
