@@ -363,6 +363,21 @@ def recon(args, wl, dev):
     iters = {j: outs[j]["iters"].cpu().numpy() for j in (2, 3)}
     ok = {j: outs[j]["ok"].cpu().numpy() for j in (2, 3)}
     bit_err = {j: int((alice[j] != bob[j]).sum().item()) for j in (2, 3)}
+    # the Gaussian-approximation iteration count (host model) beside the measured
+    # mean: a binary-input AWGN channel carrying the capacity that Alice's LLRs
+    # (given Bob's true lower slices) carry about Bob's bits, the code's own
+    # degree distributions, target bit error ratio 1/n
+    from paper_2108_08418_amd import ga
+    ga_pred = {}
+    for j in (2, 3):
+        api.slice_llr(x, sig, th, M_BITS, j, (1 << j) - 1, bob, out=llr)
+        sgn = 1.0 - 2.0 * bob[j].to(torch.float64)
+        cap = 1.0 - float(torch.nn.functional.softplus(-sgn * llr.to(torch.float64)).mean()) / math.log(2.0)
+        csr_j = qcs[j].to_csr()
+        lam, rho = ga.degree_distributions(csr_j.row_ptr, csr_j.col_idx, n)
+        m0 = ga.biawgn_mean_for_capacity(cap)
+        ga_pred[str(j)] = {"capacity": round(cap, 4), "m0": round(m0, 4),
+                           "iters_to_ber_1_over_n": ga.iterations_to(1.0 / n, m0, lam, rho)}
     s_msg = 4 if store == api.F32 else 2
     chk_bytes = 0.0
     iter_bytes = 0.0
@@ -413,7 +428,8 @@ def recon(args, wl, dev):
         "data": "synthetic: seeded Gaussian pairs, SNR 3, seeded QC-LDPC slice codes",
         "config": {
             "workload": args.workload, "pairs": N, "sub_block": n, "sub_blocks_per_slice": F,
-            "slices": "16 equiprobable Gray intervals; slices 0-1 disclosed, 2 (R=0.1875) and 3 (R=0.4922) decoded",
+            "slices": ("16 equiprobable Gray intervals; slices 0-1 disclosed, "
+                       f"2 (R={1 - qcs[2].m / n:.4f}) and 3 (R={1 - qcs[3].m / n:.4f}) decoded"),
             "decoder": ("sum-product" if algo == api.SP else
                         (f"learned normalized min-sum ({args.weights})" if args.weights else
                          f"normalized min-sum alpha={args.alpha}")),
@@ -453,6 +469,7 @@ def recon(args, wl, dev):
         "fer": {str(j): float(1.0 - ok[j].mean()) for j in (2, 3)},
         "fer_wilson95": {str(j): wilson95(int((ok[j] == 0).sum()), len(ok[j])) for j in (2, 3)},
         "mean_iters": {str(j): float(iters[j].mean()) for j in (2, 3)},
+        "ga_iterations": ga_pred,
         "bit_errors_vs_bob": bit_err,
         "reconciled_pairs_per_s": N / (t_total / args.steps),
     }
