@@ -1,0 +1,92 @@
+"""Pins of the finite-length key-rate model (Sec. IV): the paper's printed
+derivative of K'_Finite against the numerical derivative of the implemented
+K'_Finite (which fixes the form of C_Finite, including the sign and the
+natural logarithm of its (1/2) ln N_R term), the optimiser against a brute
+force search, and the leading-order optimum.  S_BE is an input (its appendix
+is not modelled): the paper's N_R* = 3.6e7 is reproduced only through the
+margin it implies -- parity unpinned for S_BE itself."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2108_08418_amd import keyrate as kr
+
+GAMMA = 2.2147                       # the paper's standard settings (gamma from its SNR equation)
+N = 1e9
+M_BITS = 5
+E_EC = E_PA = E_PE = 2.5e-10
+E_S = 1.25e-10
+EPS = E_EC + 2 * E_S + E_PA + E_PE
+LAM = {2: 0.25, 3: 0.3, 8: 0.45}
+
+
+def _setup(S_BE):
+    I = kr.capacity(GAMMA)
+    A = kr.dispersion(GAMMA)
+    B1 = kr.b1(N, S_BE, kr.delta_aep(M_BITS, N, E_S, EPS), E_PA)
+    B2 = kr.b2(3.2e-9, [20] * M_BITS, [LAM] * M_BITS)
+    return I, A, B1, B2
+
+
+def test_capacity_dispersion_and_q_inverse():
+    assert kr.capacity(3.0) == 1.0
+    assert abs(kr.q_inv(0.5)) < 1e-15 and abs(kr.q_inv(0.0227501319481792) - 2.0) < 1e-9
+    assert abs(kr.q_inv(2.5e-10) - 6.219) < 1e-3
+    # dispersion of the AWGN channel in bits^2: -> (log2 e)^2 / 2 at high SNR, ~ gamma (log2 e)^2 at low
+    assert abs(kr.dispersion(1e9) / (0.5 / math.log(2) ** 2) - 1) < 1e-8
+    assert abs(kr.dispersion(1e-9) / (1e-9 / math.log(2) ** 2) - 1) < 1e-8
+
+
+@pytest.mark.parametrize("S_BE_frac", [0.0, 0.9, 0.99])
+def test_printed_derivative_equals_numerical_derivative(S_BE_frac):
+    I, A, B1, B2 = _setup(S_BE_frac * kr.capacity(GAMMA))
+    for NR in (1e5, 1e6, 3.6e7, 5e8):
+        h = NR * 1e-5
+        num = (kr.k_prime(NR + h, N, I, A, E_EC, B1, B2) - kr.k_prime(NR - h, N, I, A, E_EC, B1, B2)) / (2 * h)
+        got = kr.dk_prime(NR, N, I, A, E_EC, B1, B2)
+        assert abs(got - num) <= 1e-6 * abs(num), (NR, got, num)
+
+
+def _margin_setup(M):
+    """S_BE chosen so that the net margin I_AB - B_1 / N equals M."""
+    I, A, _, B2 = _setup(0.0)
+    d = kr.delta_aep(M_BITS, N, E_S, EPS)
+    S_BE = I - M - (math.sqrt(N) * d + 2 * math.log2(1 / (2 * E_PA))) / N
+    B1 = kr.b1(N, S_BE, d, E_PA)
+    assert abs(I - B1 / N - M) < 1e-12
+    return I, A, B1, B2
+
+
+@pytest.mark.parametrize("M", [5e-4, 1.5e-3, 5e-3])
+def test_optimiser_matches_brute_force(M):
+    I, A, B1, B2 = _margin_setup(M)
+    r, k = kr.optimal_nr(N, I, A, E_EC, B1, B2)
+    grid = np.logspace(5, 9, 40001)
+    kv = np.array([kr.k_prime(g, N, I, A, E_EC, B1, B2) for g in grid])
+    best = grid[kv.argmax()]
+    assert abs(math.log(r / best)) <= math.log(grid[1] / grid[0]) + 1e-12
+    assert k >= kv.max() * (1 - 1e-12)
+
+
+def test_leading_order_optimum_and_the_papers_value():
+    """Without the ln term, dK'/dN_R = 0 gives N_R* = (3 sqrt(A) Q^-1 / (2 M))^2;
+    the paper's N_R* = 3.6e7 corresponds to a margin M of about 1.5e-3."""
+    I, A, B1, B2 = _margin_setup(1.5e-3)
+    r, _ = kr.optimal_nr(N, I, A, E_EC, B1, B2)
+    lead = (3 * math.sqrt(A) * kr.q_inv(E_EC) / (2 * 1.5e-3)) ** 2
+    assert abs(r / lead - 1) < 0.05, (r, lead)
+    assert abs(r / 3.6e7 - 1) < 0.1, r
+    # N_R* does not depend on the hardware constant c_h or on the iteration counts (B_2 scales K')
+    r2, _ = kr.optimal_nr(N, I, A, E_EC, B1, B2 * 1e-4)
+    assert abs(r2 / r - 1) < 1e-9
+
+
+def test_boundary_optima():
+    # a large margin: K' falls everywhere, the smallest allowed N_R wins
+    I, A, B1, B2 = _setup(0.0)
+    r, _ = kr.optimal_nr(N, I, A, E_EC, B1, B2)
+    assert r == 1e5
+    # a negative margin: no key at any N_R, K' < 0 throughout
+    I, A, B1, B2 = _margin_setup(-1e-3)
+    assert all(kr.k_prime(g, N, I, A, E_EC, B1, B2) < 0 for g in (1e5, 1e7, 1e9))
