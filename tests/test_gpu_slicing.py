@@ -109,6 +109,38 @@ def test_slice_llr_one_bit_closed_form():
     np.testing.assert_allclose(Lg, ref, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("m_bits", [1, 3, 5, 8])
+@pytest.mark.parametrize("lab", [api.GRAY, api.BINARY])
+def test_slice_llr_forms_other_widths_and_labellings(m_bits, lab):
+    """Constant-step quantisers of 1 ... 8 bits (the paper's m = 5 among them),
+    both labellings: the hard, soft-prior and binary-symmetric forms against
+    the oracle, for the top slice and a middle one."""
+    print(f"[slice_llr forms m={m_bits} lab={lab}]", flush=True)
+    N = 20_011
+    x, y = inputs.gaussian_pairs(N, SNR, seed=70 + m_bits)
+    th = inputs.constant_step_thresholds(m_bits, 3.0 / 2 ** m_bits)
+    S = oracle.quantize(y, th, m_bits, lab)
+    olab = oracle.GRAY if lab == api.GRAY else oracle.BINARY
+    lam = _priors(np.random.default_rng(71 + m_bits), N) if m_bits <= 4 else \
+        np.random.default_rng(71).normal(0, 6, size=(m_bits, N)).astype(np.float32)
+    xg, Sg, lg = _g(x), _g(S), _g(lam)
+    for j in sorted({m_bits - 1, m_bits // 2}):
+        known = (1 << j) - 1
+        Lg = api.slice_llr(xg, SIG, th, m_bits, j, known, Sg, labelling=lab, out_dtype=api.F64)
+        torch.cuda.synchronize()
+        _same_nonfinite_then_rel(Lg.cpu().numpy(), oracle.slice_llr(x, SIG, th, m_bits, olab, j, known, S), 1e-12)
+        if j >= 1:                                 # lowest known slice moved into the priors
+            Lp = api.slice_llr_prior(xg, SIG, th, m_bits, j, known & ~1, Sg, 1, lg, labelling=lab,
+                                     out_dtype=api.F64)
+            torch.cuda.synchronize()
+            ref = oracle.slice_llr_prior(x, SIG, th, m_bits, olab, j, known & ~1, S, 1, lam)
+            _same_nonfinite_then_rel(Lp.cpu().numpy(), ref, 1e-12)
+        Lb = api.slice_llr_bsc(xg, th, m_bits, j, 0.07, labelling=lab, out_dtype=api.F64)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(Lb.cpu().numpy(), oracle.slice_llr_bsc(x, th, m_bits, olab, j, 0.07),
+                                   rtol=4.5e-16, atol=0)
+
+
 def _same_nonfinite_then_rel(got, ref, rel):
     """Non-finite outputs (+-inf, NaN) at the same places with the same value;
     finite ones within rel * max(1, |ref|)."""
