@@ -25,7 +25,7 @@ __all__ = [
     "CsrCode", "QcCode", "largest_remainder", "regular_code", "irregular_code",
     "qc_protograph_code", "gaussian_pairs", "bpsk_llr", "random_bits",
     "equiprobable_thresholds", "LAMBDA_NODE_FRACTIONS", "slice_code_spec",
-    "met_low_rate_spec", "lambda_half_rate_spec",
+    "met_low_rate_spec", "lambda_half_rate_spec", "slice_code_at",
 ]
 
 # lambda(x) = 0.25 x + 0.3 x^2 + 0.45 x^7 (edge perspective).  Node-perspective
@@ -329,10 +329,17 @@ def slice_code_spec(slice_j: int, n: int, seed: int = 2108) -> QcCode:
     Slice 2 (C = 0.3153): 0.284 and 0.234 fail, 0.184 passes -> mb = 104,
     R = 0.1875.  Slice 3 (C = 0.5469): 0.492 fails, 0.442 passes -> mb = 71,
     R = 0.4453125.  Column permutation, row order and shifts are seeded."""
+    return slice_code_at(slice_j, n, {2: 104, 3: 71}[slice_j], seed)
+
+
+def slice_code_at(slice_j: int, n: int, mb: int, seed: int = 2108) -> QcCode:
+    """The slice-``slice_j`` code family at mb of the nb = 128 block rows
+    (rate 1 - mb/128): the candidates of the rate-selection loop."""
     nb = 128
-    mb = {2: 104, 3: 71}[slice_j]
     if n % nb:
         raise ValueError("n must be a multiple of 128")
+    if not 0 < mb < nb:
+        raise ValueError("mb must be in (0, 128)")
     return _lambda_qc_code(nb, mb, n // nb, seed * 131 + slice_j * 7, f"slice{slice_j}-qc n{n}")
 
 

@@ -105,3 +105,14 @@ def test_iteration_count_behaviour():
     assert all(a >= b for a, b in zip(ber, ber[1:]))
     # Delta t = c_h sum E_j D_j; the paper's c_h = 3.2e-9 s gives 1 / (7 c_h) = 4.46e7 edge updates/s
     assert abs(ga.decode_time(3.2e-9, [7.0], [1]) * 4.464e7 - 1) < 1e-3
+
+
+def test_slice_code_family_contains_the_chosen_codes():
+    """The rate-selection candidates and the codes the pipeline uses are one family."""
+    from paper_2108_08418_amd import inputs
+    for j, mb in ((2, 104), (3, 71)):
+        a = inputs.slice_code_spec(j, 4096)
+        b = inputs.slice_code_at(j, 4096, mb)
+        assert (a.shift == b.shift).all() and a.mb == b.mb == mb
+    with pytest.raises(ValueError):
+        inputs.slice_code_at(2, 4096, 128)

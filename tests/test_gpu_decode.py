@@ -465,3 +465,25 @@ def test_ragged_low_rate_met_batch_sampled_against_oracle():
         assert int(out["ok"][i]) == int(ref["ok"][0])
         np.testing.assert_array_equal(out["bits"][v0:v0 + n].cpu().numpy(), ref["bits"][0])
         np.testing.assert_array_equal(out["post"][v0:v0 + n].cpu().numpy().astype(np.float64), ref["post"][0])
+
+
+@pytest.mark.parametrize("slice_j", [2, 3])
+def test_rate_selection_loop_on_the_gpu(slice_j):
+    """The rate-selection loop: rates step down by 0.05 from 0.9 C_j, every
+    candidate before the selected one fails its decoding test, the selected one
+    decodes every sub-block to Bob's word, and C_j estimated from the LLRs is
+    the slice capacity of the oracle's quadrature (0.3153, 0.5469)."""
+    from paper_2108_08418_amd import rates
+    print(f"[rate selection slice {slice_j}, n = 2^16, 32 sub-blocks]", flush=True)
+    res = rates.select_slice_rate(slice_j, 1 << 16, frames=32)
+    cap = {2: 0.3153, 3: 0.5469}[slice_j]
+    assert abs(res["capacity"] - cap) < 2e-3, res["capacity"]
+    trail = res["trail"]
+    print(trail, flush=True)
+    assert res["selected"] is trail[-1]
+    assert all(c["failures"] + c["undetected"] > 0 for c in trail[:-1])
+    assert trail[-1]["failures"] == 0 and trail[-1]["undetected"] == 0
+    assert trail[0]["target"] == round(0.9 * res["capacity"], 4)
+    assert all(abs(a["target"] - b["target"] - 0.05) < 1e-9 for a, b in zip(trail, trail[1:]))
+    assert all(c["rate"] <= 0.9 * res["capacity"] + 1 / 256 for c in trail)
+    assert trail[-1]["ga_iters"] is not None
