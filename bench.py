@@ -214,9 +214,12 @@ def main():
 def llr_forms(args, dev):
     """Launch time of Alice's slice-3 LLR in its three forms over 2^27 pairs at
     SNR 3 (16 equiprobable Gray levels):
-      hard  - slices 0, 1, 2 held as bits (multistage decoding),
-      prior - slices 0, 1 as bits, slice 2 as a soft prior (a scaled LLR row),
-      bsc   - ln((1 - p) / p) with the sign of Alice's own quantised bit.
+      hard   - slices 0, 1, 2 held as bits (multistage decoding),
+      prior  - slices 0, 1 as bits, slice 2 as a soft prior (a scaled LLR row),
+      bsc    - ln((1 - p) / p) with the sign of Alice's own quantised bit;
+    and the one-pass pair the benchmark step uses:
+      next   - slice 2 and slice 3 for either value of slice 2, one pass,
+      choose - slice 3 picked by the decoded slice 2.
     Algorithmic bytes per sample: x (8) + the slice bytes and prior rows read
     + the fp32 output (4)."""
     import torch
@@ -235,11 +238,15 @@ def llr_forms(args, dev):
     api.slice_llr(x, sig, th, M_BITS, 2, 0b11, S, out=prior[2])
     prior[2] *= 4.0
     out = torch.empty(N, dtype=torch.float32, device=dev)
+    nx0, nx1 = torch.empty_like(out), torch.empty_like(out)
     p3 = 0.15
     forms = {
         "hard": (lambda: api.slice_llr(x, sig, th, M_BITS, 3, 0b111, S, out=out), 8 + 3 + 4),
         "prior": (lambda: api.slice_llr_prior(x, sig, th, M_BITS, 3, 0b11, S, 0b100, prior, out=out), 8 + 2 + 4 + 4),
         "bsc": (lambda: api.slice_llr_bsc(x, th, M_BITS, 3, p3, out=out), 8 + 4),
+        # slice 2 and both conditional slice-3 LLRs in one pass (three fp32 outputs)
+        "next": (lambda: api.slice_llr_next(x, sig, th, M_BITS, 2, 0b11, S, out=(out, nx0, nx1)), 8 + 2 + 12),
+        "choose": (lambda: api.slice_llr_choose(nx0, nx1, S[2], out=out), 4 + 4 + 1 + 4),
     }
     res = {}
     for name, (fn, bps) in forms.items():
@@ -305,6 +312,7 @@ def recon(args, wl, dev):
     alice = torch.empty((M_BITS, N), dtype=torch.uint8, device=dev)
     syn = {j: torch.empty(F * codes[j].m, dtype=torch.uint8, device=dev) for j in (2, 3)}
     llr = torch.empty(N, dtype=torch.float32, device=dev)
+    llr3 = (torch.empty(N, dtype=torch.float32, device=dev), torch.empty(N, dtype=torch.float32, device=dev))
     outs = {j: dict(bits=alice[j], post=None, iters=torch.empty(F, dtype=torch.int32, device=dev),
                     ok=torch.empty(F, dtype=torch.uint8, device=dev)) for j in (2, 3)}
     torch.cuda.synchronize()
@@ -315,9 +323,10 @@ def recon(args, wl, dev):
         for j in (2, 3):                                                                # Bob: syndromes
             api.syndrome_check(codes[j], bob[j], want_unsat=False, out_syndrome=syn[j])
         alice[0:2].copy_(bob[0:2])                                                     # disclosed slices
-        api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)                     # Alice: slice 2
+        # Alice: slice 2, and in the same pass slice 3 for either value of slice 2
+        api.slice_llr_next(x, sig, th, M_BITS, 2, 0b11, alice, out=(llr, *llr3))
         api.ldpc_decode_batch(batches[2], stage_params[2], llr, syn[2], workspace=ws, out=outs[2])
-        api.slice_llr(x, sig, th, M_BITS, 3, 0b111, alice, out=llr)                    # Alice: slice 3
+        api.slice_llr_choose(llr3[0], llr3[1], alice[2], out=llr)                      # slice 3 given decoded slice 2
         api.ldpc_decode_batch(batches[3], stage_params[3], llr, syn[3], workspace=ws, out=outs[3])
 
     tuned = None

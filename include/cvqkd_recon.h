@@ -150,6 +150,26 @@ cvr_status slice_llr_bsc(const double* x, int64_t n, const double* thresholds, i
                          int32_t labelling, int32_t j, double p, int32_t out_dtype, void* llr_out,
                          void* stream);
 
+/* Multistage decoding of consecutive slices (Sec. III-B steps 4-5): the LLR of
+ * slice j exactly as slice_llr computes it (llr_out), and in the same pass
+ * the LLR of slice j+1 under known_mask | (1 << j) for bit j = 0 (next_if0)
+ * and bit j = 1 (next_if1).  The interval probabilities slice j+1 needs are
+ * among those visited for slice j, and each conditional LLR is summed in the
+ * order slice_llr(j+1, ...) uses, so both equal slice_llr with that bit held
+ * known, bit for bit.  Once slice j is decoded, slice_llr_choose picks
+ * per sample.  Requires 0 <= j, j + 1 < m_bits, bits j and j+1 clear in
+ * known_mask; outputs: device [n] of out_dtype; otherwise as slice_llr.     */
+cvr_status slice_llr_next(const double* x, int64_t n, double sigma_n, const double* thresholds,
+                          int32_t m_bits, int32_t labelling, int32_t j, uint32_t known_mask,
+                          const uint8_t* slices, int32_t out_dtype, void* llr_out, void* next_if0,
+                          void* next_if1, void* stream);
+
+/* llr_out[i] = (bits[i] & 1) ? llr_if1[i] : llr_if0[i] for i < n; the three
+ * LLR arrays are device [n] of dtype (CVR_F32 or CVR_F64), bits device uint8
+ * [n] (e.g. the decoded slice j).  n = 0 is a no-op.                        */
+cvr_status slice_llr_choose(const void* llr_if0, const void* llr_if1, const uint8_t* bits, int64_t n,
+                            int32_t dtype, void* llr_out, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Syndromes                                                                  */
 /* ------------------------------------------------------------------------- */

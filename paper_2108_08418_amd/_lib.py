@@ -43,6 +43,8 @@ SIGNATURES = {
     "slice_llr": ([_P, _I64, _D, _P, _I32, _I32, _I32, _U32, _P, _I32, _P, _P], C.c_int),
     "slice_llr_prior": ([_P, _I64, _D, _P, _I32, _I32, _I32, _U32, _P, _U32, _P, _I32, _P, _P], C.c_int),
     "slice_llr_bsc": ([_P, _I64, _P, _I32, _I32, _I32, _D, _I32, _P, _P], C.c_int),
+    "slice_llr_next": ([_P, _I64, _D, _P, _I32, _I32, _I32, _U32, _P, _I32, _P, _P, _P, _P], C.c_int),
+    "slice_llr_choose": ([_P, _P, _P, _I64, _I32, _P, _P], C.c_int),
     "syndrome_check": ([_P, _I32, _P, _P, _P, _P, _P], C.c_int),
     "cvr_batch_create": ([_P, _I32, _P, _I32, _P], C.c_int),
     "cvr_batch_info": ([_P, _P, _P, _P, _P], C.c_int),

@@ -228,6 +228,45 @@ def slice_llr_prior(x: torch.Tensor, sigma_n: float, thresholds, m_bits: int, j:
     return out
 
 
+def slice_llr_next(x: torch.Tensor, sigma_n: float, thresholds, m_bits: int, j: int, known_mask: int,
+                   slices: torch.Tensor | None = None, labelling: int = GRAY, out_dtype: int = F32,
+                   out: tuple | None = None, stream=None):
+    """(L_j, L_{j+1} | bit j = 0, L_{j+1} | bit j = 1) in one pass; each equal to
+    slice_llr's value with the corresponding bits known."""
+    if x.dtype != torch.float64:
+        raise ValueError("x must be float64")
+    n = x.numel()
+    if slices is not None and (slices.dtype != torch.uint8 or not slices.is_contiguous()
+                               or slices.numel() < m_bits * n):
+        raise ValueError("slices must be contiguous uint8 [m_bits, n]")
+    if out is None:
+        out = tuple(torch.empty(n, dtype=_TORCH_OF[out_dtype], device=x.device) for _ in range(3))
+    th = _host(thresholds, np.float64)
+    check(load().slice_llr_next(_ptr(x), n, float(sigma_n), th.ctypes.data, int(m_bits), int(labelling), int(j),
+                                int(known_mask), _ptr(slices), int(out_dtype), _ptr(out[0]), _ptr(out[1]),
+                                _ptr(out[2]), _stream(stream)), "slice_llr_next")
+    return out
+
+
+def slice_llr_choose(llr_if0: torch.Tensor, llr_if1: torch.Tensor, bits: torch.Tensor,
+                     out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Per sample: llr_if1 where bits & 1, else llr_if0."""
+    n = llr_if0.numel()
+    if llr_if1.dtype != llr_if0.dtype or llr_if1.numel() != n or bits.dtype != torch.uint8 or bits.numel() < n:
+        raise ValueError("llr_if0/llr_if1 must match in dtype and size; bits uint8 with >= n entries")
+    if llr_if0.dtype == torch.float32:
+        dt = F32
+    elif llr_if0.dtype == torch.float64:
+        dt = F64
+    else:
+        raise ValueError("LLRs must be float32 or float64")
+    if out is None:
+        out = torch.empty_like(llr_if0)
+    check(load().slice_llr_choose(_ptr(llr_if0), _ptr(llr_if1), _ptr(bits), n, dt, _ptr(out), _stream(stream)),
+          "slice_llr_choose")
+    return out
+
+
 def slice_llr_bsc(x: torch.Tensor, thresholds, m_bits: int, j: int, p: float, labelling: int = GRAY,
                   out_dtype: int = F32, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Alice's hard LLRs (1 - 2 a_j) ln((1 - p) / p) from her own quantised bit a_j."""

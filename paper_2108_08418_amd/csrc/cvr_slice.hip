@@ -41,7 +41,18 @@ struct LlrArgs {
     int32_t out_f64;
     const float* prior;    // [m_bits][n]; rows in prior_mask read (prior form only)
     uint32_t prior_mask;
+    void* next0;           // LLR of slice j+1 given bit j = 0 / 1 (next form only)
+    void* next1;
     double t[kMaxThr];
+};
+
+struct ChooseArgs {
+    const void* l0;
+    const void* l1;
+    const uint8_t* bits;
+    void* out;
+    int64_t n;
+    int32_t f64;
 };
 
 struct BscArgs {
@@ -158,11 +169,15 @@ __device__ __forceinline__ double softplus(double z)
 // per interval, one log per sample); a sample whose smaller sum falls below
 // 1e-290, where erfc would lose relative accuracy or underflow, is redone in
 // the log domain (ln_interval and a running log-sum-exp).
+// NEXT: the same pass also yields the LLR of slice j+1 given bit j = 0 and
+// given bit j = 1 (the interval probabilities it needs are among those
+// visited).  Each is summed over its labels in the order slice j+1's own pass
+// would visit them, so both equal that pass bit for bit.
 // PRIOR: each label is also weighted by prod_i Pr(S_i = bit i of the label)
 // over the slices i in prior_mask, with Pr(S_i = 0) = 1 / (1 + e^-lambda_i),
 // Pr(S_i = 1) = 1 / (1 + e^lambda_i) from the prior LLR lambda_i of the sample
 // (ln of the logistic factor, -softplus, in the log-domain pass).
-template <bool PRIOR>
+template <bool PRIOR, bool NEXT>
 __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
 {
     __shared__ double bnd[kMaxThr + 2];
@@ -219,6 +234,7 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
             return w;
         };
         double p0 = 0.0, p1 = 0.0;
+        double q00 = 0.0, q01 = 0.0, q10 = 0.0, q11 = 0.0;   // NEXT: (bit j, bit j+1)
         for (int c = 0; c < (1 << nfree); ++c) {
             uint32_t k, g;
             const uint32_t bit = label(c, k, g);
@@ -226,6 +242,11 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
             if constexpr (PRIOR) p *= prior_w(g);
             if (bit) p1 += p;
             else p0 += p;
+            if constexpr (NEXT) {
+                const uint32_t up = (g >> (a.j + 1)) & 1u;
+                if (bit) (up ? q11 : q10) += p;
+                else (up ? q01 : q00) += p;
+            }
         }
         double L;
         if (p0 > 1e-290 && p1 > 1e-290) {
@@ -244,6 +265,42 @@ __global__ __launch_bounds__(256) void k_slice_llr(LlrArgs a)
         }
         if (a.out_f64) static_cast<double*>(a.out)[i] = L;
         else static_cast<float*>(a.out)[i] = float(L);
+        if constexpr (NEXT) {
+            for (uint32_t b = 0; b < 2; ++b) {
+                const double s0 = b ? q10 : q00, s1 = b ? q11 : q01;
+                double Ln;
+                if (s0 > 1e-290 && s1 > 1e-290) {
+                    Ln = log(s0 / s1);
+                } else {
+                    double m0 = -INFINITY, t0 = 0.0, m1 = -INFINITY, t1 = 0.0;
+                    for (int c = 0; c < (1 << nfree); ++c) {
+                        uint32_t k, g;
+                        const uint32_t bit = label(c, k, g);
+                        if (bit != b) continue;
+                        const double lp = ln_interval((bnd[k] - x) / a.sigma, (bnd[k + 1] - x) / a.sigma);
+                        if ((g >> (a.j + 1)) & 1u) lse_push(m1, t1, lp);
+                        else lse_push(m0, t0, lp);
+                    }
+                    Ln = (m0 + log(t0)) - (m1 + log(t1));
+                }
+                void* dst = b ? a.next1 : a.next0;
+                if (a.out_f64) static_cast<double*>(dst)[i] = Ln;
+                else static_cast<float*>(dst)[i] = float(Ln);
+            }
+        }
+    }
+}
+
+// out = bits & 1 ? l1 : l0, one sample per thread and stride.
+__global__ __launch_bounds__(256) void k_llr_choose(ChooseArgs a)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        const bool one = a.bits[i] & 1;
+        if (a.f64) static_cast<double*>(a.out)[i] = one ? static_cast<const double*>(a.l1)[i]
+                                                        : static_cast<const double*>(a.l0)[i];
+        else static_cast<float*>(a.out)[i] = one ? static_cast<const float*>(a.l1)[i]
+                                                 : static_cast<const float*>(a.l0)[i];
     }
 }
 
@@ -341,8 +398,59 @@ extern "C" cvr_status slice_llr(const double* x, int64_t n, double sigma_n, cons
     a.out_f64 = out_dtype == CVR_F64;
     for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
     ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
-    hipLaunchKernelGGL(k_slice_llr<false>, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    hipLaunchKernelGGL((k_slice_llr<false, false>), dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
     return check_launch("slice_llr");
+}
+
+extern "C" cvr_status slice_llr_next(const double* x, int64_t n, double sigma_n, const double* thresholds,
+                                     int32_t m_bits, int32_t labelling, int32_t j, uint32_t known_mask,
+                                     const uint8_t* slices, int32_t out_dtype, void* llr_out, void* next_if0,
+                                     void* next_if1, void* stream)
+{
+    if (n < 0) return fail(CVR_EINVAL, "slice_llr_next: n < 0");
+    if (labelling != CVR_GRAY && labelling != CVR_BINARY) return fail(CVR_EINVAL, "slice_llr_next: bad labelling");
+    if (cvr_status st = check_thresholds("slice_llr_next", thresholds, m_bits)) return st;
+    if (!(sigma_n > 0.0) || !std::isfinite(sigma_n))
+        return fail(CVR_EINVAL, "slice_llr_next: sigma_n must be finite and > 0");
+    if (j < 0 || j + 1 >= m_bits) return fail(CVR_EINVAL, "slice_llr_next: need 0 <= j and j + 1 < m_bits");
+    if ((known_mask >> j) & 3u) return fail(CVR_EINVAL, "slice_llr_next: slice j or j + 1 is in known_mask");
+    if (known_mask >> m_bits) return fail(CVR_EINVAL, "slice_llr_next: known_mask has bits >= m_bits");
+    if (out_dtype != CVR_F32 && out_dtype != CVR_F64)
+        return fail(CVR_EINVAL, "slice_llr_next: out_dtype must be F32 or F64");
+    if (n == 0) return CVR_OK;
+    if (!x || !llr_out || !next_if0 || !next_if1) return fail(CVR_EINVAL, "slice_llr_next: NULL x or output");
+    if (known_mask && !slices) return fail(CVR_EINVAL, "slice_llr_next: known_mask set but slices is NULL");
+    LlrArgs a{};
+    a.x = x;
+    a.slices = slices;
+    a.out = llr_out;
+    a.n = n;
+    a.sigma = sigma_n;
+    a.m_bits = m_bits;
+    a.nthr = (1 << m_bits) - 1;
+    a.gray = labelling == CVR_GRAY;
+    a.j = j;
+    a.known = known_mask;
+    a.out_f64 = out_dtype == CVR_F64;
+    a.next0 = next_if0;
+    a.next1 = next_if1;
+    for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
+    ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
+    hipLaunchKernelGGL((k_slice_llr<false, true>), dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    return check_launch("slice_llr_next");
+}
+
+extern "C" cvr_status slice_llr_choose(const void* llr_if0, const void* llr_if1, const uint8_t* bits, int64_t n,
+                                       int32_t dtype, void* llr_out, void* stream)
+{
+    if (n < 0) return fail(CVR_EINVAL, "slice_llr_choose: n < 0");
+    if (dtype != CVR_F32 && dtype != CVR_F64) return fail(CVR_EINVAL, "slice_llr_choose: dtype must be F32 or F64");
+    if (n == 0) return CVR_OK;
+    if (!llr_if0 || !llr_if1 || !bits || !llr_out) return fail(CVR_EINVAL, "slice_llr_choose: NULL argument");
+    ChooseArgs a{llr_if0, llr_if1, bits, llr_out, n, dtype == CVR_F64};
+    ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
+    hipLaunchKernelGGL(k_llr_choose, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    return check_launch("slice_llr_choose");
 }
 
 extern "C" cvr_status slice_llr_prior(const double* x, int64_t n, double sigma_n, const double* thresholds,
@@ -383,7 +491,7 @@ extern "C" cvr_status slice_llr_prior(const double* x, int64_t n, double sigma_n
     a.prior_mask = prior_mask;
     for (int q = 0; q < a.nthr; ++q) a.t[q] = thresholds[q];
     ProfScope prof(CVR_PROF_LLR, hipStream_t(stream));
-    hipLaunchKernelGGL(k_slice_llr<true>, dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
+    hipLaunchKernelGGL((k_slice_llr<true, false>), dim3(grid_for(n, 256)), dim3(256), 0, hipStream_t(stream), a);
     return check_launch("slice_llr_prior");
 }
 

@@ -70,6 +70,13 @@ def test_host_side_argument_checks(lib):
     assert lib.slice_llr_bsc(None, 10, th_ok.ctypes.data, 2, 0, 0, 1.0, 1, None, None) == -1
     assert lib.slice_llr_bsc(None, 10, th_ok.ctypes.data, 2, 0, 2, 0.1, 1, None, None) == -1
     assert lib.slice_llr_bsc(None, 0, th_ok.ctypes.data, 2, 0, 1, 0.1, 1, None, None) == 0
+    # one pass for slices j and j + 1
+    assert lib.slice_llr_next(None, 10, 0.5, th_ok.ctypes.data, 2, 0, 1, 0, None, 1, None, None, None, None) == -1
+    assert b"j + 1 < m_bits" in lib.cvr_last_error()
+    assert lib.slice_llr_next(None, 10, 0.5, th_ok.ctypes.data, 2, 0, 0, 0b10, None, 1, None, None, None, None) == -1
+    assert lib.slice_llr_next(None, 0, 0.5, th_ok.ctypes.data, 2, 0, 0, 0, None, 1, None, None, None, None) == 0
+    assert lib.slice_llr_choose(None, None, None, 5, 1, None, None) == -1
+    assert lib.slice_llr_choose(None, None, None, 0, 1, None, None) == 0
     # malformed CSR: columns not ascending / out of range / degree 0
     h = C.c_void_p()
     rp = np.array([0, 2, 4], np.int32)

@@ -141,6 +141,52 @@ def test_slice_llr_forms_other_widths_and_labellings(m_bits, lab):
                                    rtol=4.5e-16, atol=0)
 
 
+@pytest.mark.parametrize("m_bits,lab,j,known", [(4, api.GRAY, 2, 0b11), (4, api.GRAY, 0, 0), (4, api.GRAY, 1, 0b1),
+                                                (4, api.GRAY, 1, 0b1000), (5, api.BINARY, 3, 0b111),
+                                                (5, api.GRAY, 2, 0b10011)])
+@pytest.mark.parametrize("dt", [api.F64, api.F32])
+def test_slice_llr_next_equals_slice_llr_bit_for_bit(m_bits, lab, j, known, dt):
+    """One pass for slice j and both conditional LLRs of slice j+1 equals
+    slice_llr on each, bit for bit, far tails (log-domain pass) included; the
+    choice by the decoded bits equals slice_llr with those bits known."""
+    print(f"[slice_llr_next m={m_bits} lab={lab} j={j} known={known:b} dt={dt}]", flush=True)
+    N = (1 << 18) + 13
+    x, y = inputs.gaussian_pairs(N, SNR, seed=80 + j)
+    x[:33] = np.linspace(-30, 30, 33)
+    th = TH4 if m_bits == 4 else inputs.constant_step_thresholds(m_bits, 3.0 / 2 ** m_bits)
+    S = oracle.quantize(y, th, m_bits, oracle.GRAY if lab == api.GRAY else oracle.BINARY)
+    xg, Sg = _g(x), _g(S)
+    L, N0, N1 = api.slice_llr_next(xg, SIG, th, m_bits, j, known, Sg, labelling=lab, out_dtype=dt)
+    ref = api.slice_llr(xg, SIG, th, m_bits, j, known, Sg, labelling=lab, out_dtype=dt)
+    torch.cuda.synchronize()
+    assert torch.equal(L, ref)
+    for b, got in ((0, N0), (1, N1)):
+        Sb = S.copy()
+        Sb[j] = b
+        ref_b = api.slice_llr(xg, SIG, th, m_bits, j + 1, known | (1 << j), _g(Sb), labelling=lab, out_dtype=dt)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref_b), b
+    # the choice by Bob's (here: the true) bits of slice j
+    chosen = api.slice_llr_choose(N0, N1, Sg[j])
+    direct = api.slice_llr(xg, SIG, th, m_bits, j + 1, known | (1 << j), Sg, labelling=lab, out_dtype=dt)
+    torch.cuda.synchronize()
+    assert torch.equal(chosen, direct)
+    if dt == api.F64:
+        olab = oracle.GRAY if lab == api.GRAY else oracle.BINARY
+        Lo = oracle.slice_llr(x, SIG, th, m_bits, olab, j + 1, known | (1 << j), S)
+        _same_nonfinite_then_rel(chosen.cpu().numpy(), Lo, 1e-12)
+
+
+def test_slice_llr_choose_edge_cases():
+    for n in (0, 1, 1003):
+        a = torch.arange(n, dtype=torch.float32, device=DEV)
+        b = -a - 1
+        bits = torch.from_numpy(np.random.default_rng(n).integers(0, 2, n).astype(np.uint8)).to(DEV)
+        got = api.slice_llr_choose(a, b, bits)
+        torch.cuda.synchronize()
+        assert torch.equal(got, torch.where(bits.bool(), b, a))
+
+
 def _same_nonfinite_then_rel(got, ref, rel):
     """Non-finite outputs (+-inf, NaN) at the same places with the same value;
     finite ones within rel * max(1, |ref|)."""
