@@ -153,7 +153,8 @@ def _conditional_entropy_quadrature(j, snr=SNR, m=4, npts=300):
 
 
 def test_slice_capacities_match_quadrature_constants():
-    # survey-computed constants at SNR 3 with 16 equiprobable Gray intervals
+    # four-digit slice capacities at SNR 3, 16 equiprobable Gray intervals, computed beforehand
+    # by an independent numerical integration
     caps = [1 - _conditional_entropy_quadrature(j) for j in range(4)]
     np.testing.assert_allclose(caps, [0.0228, 0.0747, 0.3153, 0.5469], atol=6e-4)
 
