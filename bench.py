@@ -170,7 +170,7 @@ def stage_bytes(iters, T, n, m, E, s_msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                           "(frames shard across GPUs with no exchange, see the design notes)"}))
         sys.exit(2)
     import torch
