@@ -318,13 +318,20 @@ def recon(args, wl, dev):
     torch.cuda.synchronize()
     print(f"# inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
+    # Bob's syndromes (HBM-bound) run on a second stream of default priority,
+    # beside Alice's fp64-bound LLR pass; the decoders wait for both.
+    side = torch.cuda.Stream(device=dev)
+
     def step():
+        main = torch.cuda.current_stream()
         api.slice_quantize(y, th, M_BITS, out=bob)                                    # Bob: M(.) and slices
+        side.wait_stream(main)
         for j in (2, 3):                                                                # Bob: syndromes
-            api.syndrome_check(codes[j], bob[j], want_unsat=False, out_syndrome=syn[j])
+            api.syndrome_check(codes[j], bob[j], want_unsat=False, out_syndrome=syn[j], stream=side)
         alice[0:2].copy_(bob[0:2])                                                     # disclosed slices
         # Alice: slice 2, and in the same pass slice 3 for either value of slice 2
         api.slice_llr_next(x, sig, th, M_BITS, 2, 0b11, alice, out=(llr, *llr3))
+        main.wait_stream(side)
         api.ldpc_decode_batch(batches[2], stage_params[2], llr, syn[2], workspace=ws, out=outs[2])
         api.slice_llr_choose(llr3[0], llr3[1], alice[2], out=llr)                      # slice 3 given decoded slice 2
         api.ldpc_decode_batch(batches[3], stage_params[3], llr, syn[3], workspace=ws, out=outs[3])
