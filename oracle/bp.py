@@ -39,6 +39,10 @@ def _load():
         lib.orc_decode.argtypes = [i32, i32, P, P, P, i32, i32, P, P, i32, i32, i32, i32, i32,
                                    d, P, d, P, P, P, P, P, P, P]
         lib.orc_nms_unrolled.argtypes = [i32, i32, P, P, P, i32, i32, P, P, P, i32, P, i32, P, P, P, P]
+        lib.orc_flood_step.argtypes = [i32, i32, P, P, P, i32, P, P, i32, i32, i32, i32, d, P, d, P, P, P]
+        lib.orc_decode_layered.argtypes = [i32, i32, P, P, P, i32, i32, P, i32, P, P, i32, i32, i32, i32, i32,
+                                           d, P, d, P, P, P, P, P, P, P]
+        lib.orc_layered_step.argtypes = [i32, i32, P, P, P, i32, i32, P, P, P, i32, i32, i32, i32, d, P, d, P, P]
         lib.orc_round_half.argtypes = [d]
         lib.orc_round_half.restype = d
         _lib = lib
@@ -130,3 +134,86 @@ def nms_unrolled(code, llr, syndrome, truth, weights, want_dllr=False, prec32=Fa
     if want_dllr:
         res["dllr"] = dl
     return res
+
+
+def flood_step(code, llr, syndrome, c2v, t, *, algo=SP, store_half=False, prec32=False, alpha=0.75,
+               weights=None, clamp=50.0):
+    """One flooding iteration of one frame from the state c2v(t) [E] (CSR edge
+    order): returns (c2v(t+1), L_post(t+1)).  ``llr`` [n], ``syndrome`` [m] or None."""
+    lib = _load()
+    rp, ci, et = _code_arrays(code)
+    llr = np.ascontiguousarray(llr, dtype=np.float64).reshape(-1)
+    cin = np.ascontiguousarray(c2v, dtype=np.float64).reshape(-1)
+    syn = None if syndrome is None else np.ascontiguousarray(syndrome, dtype=np.uint8).reshape(-1)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    cout = np.zeros(code.n_edges)
+    post = np.zeros(code.n)
+    rc = lib.orc_flood_step(code.n, code.m, _p(rp), _p(ci), _p(et), code.n_types, _p(llr), _p(syn), int(algo),
+                            int(t), int(bool(store_half)), int(bool(prec32)), float(alpha), _p(w), float(clamp),
+                            _p(cin), _p(cout), _p(post))
+    if rc:
+        raise ValueError("oracle flood_step rejected its arguments")
+    return cout, post
+
+
+def qc_layers(mb: int, Z: int) -> np.ndarray:
+    """Layer boundaries of a quasi-cyclic code: layer i = the Z checks of block row i."""
+    return (np.arange(mb + 1, dtype=np.int32) * Z).astype(np.int32)
+
+
+def decode_layered(code, llr, syndrome=None, *, layers, algo=SP, max_iter=50, early_stop=True,
+                   store_half=False, alpha=0.75, weights=None, clamp=50.0, trace=False, prec32=False):
+    """Layered BP over frames llr [F, n]; ``layers`` = row boundaries [n_layers + 1]
+    (rows of one layer share no variable).  Same outputs as :func:`decode`."""
+    lib = _load()
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
+    F, n = llr.shape
+    if n != code.n:
+        raise ValueError("llr width != code length")
+    rp, ci, et = _code_arrays(code)
+    lp = np.ascontiguousarray(layers, dtype=np.int32)
+    syn = None if syndrome is None else np.ascontiguousarray(np.atleast_2d(syndrome), dtype=np.uint8)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    if w is not None and w.shape != (max_iter, code.n_types):
+        raise ValueError("weights must be [max_iter, n_types]")
+    out = dict(bits=np.zeros((F, n), np.uint8), post=np.zeros((F, n)),
+               iters=np.zeros(F, np.int32), ok=np.zeros(F, np.uint8))
+    tr = sc = ut = None
+    if trace:
+        tr = np.full((F, max_iter + 1, n), np.nan)
+        sc = np.full((F, max_iter + 1, n), np.nan)
+        ut = np.full((F, max_iter + 1), -1, dtype=np.int32)
+    rc = lib.orc_decode_layered(code.n, code.m, _p(rp), _p(ci), _p(et), code.n_types, len(lp) - 1, _p(lp), F,
+                                _p(llr), _p(syn), int(algo), int(max_iter), int(bool(early_stop)),
+                                int(bool(store_half)), int(bool(prec32)), float(alpha), _p(w), float(clamp),
+                                _p(out["bits"]), _p(out["post"]), _p(out["iters"]), _p(out["ok"]),
+                                _p(tr), _p(sc), _p(ut))
+    if rc == -2:
+        raise ValueError("two rows of one layer share a variable")
+    if rc:
+        raise ValueError("oracle decode_layered rejected its arguments")
+    if trace:
+        out.update(post_trace=tr, scale_trace=sc, unsat_trace=ut)
+    return out
+
+
+def layered_step(code, llr, syndrome, c2v, post, t, *, layers, algo=SP, store_half=False, prec32=False,
+                 alpha=0.75, weights=None, clamp=50.0):
+    """One layered iteration of one frame from the state (c2v [E], post [n]);
+    returns the new (c2v, post).  In fp64 mode ``post`` is only an output."""
+    lib = _load()
+    rp, ci, et = _code_arrays(code)
+    lp = np.ascontiguousarray(layers, dtype=np.int32)
+    llr = np.ascontiguousarray(llr, dtype=np.float64).reshape(-1)
+    c = np.array(c2v, dtype=np.float64).reshape(-1)
+    p = np.array(post, dtype=np.float64).reshape(-1)
+    syn = None if syndrome is None else np.ascontiguousarray(syndrome, dtype=np.uint8).reshape(-1)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    rc = lib.orc_layered_step(code.n, code.m, _p(rp), _p(ci), _p(et), code.n_types, len(lp) - 1, _p(lp),
+                              _p(llr), _p(syn), int(algo), int(t), int(bool(store_half)), int(bool(prec32)),
+                              float(alpha), _p(w), float(clamp), _p(c), _p(p))
+    if rc == -2:
+        raise ValueError("two rows of one layer share a variable")
+    if rc:
+        raise ValueError("oracle layered_step rejected its arguments")
+    return c, p

@@ -11,9 +11,15 @@
  *   - syndrome decoding: every check-to-variable message of check c is
  *     multiplied by (1 - 2 s_c), s_c being the syndrome bit Bob sends
  *     (Sec. II Step 5, Sec. III-B steps 2-4);
- *   - flooding schedule: all checks, then all variables, per iteration;
+ *   - flooding schedule (orc_decode): all checks, then all variables, per
+ *     iteration; the layered schedule (orc_decode_layered) updates groups of
+ *     rows one after another within an iteration;
  *   - the syndrome of the hard decisions is tested before the first
  *     iteration and after every iteration (failure detection, Sec. II Step 5).
+ *
+ * orc_flood_step and orc_layered_step run a single iteration from a given
+ * state, so that the fp64 definitions and the binary32 forms can be compared
+ * one step at a time.
  *
  * Every function below is plain loops in double precision, written to be
  * read against its definition rather than to be fast.  OpenMP splits the
@@ -406,6 +412,280 @@ int orc_nms_unrolled(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t
     }
     if (loss_out) *loss_out = loss_total;
     free(dw_frame); free(loss_frame);
+    free_colview(&cv);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One check row of the check-node rule, shared by the step-wise functions  */
+/* below (the same rule orc_decode writes out inline):                      */
+/*   SP:  out_e = (1 - 2 s_c) prod_{k != e} sign(x_k) phi(sum_{k != e} phi(|x_k|)), */
+/*        every x first clamped to [-clamp, clamp];                         */
+/*   NMS: out_e = w_e (1 - 2 s_c) prod_{k != e} sign(x_k) min_{k != e} |x_k|. */
+/* prec32 rounds every add, multiply and phi to binary32.                   */
+/* ------------------------------------------------------------------------ */
+static void check_row_rule(int32_t d, const double* x, double ssign, int32_t algo, int32_t prec32,
+                           double clamp, const double* w, double* mag, double* out)
+{
+    for (int32_t k = 0; k < d; ++k) {
+        double v = x[k];
+        if (algo == ORC_SP) {
+            if (v > clamp) v = clamp;
+            if (v < -clamp) v = -clamp;
+        }
+        mag[k] = v;
+    }
+    for (int32_t e = 0; e < d; ++e) {
+        double sg = ssign;
+        for (int32_t k = 0; k < d; ++k)
+            if (k != e && neg(mag[k])) sg = -sg;
+        if (algo == ORC_SP) {
+            double acc = 0.0;
+            for (int32_t k = 0; k < d; ++k)
+                if (k != e) acc = rnd(prec32, acc + rnd(prec32, phi(fabs(mag[k]))));
+            out[e] = sg * rnd(prec32, phi(acc));
+        } else {
+            double mn = INFINITY;
+            for (int32_t k = 0; k < d; ++k)
+                if (k != e && fabs(mag[k]) < mn) mn = fabs(mag[k]);
+            out[e] = rnd(prec32, rnd(prec32, w[e]) * (sg * mn));
+        }
+    }
+}
+
+/*
+ * One flooding iteration from a given state, for step-by-step comparisons of
+ * the two precisions: c2v_in = c2v(t) [E] (all zero at t = 0) -> c2v_out =
+ * c2v(t+1) and post_out = L_post(t+1) [n], for one frame.  t selects the row
+ * of weights.  The fp64 mode forms v2c_e = L_ch + sum_{c' != c} c2v_{c'}(t);
+ * the binary32 mode first accumulates L_post(t) = L_ch + sum c2v(t) in
+ * ascending check order in binary32 and forms v2c_e = L_post(t) - c2v_e(t),
+ * which is what orc_decode does in each mode at iteration t.
+ */
+int orc_flood_step(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                   const uint8_t* edge_type, int32_t n_types, const double* llr, const uint8_t* s,
+                   int32_t algo, int32_t t, int32_t store_half, int32_t prec32, double alpha,
+                   const double* weights, double clamp, const double* c2v_in, double* c2v_out,
+                   double* post_out)
+{
+    if (n <= 0 || m < 0 || t < 0) return -1;
+    const int64_t E = row_ptr[m];
+    colview cv = make_colview(n, m, row_ptr, col_idx);
+    int32_t maxdeg = 1;
+    for (int32_t c = 0; c < m; ++c)
+        if (row_ptr[c + 1] - row_ptr[c] > maxdeg) maxdeg = row_ptr[c + 1] - row_ptr[c];
+    double* v2c = (double*)malloc((size_t)(E > 0 ? E : 1) * sizeof(double));
+    double* mag = (double*)malloc((size_t)maxdeg * sizeof(double));
+    double* w = (double*)malloc((size_t)maxdeg * sizeof(double));
+    double* out = (double*)malloc((size_t)maxdeg * sizeof(double));
+    for (int32_t v = 0; v < n; ++v) {
+        double lp = 0.0;
+        if (prec32) {
+            lp = rnd(1, llr[v]);
+            for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) lp = rnd(1, lp + c2v_in[cv.edge[k]]);
+        }
+        for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) {
+            double a;
+            if (prec32) {
+                a = rnd(1, lp - c2v_in[cv.edge[k]]);
+            } else {
+                a = llr[v];
+                for (int32_t k2 = cv.ptr[v]; k2 < cv.ptr[v + 1]; ++k2)
+                    if (k2 != k) a += c2v_in[cv.edge[k2]];
+            }
+            v2c[cv.edge[k]] = a;
+        }
+    }
+    for (int32_t c = 0; c < m; ++c) {
+        const int32_t e0 = row_ptr[c], d = row_ptr[c + 1] - e0;
+        for (int32_t e = 0; e < d; ++e)
+            w[e] = weights ? weights[(int64_t)t * n_types + (edge_type ? edge_type[e0 + e] : 0)] : alpha;
+        check_row_rule(d, v2c + e0, (s && (s[c] & 1)) ? -1.0 : 1.0, algo, prec32, clamp, w, mag, out);
+        for (int32_t e = 0; e < d; ++e) c2v_out[e0 + e] = store_half ? orc_round_half(out[e]) : out[e];
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        double a = rnd(prec32, llr[v]);
+        for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a = rnd(prec32, a + c2v_out[cv.edge[k]]);
+        post_out[v] = a;
+    }
+    free(v2c); free(mag); free(w); free(out);
+    free_colview(&cv);
+    return 0;
+}
+
+/*
+ * Layered (row-serial) belief propagation.  The paper names belief
+ * propagation without a schedule (Sec. III-C); this is the serial schedule
+ * over layers: rows are grouped into layers (layer l holds rows
+ * layer_ptr[l] .. layer_ptr[l+1]-1, no two of which share a variable), and an
+ * iteration updates the layers one after another, each from the messages its
+ * predecessors in the same iteration have already replaced.
+ *
+ * fp64 mode (the definition): for every row c of layer l and edge e = (c, v),
+ *     v2c_e = L_ch[v] + sum_{c' in N(v), c' != c} c2v_{c'}    (current values),
+ *     c2v_e <- check rule of the row (as in orc_decode),
+ * and after the last layer L_post[v] = L_ch[v] + sum_{c in N(v)} c2v_c.
+ * Rows of one layer touch disjoint variables, so the order of rows inside a
+ * layer does not matter.
+ *
+ * prec32 mode: the binary32 form a layered decoder runs.  It keeps the
+ * posterior L[v] as a running value (L = L_ch rounded at the start) and, for
+ * every edge of a row, forms x_e = L[v] - c2v_e(old), applies the check rule
+ * and sets L[v] = x_e + c2v_e(new), each operation rounded to binary32.  In
+ * exact arithmetic L[v] stays equal to L_ch[v] + sum c2v, so this is the fp64
+ * mode up to rounding; it differs from it by the rounding of the running sum.
+ *
+ * Stopping, traces and outputs as orc_decode: the syndrome of the hard
+ * decisions of L_post is tested before the first iteration and after each
+ * (a check touching a NaN posterior counts as unsatisfied).  Returns -1 for
+ * bad arguments, -2 when two rows of one layer share a variable.
+ */
+static int layers_disjoint(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                           int32_t n_layers, const int32_t* layer_ptr)
+{
+    int32_t* seen = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    for (int32_t v = 0; v < n; ++v) seen[v] = -1;
+    int ok = 1;
+    for (int32_t l = 0; l < n_layers && ok; ++l)
+        for (int32_t c = layer_ptr[l]; c < layer_ptr[l + 1] && ok; ++c)
+            for (int32_t e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+                if (seen[col_idx[e]] == l) { ok = 0; break; }
+                seen[col_idx[e]] = l;
+            }
+    free(seen);
+    return ok;
+}
+
+/* One layered iteration (all layers) of one frame: c2v and L are updated in
+ * place.  In fp64 mode L is recomputed from c2v at the end; in prec32 mode it
+ * is the running posterior. */
+static void layered_iteration(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                              const uint8_t* edge_type, int32_t n_types, const colview* cv,
+                              int32_t n_layers, const int32_t* layer_ptr, const double* Lch,
+                              const uint8_t* s, int32_t algo, int32_t t, int32_t store_half,
+                              int32_t prec32, double alpha, const double* weights, double clamp,
+                              double* c2v, double* L, double* x, double* mag, double* w, double* out)
+{
+    for (int32_t l = 0; l < n_layers; ++l) {
+        for (int32_t c = layer_ptr[l]; c < layer_ptr[l + 1]; ++c) {
+            const int32_t e0 = row_ptr[c], d = row_ptr[c + 1] - e0;
+            for (int32_t e = 0; e < d; ++e) {
+                const int32_t v = col_idx[e0 + e];
+                if (prec32) {
+                    x[e] = rnd(1, L[v] - c2v[e0 + e]);
+                } else {
+                    double a = Lch[v];
+                    for (int32_t k = cv->ptr[v]; k < cv->ptr[v + 1]; ++k)
+                        if (cv->edge[k] != e0 + e) a += c2v[cv->edge[k]];
+                    x[e] = a;
+                }
+                w[e] = weights ? weights[(int64_t)t * n_types + (edge_type ? edge_type[e0 + e] : 0)] : alpha;
+            }
+            check_row_rule(d, x, (s && (s[c] & 1)) ? -1.0 : 1.0, algo, prec32, clamp, w, mag, out);
+            for (int32_t e = 0; e < d; ++e) {
+                c2v[e0 + e] = store_half ? orc_round_half(out[e]) : out[e];
+                if (prec32) L[col_idx[e0 + e]] = rnd(1, x[e] + c2v[e0 + e]);
+            }
+        }
+    }
+    if (!prec32) {
+        for (int32_t v = 0; v < n; ++v) {
+            double a = Lch[v];
+            for (int32_t k = cv->ptr[v]; k < cv->ptr[v + 1]; ++k) a += c2v[cv->edge[k]];
+            L[v] = a;
+        }
+    }
+}
+
+int orc_decode_layered(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                       const uint8_t* edge_type, int32_t n_types, int32_t n_layers,
+                       const int32_t* layer_ptr, int32_t F, const double* llr, const uint8_t* syn,
+                       int32_t algo, int32_t T, int32_t early_stop, int32_t store_half, int32_t prec32,
+                       double alpha, const double* weights, double clamp,
+                       uint8_t* bits, double* post, int32_t* iters, uint8_t* ok,
+                       double* trace, double* trace_scale, int32_t* trace_unsat)
+{
+    if (n <= 0 || m < 0 || F < 0 || T < 0 || n_layers < 0) return -1;
+    if (layer_ptr[0] != 0 || layer_ptr[n_layers] != m) return -1;
+    for (int32_t l = 0; l < n_layers; ++l)
+        if (layer_ptr[l + 1] < layer_ptr[l]) return -1;
+    if (!layers_disjoint(n, row_ptr, col_idx, n_layers, layer_ptr)) return -2;
+    const int64_t E = row_ptr[m];
+    colview cv = make_colview(n, m, row_ptr, col_idx);
+    int32_t maxdeg = 1;
+    for (int32_t c = 0; c < m; ++c)
+        if (row_ptr[c + 1] - row_ptr[c] > maxdeg) maxdeg = row_ptr[c + 1] - row_ptr[c];
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t f = 0; f < F; ++f) {
+        const double* Lch = llr + (int64_t)f * n;
+        const uint8_t* s = syn ? syn + (int64_t)f * m : NULL;
+        double* c2v = (double*)calloc((size_t)(E > 0 ? E : 1), sizeof(double));
+        double* L = (double*)malloc((size_t)n * sizeof(double));
+        double* x = (double*)malloc((size_t)maxdeg * sizeof(double));
+        double* mag = (double*)malloc((size_t)maxdeg * sizeof(double));
+        double* w = (double*)malloc((size_t)maxdeg * sizeof(double));
+        double* out = (double*)malloc((size_t)maxdeg * sizeof(double));
+        for (int32_t v = 0; v < n; ++v) L[v] = rnd(prec32, Lch[v]);
+        int32_t t = 0;
+        for (;;) {
+            const int32_t u = count_unsat(m, row_ptr, col_idx, L, s);
+            if (trace) memcpy(trace + ((int64_t)f * (T + 1) + t) * n, L, (size_t)n * sizeof(double));
+            if (trace_scale) {
+                double* sc = trace_scale + ((int64_t)f * (T + 1) + t) * n;
+                for (int32_t v = 0; v < n; ++v) {
+                    double a = fabs(Lch[v]);
+                    for (int32_t k = cv.ptr[v]; k < cv.ptr[v + 1]; ++k) a += fabs(c2v[cv.edge[k]]);
+                    sc[v] = a;
+                }
+            }
+            if (trace_unsat) trace_unsat[(int64_t)f * (T + 1) + t] = u;
+            if ((early_stop && u == 0) || t == T) {
+                iters[f] = t;
+                ok[f] = (uint8_t)(u == 0);
+                break;
+            }
+            layered_iteration(n, row_ptr, col_idx, edge_type, n_types, &cv, n_layers, layer_ptr, Lch, s,
+                              algo, t, store_half, prec32, alpha, weights, clamp, c2v, L, x, mag, w, out);
+            ++t;
+        }
+        for (int32_t v = 0; v < n; ++v) {
+            if (bits) bits[(int64_t)f * n + v] = (uint8_t)neg(L[v]);
+            if (post) post[(int64_t)f * n + v] = L[v];
+        }
+        free(c2v); free(L); free(x); free(mag); free(w); free(out);
+    }
+    free_colview(&cv);
+    return 0;
+}
+
+/*
+ * One layered iteration of one frame from a given state (for step-by-step
+ * comparisons): c2v [E] and post [n] are read and overwritten in place.  In
+ * fp64 mode post is only written (the posterior is a function of c2v); in
+ * prec32 mode post is the running binary32 posterior the iteration starts
+ * from (L_ch rounded to binary32 before the first iteration).
+ */
+int orc_layered_step(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* col_idx,
+                     const uint8_t* edge_type, int32_t n_types, int32_t n_layers, const int32_t* layer_ptr,
+                     const double* llr, const uint8_t* s, int32_t algo, int32_t t, int32_t store_half,
+                     int32_t prec32, double alpha, const double* weights, double clamp,
+                     double* c2v, double* post)
+{
+    if (n <= 0 || m < 0 || t < 0 || n_layers < 0) return -1;
+    if (layer_ptr[0] != 0 || layer_ptr[n_layers] != m) return -1;
+    if (!layers_disjoint(n, row_ptr, col_idx, n_layers, layer_ptr)) return -2;
+    colview cv = make_colview(n, m, row_ptr, col_idx);
+    int32_t maxdeg = 1;
+    for (int32_t c = 0; c < m; ++c)
+        if (row_ptr[c + 1] - row_ptr[c] > maxdeg) maxdeg = row_ptr[c + 1] - row_ptr[c];
+    double* x = (double*)malloc((size_t)maxdeg * sizeof(double));
+    double* mag = (double*)malloc((size_t)maxdeg * sizeof(double));
+    double* w = (double*)malloc((size_t)maxdeg * sizeof(double));
+    double* out = (double*)malloc((size_t)maxdeg * sizeof(double));
+    layered_iteration(n, row_ptr, col_idx, edge_type, n_types, &cv, n_layers, layer_ptr, llr, s, algo, t,
+                      store_half, prec32, alpha, weights, clamp, c2v, post, x, mag, w, out);
+    free(x); free(mag); free(w); free(out);
     free_colview(&cv);
     return 0;
 }

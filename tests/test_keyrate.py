@@ -90,3 +90,24 @@ def test_boundary_optima():
     # a negative margin: no key at any N_R, K' < 0 throughout
     I, A, B1, B2 = _margin_setup(-1e-3)
     assert all(kr.k_prime(g, N, I, A, E_EC, B1, B2) < 0 for g in (1e5, 1e7, 1e9))
+
+
+def test_delta_aep_and_b1_at_the_standard_settings_against_hand_evaluation():
+    """Delta_AEP and B_1 (Sec. IV) evaluated by hand at the paper's standard
+    settings: m = 5, N = 1e9, eps_s = 1.25e-10, eps = eps_EC + 2 eps_s +
+    eps_PA + eps_PE = 1e-9, eps_PA = 2.5e-10, S_BE = 0 (an input here).
+      (m+1)^2                          = 36
+      2 / eps_s^2 = 1.28e20, log2 = 20 log2 10 + log2 1.28 = 66.7947057080;
+      4 (m+1) sqrt(66.7947057080)     = 24 x 8.1728028061 = 196.1472673472
+      2 / (eps^2 eps_s) = 1.6e28, 2 log2 = 2 (28 log2 10 + log2 1.6) = 187.3841171239
+      4 eps_s m / (eps sqrt N)        = 2.5e-9 / 3.16227766e-5 = 0.0000790569
+      Delta_AEP                        = 419.5314635281
+      B_1 = sqrt(N) Delta_AEP + 2 log2(1 / (2 eps_PA)) = 31622.7766017 x 419.5314635
+            + 2 (1 + 9 log2 10) = 13266749.7485 + 61.7947057 = 13266811.5432
+    and with S_BE = 0.5 B_1 grows by N S_BE = 5e8."""
+    d = kr.delta_aep(M_BITS, N, E_S, EPS)
+    assert abs(d - 419.5314635281) < 1e-9 * 419.5
+    assert abs(kr.b1(N, 0.0, d, E_PA) - 13266811.5432) < 1e-3
+    assert abs(kr.b1(N, 0.5, d, E_PA) - (5e8 + 13266811.5432)) < 1e-3
+    # the paper's remark that the last AEP term is negligible at reasonable N
+    assert abs(kr.delta_aep(M_BITS, 1e30, E_S, EPS) - d + 0.0000790569) < 1e-9

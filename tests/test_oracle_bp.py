@@ -380,3 +380,23 @@ def test_unrolled_prec32_forward_matches_binary32_decoder_and_gradient_is_close(
     np.testing.assert_array_equal(u32["post"], d32["post"])
     u64 = oracle.nms_unrolled(code, llr, s, bits, w)
     np.testing.assert_allclose(u32["dw"], u64["dw"], rtol=1e-4, atol=1e-9)
+
+
+def test_scale_trace_is_channel_plus_message_magnitudes_on_a_hand_built_graph():
+    """H = [[1 1 1 0], [0 1 0 1]], L = (1, -2, 3, 0.5), min-sum with alpha = 1,
+    s = 0.  Iteration 1 (v2c = L_ch): row 0 sends (-2, +1, -1) to v0, v1, v2
+    (sign product of the others times their smallest magnitude), row 1 sends
+    (+0.5, -2) to v1, v3.  Scale |L_ch| + sum |c2v| = (3, 3.5, 4, 2.5) and
+    L_post = (-1, -0.5, 2, -1.5).  Iteration 2: v2c of v1 to row 0 is
+    -2 + 0.5 = -1.5 and to row 1 is -2 + 1 = -1; v0, v2, v3 send L_ch.  Row 0
+    sends (-1.5, +1, -1), row 1 sends (+0.5, -1): L_post = (-0.5, -0.5, 2, -0.5)
+    and scale (2.5, 3.5, 4, 1.5)."""
+    H = np.array([[1, 1, 1, 0], [0, 1, 0, 1]], np.uint8)
+    code = _csr_from_dense(H)
+    L = np.array([[1.0, -2.0, 3.0, 0.5]])
+    r = oracle.decode(code, L, None, algo=oracle.NMS, alpha=1.0, max_iter=2, early_stop=False, trace=True)
+    np.testing.assert_array_equal(r["scale_trace"][0, 0], [1.0, 2.0, 3.0, 0.5])
+    np.testing.assert_array_equal(r["post_trace"][0, 1], [-1.0, -0.5, 2.0, -1.5])
+    np.testing.assert_array_equal(r["scale_trace"][0, 1], [3.0, 3.5, 4.0, 2.5])
+    np.testing.assert_array_equal(r["post_trace"][0, 2], [-0.5, -0.5, 2.0, -0.5])
+    np.testing.assert_array_equal(r["scale_trace"][0, 2], [2.5, 3.5, 4.0, 1.5])
