@@ -376,6 +376,8 @@ def recon(args, wl, dev):
     value = decoded_bits / (t_total / args.steps)
 
     # ---- correctness summary of the last step ----
+    for j in (2, 3):
+        api.check_abandoned(outs[j])
     iters = {j: outs[j]["iters"].cpu().numpy() for j in (2, 3)}
     ok = {j: outs[j]["ok"].cpu().numpy() for j in (2, 3)}
     bit_err = {j: int((alice[j] != bob[j]).sum().item()) for j in (2, 3)}
@@ -572,6 +574,7 @@ def ragged(args, wl, dev):
     t_total = time.perf_counter() - t_start
     api.profile_enable(False)
     per_ms, per_n = api.profile_read(6, reset=True)
+    api.check_abandoned(out)
     iters = out["iters"].cpu().numpy()
     ok = out["ok"].cpu().numpy()
     err = (out["bits"] != bits_g).cpu().numpy()

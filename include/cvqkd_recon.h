@@ -214,9 +214,10 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *                    phi(x) = -ln tanh(x/2), v2c clamped to +-msg_clamp first;
  *            CVR_NMS: normalized min-sum, c2v = w (1-2s_c) prod sign * min|v2c|,
  *                    w = weights[t][edge_type] or alpha when weights is NULL.
- *  Flooding schedule.  The syndrome of the hard decisions is tested before the
- *  first iteration and after each one; a frame stops at the first success when
- *  early_stop != 0, and after max_iter iterations otherwise.
+ *  Flooding schedule (every check, then every variable, per iteration) unless
+ *  schedule is CVR_SCHED_LAYERED.  The syndrome of the hard decisions is
+ *  tested before the first iteration and after each one; a frame stops at the
+ *  first success when early_stop != 0, and after max_iter iterations otherwise.
  *  math      CVR_F32 or CVR_F64: arithmetic precision and the dtype of llr,
  *            llr_post_out and trace.
  *  store     precision of the stored check-to-variable messages: CVR_F64
@@ -236,10 +237,24 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            complex die: its compute units share an L2 cache), each group
  *            decoding one frame at a time with barriers between the passes (the
  *            same codes as persistent; every compute unit must be free for the
- *            launch, else a barrier gives up after 0.2 s and the frames are
- *            reported with ok = 0); CVR_SCHED_AUTO: for the codes of the
+ *            launch, else a barrier gives up after 0.2 s and every frame of
+ *            the decode is reported abandoned: iters_out = -1, ok_out = 0);
+ *            CVR_SCHED_AUTO: for the codes of the
  *            persistent schedule, persistent when the batch has at least one
  *            frame per compute unit and group below that; passes otherwise.
+ *            CVR_SCHED_LAYERED is another message-passing order, so its
+ *            results differ from flooding: the layered (row-serial) schedule
+ *            over the block rows of a QC code (Sec. III-C names belief
+ *            propagation without fixing a schedule).  Iteration t updates block
+ *            row 0, 1, ..., mb-1 in turn; row k of block row i forms
+ *            x_e = L[v] - c2v_e for its edges, computes c2v_e by the check rule
+ *            (weights of iteration t) and sets L[v] = x_e + c2v_e with the
+ *            stored c2v_e, so later block rows see the updated L.  L starts
+ *            as the channel LLRs; the syndrome test, stop rule and outputs are
+ *            those of flooding.  One workgroup decodes a frame (the codes of
+ *            the persistent schedule, else CVR_EUNSUPPORTED); wg_threads may be
+ *            0 (= 512), 256, 512 or 1024 and lds_cache_kb applies; min_waves
+ *            and group_wgs are ignored.
  *  wg_threads, min_waves  tuning knobs of the persistent decoder that do
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
@@ -257,7 +272,8 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *  group_wgs workgroups per frame of the group schedule (results unchanged):
  *            0 = the workgroups an XCD holds divided by its frames, at least
  *            1; capped by the workgroups an XCD holds.                        */
-enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2, CVR_SCHED_GROUP = 3 };
+enum { CVR_SCHED_AUTO = 0, CVR_SCHED_PASSES = 1, CVR_SCHED_PERSISTENT = 2, CVR_SCHED_GROUP = 3,
+       CVR_SCHED_LAYERED = 4 };
 
 typedef struct {
     int32_t algo;
@@ -285,7 +301,9 @@ cvr_status cvr_decode_workspace_size(cvr_batch_t batch, const cvr_decode_params*
  *  syndrome:     device uint8 [total_m] Bob's syndromes, or NULL (all zero);
  *  bits_out:     device uint8 [total_n] hard decisions at the stop;
  *  llr_post_out: device [total_n] posteriors at the stop (math dtype) or NULL;
- *  iters_out:    device int32 [F] iteration at which the frame stopped;
+ *  iters_out:    device int32 [F] iteration at which the frame stopped, or -1
+ *                when the decode was abandoned (a group barrier gave up, see
+ *                CVR_SCHED_GROUP): the frame's other outputs are then invalid;
  *  ok_out:       device uint8 [F] 1 iff the syndrome was satisfied at the stop;
  *  workspace:    device, >= cvr_decode_workspace_size bytes, 256-byte aligned.
  * Non-finite LLRs are allowed.  A check touching a NaN posterior counts as
@@ -358,9 +376,9 @@ cvr_status cvr_profile_read(int32_t kind, double* total_ms, int64_t* launches, i
  * `ticks` of the 100 MHz device wall clock, for later launches of this
  * process; the default is 20,000,000 (0.2 s).  With 0 a barrier that is not
  * complete when a workgroup arrives gives up at once: the launch still ends,
- * and every frame of that decode is reported with ok = 0 (the path a barrier
- * takes when a group's workgroups are not all resident).  For tests of that
- * failure path.  ticks > 1e10 returns CVR_EINVAL. */
+ * and every frame of that decode is reported abandoned, iters = -1 and
+ * ok = 0 (the path a barrier takes when a group's workgroups are not all
+ * resident).  For tests of that failure path.  ticks > 1e10 returns CVR_EINVAL. */
 cvr_status cvr_debug_group_wait_ticks(uint64_t ticks);
 
 #ifdef __cplusplus

@@ -19,7 +19,7 @@ from ._lib import DecodeParams, Frame, check, load
 GRAY, BINARY = 0, 1
 SP, NMS = 0, 1
 F64, F32, F16 = 0, 1, 2
-SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT, SCHED_GROUP = 0, 1, 2, 3
+SCHED_AUTO, SCHED_PASSES, SCHED_PERSISTENT, SCHED_GROUP, SCHED_LAYERED = 0, 1, 2, 3, 4
 
 _TORCH_OF = {F64: torch.float64, F32: torch.float32}
 
@@ -115,6 +115,9 @@ class Batch:
         check(load().cvr_batch_info(h, C.byref(F), C.byref(tn), C.byref(tm), C.byref(te)), "cvr_batch_info")
         self.F, self.total_n, self.total_m, self.total_edges = F.value, tn.value, tm.value, te.value
         self.frames = [tuple(int(x) for x in f) for f in frames]
+        # per-type weights are indexed [t * n_types + type] with the largest
+        # number of edge types among the batch's codes
+        self.n_types = max((c.n_types for c in self.codes), default=1)
 
     @classmethod
     def uniform(cls, code: Code, F: int) -> "Batch":
@@ -305,6 +308,24 @@ def syndrome_check(code: Code, bits: torch.Tensor, syndrome: torch.Tensor | None
     return s_out, u
 
 
+def _check_weights(weights: torch.Tensor, T: int, n_types: int, what: str) -> None:
+    """The kernels read weights[t * n_types + type] for every t < T."""
+    if not isinstance(weights, torch.Tensor):
+        raise ValueError(f"{what}: weights must be a tensor")
+    if weights.dtype != torch.float32 or not weights.is_contiguous():
+        raise ValueError(f"{what}: weights must be contiguous float32")
+    if weights.numel() != T * n_types:
+        raise ValueError(f"{what}: weights must hold max_iter x n_types = {T} x {n_types} entries, "
+                         f"not {weights.numel()}")
+    if not weights.is_cuda:
+        raise ValueError(f"{what}: weights must be a device tensor")
+
+
+def _check_len(t: torch.Tensor, n: int, dtype, what: str) -> None:
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{what} must be contiguous {dtype} with >= {n} entries")
+
+
 def decode_workspace_size(batch: Batch, params: Params) -> int:
     sz = C.c_size_t()
     p = params.c_struct()
@@ -339,11 +360,22 @@ def ldpc_decode_batch(batch: Batch, params: Params, llr: torch.Tensor, syndrome:
         workspace = alloc_workspace(batch, params, dev)
     if trace is not None and (trace.dtype != mdt or trace.numel() < (params.max_iter + 1) * batch.total_n):
         raise ValueError("trace must have (max_iter + 1) * total_n entries of the math dtype")
+    if params.weights is not None:
+        _check_weights(params.weights, params.max_iter, batch.n_types, "ldpc_decode_batch")
     p = params.c_struct(trace)
     check(load().ldpc_decode_batch(batch.handle, C.byref(p), _ptr(llr), _ptr(syndrome), _ptr(out["bits"]),
                                    _ptr(out.get("post")), _ptr(out["iters"]), _ptr(out["ok"]),
                                    _ptr(workspace), workspace.numel(), _stream(stream)), "ldpc_decode_batch")
     return out
+
+
+def check_abandoned(out: dict) -> None:
+    """Raises CvrError(CVR_EHIP) when the decode that wrote ``out`` was abandoned
+    (iters = -1: a barrier of the group schedule gave up because its workgroups
+    were not all resident).  Waits for the decode."""
+    if out["iters"].numel() and int(out["iters"].min().item()) < 0:
+        raise _lib.CvrError(_lib.CVR_EHIP, "ldpc_decode_batch",
+                            "the decode was abandoned: a group barrier gave up (frames report iters = -1)")
 
 
 def version() -> int:
@@ -391,14 +423,15 @@ def nms_unrolled_fwd(batch: Batch, T: int, ckpt_every: int, weights: torch.Tenso
                      syndrome: torch.Tensor | None = None, stream=None):
     """Posteriors after T weighted min-sum iterations and the checkpoints."""
     ck, fw, _ = nms_unrolled_sizes(batch, T, ckpt_every)
+    _check_weights(weights, T, batch.n_types, "nms_unrolled_fwd")
+    _check_len(llr, batch.total_n, torch.float32, "nms_unrolled_fwd: llr")
+    if syndrome is not None:
+        _check_len(syndrome, batch.total_m, torch.uint8, "nms_unrolled_fwd: syndrome")
     dev = llr.device
     post = torch.empty(batch.total_n, dtype=torch.float32, device=dev)
     ckpt = torch.empty(max(ck, 1), dtype=torch.float32, device=dev)
     ws = torch.empty(max(fw, 256), dtype=torch.uint8, device=dev)
-    for name, t in (("weights", weights), ("llr", llr)):
-        if t.dtype != torch.float32:
-            raise ValueError(f"{name} must be float32")
-    check(load().nms_unrolled_fwd(batch.handle, int(T), int(ckpt_every), _ptr(weights.contiguous()), _ptr(llr),
+    check(load().nms_unrolled_fwd(batch.handle, int(T), int(ckpt_every), _ptr(weights), _ptr(llr),
                                   _ptr(syndrome), _ptr(post), _ptr(ckpt), _ptr(ws), ws.numel(), _stream(stream)),
           "nms_unrolled_fwd")
     return post, ckpt
@@ -409,12 +442,19 @@ def nms_unrolled_bwd(batch: Batch, T: int, ckpt_every: int, weights: torch.Tenso
                      want_dllr: bool = False, stream=None):
     """(d loss / d weights [T, n_types], d loss / d llr or None)."""
     _, _, bw = nms_unrolled_sizes(batch, T, ckpt_every)
+    _check_weights(weights, T, batch.n_types, "nms_unrolled_bwd")
+    _check_len(llr, batch.total_n, torch.float32, "nms_unrolled_bwd: llr")
+    _check_len(dloss_dpost, batch.total_n, torch.float32, "nms_unrolled_bwd: dloss_dpost")
+    if syndrome is not None:
+        _check_len(syndrome, batch.total_m, torch.uint8, "nms_unrolled_bwd: syndrome")
+    ck, _, _ = nms_unrolled_sizes(batch, T, ckpt_every)
+    _check_len(ckpt, ck, torch.float32, "nms_unrolled_bwd: ckpt")
     dev = llr.device
     dw = torch.empty_like(weights, dtype=torch.float32).contiguous()
     dl = torch.empty(batch.total_n, dtype=torch.float32, device=dev) if want_dllr else None
     ws = torch.empty(max(bw, 256), dtype=torch.uint8, device=dev)
-    check(load().nms_unrolled_bwd(batch.handle, int(T), int(ckpt_every), _ptr(weights.contiguous()), _ptr(llr),
-                                  _ptr(syndrome), _ptr(ckpt), _ptr(dloss_dpost.contiguous()), _ptr(dw), _ptr(dl),
+    check(load().nms_unrolled_bwd(batch.handle, int(T), int(ckpt_every), _ptr(weights), _ptr(llr),
+                                  _ptr(syndrome), _ptr(ckpt), _ptr(dloss_dpost), _ptr(dw), _ptr(dl),
                                   _ptr(ws), ws.numel(), _stream(stream)), "nms_unrolled_bwd")
     return dw, dl
 
@@ -437,6 +477,6 @@ class NMSUnrolled(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_post):
         w, l, ckpt = ctx.saved_tensors
-        dw, dl = nms_unrolled_bwd(ctx.batch, ctx.T, ctx.K, w, l, ctx.syndrome, ckpt, grad_post,
+        dw, dl = nms_unrolled_bwd(ctx.batch, ctx.T, ctx.K, w, l, ctx.syndrome, ckpt, grad_post.contiguous(),
                                   want_dllr=ctx.needs_input_grad[1])
         return dw, dl, None, None, None, None

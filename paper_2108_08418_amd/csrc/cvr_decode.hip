@@ -1,5 +1,5 @@
-// Batched flooding belief-propagation decoding of sub-blocks (Sec. III-A,
-// Sec. III-C) and syndrome checks (Sec. II Step 5).
+// Batched belief-propagation decoding of sub-blocks (Sec. III-A, Sec. III-C),
+// flooding or layered, and syndrome checks (Sec. II Step 5).
 //
 // State kept between the two half-iterations of frame f:
 //   c2v  [msg_off .. msg_off + E)  check-to-variable messages (store dtype)
@@ -116,9 +116,13 @@ static cvr_status check_params(const cvr_batch_s* b, const cvr_decode_params* p)
     if (p->math == CVR_F64 && p->store != CVR_F64)
         return fail(CVR_EUNSUPPORTED, "decode: F64 math is implemented with F64 storage only");
     if (p->algo == CVR_SP && !(p->msg_clamp > 0.0f)) return fail(CVR_EINVAL, "decode: msg_clamp must be > 0");
-    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_GROUP) return fail(CVR_EINVAL, "decode: bad schedule");
-    if (p->wg_threads != 0 && p->wg_threads != 512 && p->wg_threads != 1024)
+    if (p->schedule < CVR_SCHED_AUTO || p->schedule > CVR_SCHED_LAYERED) return fail(CVR_EINVAL, "decode: bad schedule");
+    if (p->schedule == CVR_SCHED_LAYERED) {
+        if (p->wg_threads != 0 && p->wg_threads != 256 && p->wg_threads != 512 && p->wg_threads != 1024)
+            return fail(CVR_EINVAL, "decode: wg_threads must be 0, 256, 512 or 1024");
+    } else if (p->wg_threads != 0 && p->wg_threads != 512 && p->wg_threads != 1024) {
         return fail(CVR_EINVAL, "decode: wg_threads must be 0, 512 or 1024");
+    }
     if (p->min_waves != 0 && p->min_waves != 8) return fail(CVR_EINVAL, "decode: min_waves must be 0 or 8");
     if (p->lds_cache_kb < -1 || p->lds_cache_kb > 1024) return fail(CVR_EINVAL, "decode: lds_cache_kb must be in [-1, 1024]");
     if (p->group_wgs < 0 || p->group_wgs > 1024) return fail(CVR_EINVAL, "decode: group_wgs must be in [0, 1024]");
@@ -195,6 +199,11 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
             return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the group schedule needs QC codes with <= 2048 "
                                           "circulants, <= 512 block rows/columns and Z <= 65535");
         mode = 2;
+    } else if (params->schedule == CVR_SCHED_LAYERED) {
+        if (!frames_fit(batch))
+            return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch: the layered schedule needs QC codes with <= 2048 "
+                                          "circulants, <= 512 block rows/columns and Z <= 65535");
+        mode = 3;
     } else if (params->schedule == CVR_SCHED_AUTO) {
         // a workgroup per frame leaves compute units idle below one frame per
         // CU; then groups of workgroups share each frame (16 frames of 2^16:

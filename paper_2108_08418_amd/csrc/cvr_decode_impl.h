@@ -462,6 +462,7 @@ constexpr int kMaxLdsZ = 65535;
 struct LdsMap {
     int32_t rptr, cptr, row, col, cslot, cache;   // word offsets
     int32_t cache_bytes;
+    int32_t hard;                                 // layered schedule: hard-decision bits
 };
 constexpr int32_t kCached = 1 << 29;
 
@@ -1251,12 +1252,368 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
     for (int q = int(threadIdx.x); q < words; q += 256) ws[q] = 0;
 }
 
-// A barrier that gave up leaves the frames' results unreliable: report every
-// frame as not decoded.
-[[maybe_unused]] __global__ __launch_bounds__(256) static void k_group_final(uint8_t* ok, const int32_t* ws, int32_t F)
+// A barrier that gave up leaves the frames' results unreliable: every frame
+// of the decode is reported as abandoned, iters = -1 and ok = 0, which a
+// caller tells apart from a decoding failure (iters >= 0, ok = 0).
+[[maybe_unused]] __global__ __launch_bounds__(256) static void k_group_final(uint8_t* ok, int32_t* iters,
+                                                                             const int32_t* ws, int32_t F)
 {
     const int f = int(blockIdx.x) * 256 + int(threadIdx.x);
-    if (f < F && ws[kGwErr]) ok[f] = 0;
+    if (f < F && ws[kGwErr]) {
+        ok[f] = 0;
+        iters[f] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layered (row-serial) schedule for quasi-cyclic codes, one workgroup per frame
+// ---------------------------------------------------------------------------
+// Layer i is block row i: its Z checks touch every block column at most once
+// (one circulant per protograph entry), so they share no variable and update
+// in parallel.  Iteration t runs the layers i = 0 .. mb-1 in order; for row k
+// of layer i and its edge q at variable v = j_q Z + (k + s_q) mod Z:
+//     x_q   = L[v] - c2v_q          (c2v_q from iteration t-1; 0 at t = 0)
+//     c2v_q = the check rule over x (weights of iteration t), stored
+//     L[v]  = x_q + c2v_q           (the stored value, as it will be read back)
+// L is the running posterior (L_ch before the first iteration), so a layer
+// sees every update of the layers before it in the same iteration.  The
+// syndrome of the hard decisions of L is tested before the first iteration
+// and after each one.
+//
+// State: c2v in HBM in the flooding layout ([block][k]); L in LDS for the
+// cached (highest-degree) block columns and in the frame's posterior array
+// otherwise; the hard decisions as a bit array in LDS (bit j Z + p for
+// variable p of block column j), kept equal to [L < 0] by flipping a bit
+// whenever an update changes the sign; a flag that any posterior is NaN (a
+// NaN posterior stays NaN: x = NaN - c and L = NaN + c), which makes the
+// syndrome test fail as a NaN does in the flooding schedule.
+//
+// Dynamic LDS (LdsMap, 32-bit words): rptr [mb+1], cptr [nb+1] (unused),
+// row [NB] (shift | loc << 16 | type << 25 | cached << 29, as the persistent
+// decoder's), col [NB] (block column of row entry q), cslot [nb], hard
+// [n / 32], then the posterior cache.
+template <typename M, int NT>
+__device__ __forceinline__ void load_layer_tables(const LdsMap& lm, int32_t* dsm, const DevCode& cd)
+{
+    const int tid = int(threadIdx.x);
+    int32_t* s_rptr = dsm + lm.rptr;
+    int32_t* s_row = dsm + lm.row;
+    int32_t* s_lcol = dsm + lm.col;
+    int32_t* s_cslot = dsm + lm.cslot;
+    const int nslot = min(cd.nb, int(lm.cache_bytes / (int64_t(cd.Z) * int64_t(sizeof(M)))));
+    for (int q = tid; q <= cd.mb; q += NT) s_rptr[q] = cd.qrow_ptr[q];
+    for (int q = tid; q < cd.nb; q += NT) s_cslot[q] = -1;
+    __syncthreads();
+    for (int q = tid; q < nslot; q += NT) s_cslot[cd.qcol_rank[q]] = q;
+    __syncthreads();
+    for (int q = tid; q < cd.NB; q += NT) {
+        const QcBlock br = cd.qrow[q];
+        const int slot = s_cslot[br.other];
+        const int loc = slot >= 0 ? slot : br.other;
+        s_row[q] = br.shift | (loc << 16) | (br.type << 25) | (slot >= 0 ? kCached : 0);
+        s_lcol[q] = br.other;
+    }
+    __syncthreads();
+}
+
+// What the layer steps of one frame need beyond FrameCtx.
+struct LayerCtx {
+    const int32_t* s_lcol;
+    uint32_t* s_hard;
+    int32_t* s_nan;
+};
+
+// Rows k[0..R) of the layer whose table entries start at q0, with exactly D
+// edges: all R x D posteriors and stored messages are loaded before any
+// arithmetic, then each row is updated and written back.
+template <typename M, typename S, int ALGO, int D, bool CACHE, int R>
+__device__ __forceinline__ void layer_rows(const FrameCtx<M, S>& c, const LayerCtx& lc, int q0, const int (&k)[R],
+                                           const int (&sraw)[R])
+{
+    int32_t e[D], jc[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+        e[q] = __builtin_amdgcn_readfirstlane(c.s_row[q0 + q]);
+        jc[q] = __builtin_amdgcn_readfirstlane(lc.s_lcol[q0 + q]);
+    }
+    int idx[R][D];
+    M lr[R][D];
+    S mr[R][D];
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            int p = k[h] + (e[q] & 0xffff);
+            p = p >= c.Z ? p - c.Z : p;
+            idx[h][q] = p;
+            const int at_loc = ((e[q] >> 16) & 0x1ff) * c.Z + p;
+            if (CACHE && (e[q] & kCached)) lr[h][q] = lds_read(c.s_post + at_loc);
+            else lr[h][q] = at(c.Lp, uint32_t(at_loc));
+        }
+    }
+    if (c.t > 0) {
+#pragma unroll
+        for (int h = 0; h < R; ++h) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) mr[h][q] = at(c.msg, uint32_t((q0 + q) * c.Z + k[h]));
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < R; ++h) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) mr[h][q] = S(0);
+        }
+    }
+    bool nan = false;
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+        M x[D], nl[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) x[q] = lr[h][q] - M(StoreT<S>::get(mr[h][q]));
+        auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
+        auto emit = [&](int q, M v) {
+            const S sv = StoreT<S>::put(v);
+            at(c.msg, uint32_t((q0 + q) * c.Z + k[h])) = sv;
+            nl[q] = x[q] + M(StoreT<S>::get(sv));
+        };
+        check_rule<M, ALGO, D>(x, D, sraw[h] & 1, M(c.clamp), weight, emit);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const int at_loc = ((e[q] >> 16) & 0x1ff) * c.Z + idx[h][q];
+            if (CACHE && (e[q] & kCached)) c.s_post[at_loc] = nl[q];
+            else at(c.Lp, uint32_t(at_loc)) = nl[q];
+            nan |= nl[q] != nl[q];
+            if ((lr[h][q] < M(0)) != (nl[q] < M(0))) {
+                const uint32_t b = uint32_t(jc[q] * c.Z + idx[h][q]);
+                atomicXor(lc.s_hard + (b >> 5), 1u << (b & 31));
+            }
+        }
+    }
+    if (nan) *lc.s_nan = 1;
+}
+
+// The same for any degree d <= MAXD (one row, masked).
+template <typename M, typename S, int ALGO, int MAXD, bool CACHE>
+__device__ __forceinline__ void layer_row_any(const FrameCtx<M, S>& c, const LayerCtx& lc, int q0, int d, int k,
+                                              int sraw)
+{
+    int32_t e[MAXD], jc[MAXD], idx[MAXD];
+    M lr[MAXD], x[MAXD], nl[MAXD];
+    S mr[MAXD];
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) {
+        e[q] = (q < d) ? __builtin_amdgcn_readfirstlane(c.s_row[q0 + q]) : 0;
+        jc[q] = (q < d) ? __builtin_amdgcn_readfirstlane(lc.s_lcol[q0 + q]) : 0;
+        lr[q] = M(0);
+        mr[q] = S(0);
+        idx[q] = 0;
+        nl[q] = M(0);
+        if (q < d) {
+            int p = k + (e[q] & 0xffff);
+            p = p >= c.Z ? p - c.Z : p;
+            idx[q] = p;
+            const int at_loc = ((e[q] >> 16) & 0x1ff) * c.Z + p;
+            if (CACHE && (e[q] & kCached)) lr[q] = lds_read(c.s_post + at_loc);
+            else lr[q] = at(c.Lp, uint32_t(at_loc));
+            if (c.t > 0) mr[q] = at(c.msg, uint32_t((q0 + q) * c.Z + k));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) x[q] = (q < d) ? lr[q] - M(StoreT<S>::get(opaque(mr[q]))) : M(0);
+    auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
+    auto emit = [&](int q, M v) {
+        const S sv = StoreT<S>::put(v);
+        at(c.msg, uint32_t((q0 + q) * c.Z + k)) = sv;
+        nl[q] = x[q] + M(StoreT<S>::get(sv));
+    };
+    check_rule<M, ALGO, MAXD>(x, d, sraw & 1, M(c.clamp), weight, emit);
+    bool nan = false;
+#pragma unroll
+    for (int q = 0; q < MAXD; ++q) {
+        if (q < d) {
+            const int at_loc = ((e[q] >> 16) & 0x1ff) * c.Z + idx[q];
+            if (CACHE && (e[q] & kCached)) c.s_post[at_loc] = nl[q];
+            else at(c.Lp, uint32_t(at_loc)) = nl[q];
+            nan |= nl[q] != nl[q];
+            if ((lr[q] < M(0)) != (nl[q] < M(0))) {
+                const uint32_t b = uint32_t(jc[q] * c.Z + idx[q]);
+                atomicXor(lc.s_hard + (b >> 5), 1u << (b & 31));
+            }
+        }
+    }
+    if (nan) *lc.s_nan = 1;
+}
+
+// One frame, all iterations, on the layered schedule.
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool CACHE>
+__device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const LdsMap& lm, int32_t* dsm,
+                                                     int32_t (&s_unsat)[2], int32_t& s_nan, float (&s_w)[kMaxTypes],
+                                                     int f, const DevFrame& fr, const DevCode& cd)
+{
+    const int tid = int(threadIdx.x);
+    const int Z = cd.Z;
+    const int mb = cd.mb, m = cd.mb * Z, n = cd.nb * Z;
+    const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
+    const int32_t* s_rptr = dsm + lm.rptr;
+    FrameCtx<M, S> c;
+    c.Lp = static_cast<M*>(a.post) + fr.vn_off;
+    c.Lc = static_cast<const M*>(a.llr) + fr.vn_off;
+    c.msg = static_cast<S*>(a.c2v) + fr.msg_off;
+    c.s_row = dsm + lm.row;
+    c.s_col = nullptr;
+    c.s_cslot = dsm + lm.cslot;
+    c.s_post = reinterpret_cast<M*>(dsm + lm.cache);
+    c.s_w = s_w;
+    c.Z = Z;
+    c.T = a.T;
+    c.weighted = a.weights != nullptr;
+    c.alpha = a.alpha;
+    c.clamp = a.clamp;
+    LayerCtx lc{dsm + lm.col, reinterpret_cast<uint32_t*>(dsm + lm.hard), &s_nan};
+    const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
+    M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
+    auto column = [&](int v) { return zsh >= 0 ? (v >> zsh) : v / Z; };
+    auto slot_of = [&](int j) { return CACHE ? c.s_cslot[j] : -1; };
+    auto post_at = [&](int v) -> M {
+        const int j = column(v);
+        const int slot = slot_of(j);
+        return slot >= 0 ? c.s_post[slot * Z + (v - j * Z)] : at(c.Lp, v);
+    };
+    for (int w = tid; w < (n + 31) / 32; w += NT) lc.s_hard[w] = 0u;
+    if (tid == 0) {
+        s_unsat[0] = 0;
+        s_unsat[1] = 0;
+        s_nan = 0;
+    }
+    __syncthreads();
+    for (int v = tid; v < n; v += NT) {
+        const int j = column(v);
+        const int slot = slot_of(j);
+        const M l = at(c.Lc, v);
+        if (slot >= 0) c.s_post[slot * Z + (v - j * Z)] = l;
+        else at(c.Lp, v) = l;
+        if (tr) tr[v] = l;
+        if (l < M(0)) atomicOr(lc.s_hard + (v >> 5), 1u << (v & 31));
+        if (l != l) s_nan = 1;
+    }
+    // rows per thread and body: R rows k0 + h Z / R of a layer, so that R x D
+    // loads are in flight together when a layer has more rows than threads
+    const int R = (Z >= 4 * NT && Z % 4 == 0) ? 4 : ((Z >= 2 * NT && Z % 2 == 0) ? 2 : 1);
+    for (int t = 0;; ++t) {
+        c.t = t;
+        // the weights of iteration t (every read of the previous ones ended at
+        // the barrier after the last layer)
+        if (a.weights && t < a.T && tid < a.n_types) s_w[tid] = a.weights[int64_t(t) * a.n_types + tid];
+        __syncthreads();
+        // syndrome test of the hard decisions of L
+        int bad = 0;
+        for (int r = tid; r < m; r += NT) {
+            const int i = zsh >= 0 ? (r >> zsh) : r / Z;
+            const int k = r - i * Z;
+            const int q1 = s_rptr[i + 1];
+            int par = syn ? int(at(syn, r)) & 1 : 0;
+            for (int q = s_rptr[i]; q < q1; ++q) {
+                int p = k + (c.s_row[q] & 0xffff);
+                p = p >= Z ? p - Z : p;
+                const uint32_t b = uint32_t(lc.s_lcol[q] * Z + p);
+                par ^= int(lc.s_hard[b >> 5] >> (b & 31)) & 1;
+            }
+            bad += par;
+        }
+        if (bad) atomicAdd(&s_unsat[t & 1], bad);
+        __syncthreads();
+        const int u = s_unsat[t & 1] + (s_nan ? 1 : 0);
+        if ((a.early_stop && u == 0) || t >= a.T) {
+            if (tid == 0) {
+                a.iters[f] = t;
+                a.ok[f] = uint8_t(u == 0);
+            }
+            break;
+        }
+        if (tid == 0) s_unsat[(t + 1) & 1] = 0;
+        for (int i = 0; i < mb; ++i) {
+            const int q0 = __builtin_amdgcn_readfirstlane(s_rptr[i]);
+            const int d = __builtin_amdgcn_readfirstlane(s_rptr[i + 1]) - q0;
+            const uint8_t* si = syn ? syn + i * Z : nullptr;
+            auto rows = [&](auto rc) {
+                constexpr int RR = decltype(rc)::value;
+                const int qz = Z / RR;
+                for (int p = tid; p < qz; p += NT) {
+                    int kk[RR], ss[RR];
+#pragma unroll
+                    for (int h = 0; h < RR; ++h) {
+                        kk[h] = p + h * qz;
+                        ss[h] = si ? int(at(si, kk[h])) : 0;
+                    }
+                    switch (d) {
+                    case 1: layer_rows<M, S, ALGO, 1, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 2: layer_rows<M, S, ALGO, 2, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 3: layer_rows<M, S, ALGO, 3, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 4: layer_rows<M, S, ALGO, 4, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 5: layer_rows<M, S, ALGO, 5, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 6: layer_rows<M, S, ALGO, 6, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 7: layer_rows<M, S, ALGO, 7, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    case 8: layer_rows<M, S, ALGO, 8, CACHE, RR>(c, lc, q0, kk, ss); break;
+                    default:
+                        if constexpr (MAXD > 8) {
+                            for (int h = 0; h < RR; ++h)
+                                layer_row_any<M, S, ALGO, MAXD, CACHE>(c, lc, q0, d, kk[h], ss[h]);
+                        }
+                        break;
+                    }
+                }
+            };
+            if (R == 4) rows(std::integral_constant<int, 4>{});
+            else if (R == 2) rows(std::integral_constant<int, 2>{});
+            else rows(std::integral_constant<int, 1>{});
+            __syncthreads();
+        }
+        if (tr)
+            for (int v = tid; v < n; v += NT) tr[int64_t(t + 1) * a.total_n + v] = post_at(v);
+    }
+    // hard decisions; cached posteriors go back to HBM
+    for (int v = tid; v < n; v += NT) {
+        const int j = column(v);
+        const int slot = slot_of(j);
+        M l;
+        if (slot >= 0) {
+            l = c.s_post[slot * Z + (v - j * Z)];
+            at(c.Lp, v) = l;
+        } else {
+            l = at(c.Lp, v);
+        }
+        a.bits[fr.vn_off + v] = l < M(0) ? 1 : 0;
+    }
+}
+
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool CACHE>
+__global__ __launch_bounds__(NT) void k_layered_qc(DecArgs a, LdsMap lm, int32_t* queue, int32_t F,
+                                                   const int32_t* order)
+{
+    extern __shared__ __align__(16) int32_t dsm[];
+    __shared__ int32_t s_frame;
+    __shared__ int32_t s_unsat[2];
+    __shared__ int32_t s_nan;
+    __shared__ float s_w[kMaxTypes];
+    const int tid = int(threadIdx.x);
+    int cur = -1;
+    for (;;) {
+        if (tid == 0) {
+            const int slot = atomicAdd(queue, 1);
+            s_frame = slot < F ? order[slot] : F;
+        }
+        __syncthreads();
+        const int f = __builtin_amdgcn_readfirstlane(s_frame);
+        if (f >= F) break;
+        const DevFrame fr = a.frames[f];
+        const DevCode& cd = a.codes[fr.code];
+        if (fr.code != cur) {
+            load_layer_tables<M, NT>(lm, dsm, cd);
+            cur = fr.code;
+        }
+        decode_frame_layered<M, S, ALGO, MAXD, NT, CACHE>(a, lm, dsm, s_unsat, s_nan, s_w, f, fr, cd);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1524,7 +1881,7 @@ static cvr_status launch_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, i
     if (cvr_status st = check_launch("decode (group)")) return st;
     {
         ProfScope prof(CVR_PROF_DEC_SETUP, s);
-        hipLaunchKernelGGL(k_group_final, dim3((b->F + 255) / 256), dim3(256), 0, s, a.ok, ws, b->F);
+        hipLaunchKernelGGL(k_group_final, dim3((b->F + 255) / 256), dim3(256), 0, s, a.ok, a.iters, ws, b->F);
     }
     return check_launch("decode (group) final");
 }
@@ -1543,7 +1900,74 @@ static cvr_status run_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int3
     }
 }
 
-// mode: 0 per-pass launches, 1 persistent frame-per-workgroup, 2 frame groups
+// Layered schedule (QC codes whose tables fit in LDS): one workgroup per frame
+// from the frame queue; NT threads (256, 512 or 1024); the LDS left after the
+// tables and the hard-decision bits caches posteriors (lds_kb as for the
+// persistent decoder).
+template <typename M, typename S, int ALGO, int MAXD, int NT>
+static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int lds_kb)
+{
+    auto kern = k_layered_qc<M, S, ALGO, MAXD, NT, true>;
+    static int lds_blk = 0, lds_cu = 0, static_lds = 0;
+    if (lds_blk == 0) {
+        lds_cu = device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 65536);
+        lds_blk = std::min(lds_cu, device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536));
+        hipFuncAttributes fa{};
+        static_lds = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kern)) == hipSuccess
+                         ? int(fa.sharedSizeBytes) : 1024;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  lds_blk - static_lds);
+    }
+    int64_t max_n = 0;
+    for (const cvr_code_t c : b->codes) max_n = std::max<int64_t>(max_n, c->dev.n);
+    auto map = [&](int cache_bytes) {
+        LdsMap lm = lds_map(b, cache_bytes);
+        lm.hard = lm.cache;
+        lm.cache = int32_t((lm.hard + (max_n + 31) / 32 + 3) / 4 * 4);
+        return lm;
+    };
+    const int tab = map(0).cache * 4;
+    const int room = lds_blk - static_lds - tab;
+    if (room < 0) return fail(CVR_EUNSUPPORTED, "decode (layered): code tables and decision bits exceed LDS");
+    auto occupancy = [&](int dyn) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, NT, size_t(dyn)) != hipSuccess || v < 1) v = 1;
+        return v;
+    };
+    int cache = 0;
+    if (lds_kb > 0) {
+        cache = std::min(room, lds_kb * 1024);
+    } else if (lds_kb == 0) {
+        const int want = occupancy(tab);
+        cache = std::min(room, lds_cu / want - static_lds - tab - 512);
+        while (cache > 0 && occupancy(tab + cache) < want) cache -= 2048;
+    }
+    cache = std::max(0, cache) / 256 * 256;
+    const LdsMap lm = map(cache);
+    const int dyn = tab + cache;
+    const int per_cu = occupancy(dyn);
+    const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
+    ProfScope prof(CVR_PROF_FRAMES, s);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), size_t(dyn), s, a, lm, queue, b->F, b->d_order);
+    return check_launch("decode (layered)");
+}
+
+template <typename M, typename S, int ALGO, int MAXD>
+static cvr_status run_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, const LaunchShape& sh)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, s, queue, int64_t(1));
+    if (cvr_status st = check_launch("decode queue reset")) return st;
+    if constexpr (sizeof(M) == 8 || MAXD > 8) {
+        return launch_layered<M, S, ALGO, MAXD, 512>(b, a, queue, s, sh.lds_kb);
+    } else {
+        if (sh.wg == 256) return launch_layered<M, S, ALGO, MAXD, 256>(b, a, queue, s, sh.lds_kb);
+        if (sh.wg == 1024) return launch_layered<M, S, ALGO, MAXD, 1024>(b, a, queue, s, sh.lds_kb);
+        return launch_layered<M, S, ALGO, MAXD, 512>(b, a, queue, s, sh.lds_kb);
+    }
+}
+
+// mode: 0 per-pass launches, 1 persistent frame-per-workgroup, 2 frame groups,
+// 3 layered schedule (one workgroup per frame)
 template <typename M, typename S, int ALGO>
 static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, bool qc, int mode, int32_t* queue,
                                int32_t* gridws, const LaunchShape& sh)
@@ -1552,6 +1976,10 @@ static cvr_status dispatch_deg(const cvr_batch_s* b, DecArgs a, hipStream_t s, b
         if (b->max_row_deg <= 8) return run_frames<M, S, ALGO, 8>(b, a, queue, s, sh);
         if (b->max_row_deg <= 16) return run_frames<M, S, ALGO, 16>(b, a, queue, s, sh);
         return run_frames<M, S, ALGO, 32>(b, a, queue, s, sh);
+    }
+    if (mode == 3) {
+        if (b->max_row_deg <= 8) return run_layered<M, S, ALGO, 8>(b, a, queue, s, sh);
+        return run_layered<M, S, ALGO, 32>(b, a, queue, s, sh);
     }
     if (mode == 2) {
         if (b->max_row_deg <= 8) return run_group<M, S, ALGO, 8>(b, a, s, gridws, sh);

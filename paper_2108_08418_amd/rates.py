@@ -58,6 +58,7 @@ def select_slice_rate(slice_j: int, n: int, frames: int = 64, snr: float = 3.0, 
             syn, _ = api.syndrome_check(code, bob, want_unsat=False)
             out = api.ldpc_decode_batch(batch, params, llr, syn.view(-1), want_post=False)
             torch.cuda.synchronize()        # code and batch are released when rebound
+            api.check_abandoned(out)
             ok = out["ok"].to(torch.bool)
             wrong = (out["bits"].view(frames, n) != bob).any(dim=1)
             csr = qc.to_csr()

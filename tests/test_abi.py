@@ -98,3 +98,20 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _lib.load()
+
+
+def test_binding_rejects_weights_that_do_not_match_the_batch():
+    """The kernels read weights[t * n_types + type] for every t < T: the binding
+    refuses a weight tensor of another size, dtype or layout before any call."""
+    import torch
+    from paper_2108_08418_amd import api
+    ok = torch.zeros(20, 3, dtype=torch.float32)
+    for bad, msg in ((torch.zeros(19, 3), "20 x 3"), (torch.zeros(20, 4), "20 x 3"),
+                     (torch.zeros(20, 3, dtype=torch.float64), "float32"),
+                     (torch.zeros(3, 20).t(), "contiguous"), (ok, "device")):
+        with pytest.raises(ValueError, match=msg):
+            api._check_weights(bad, 20, 3, "test")
+    with pytest.raises(ValueError, match=">= 100"):
+        api._check_len(torch.zeros(99, dtype=torch.float32), 100, torch.float32, "llr")
+    with pytest.raises(ValueError, match="float32"):
+        api._check_len(torch.zeros(100, dtype=torch.float64), 100, torch.float32, "llr")

@@ -362,8 +362,9 @@ def test_failure_injection_and_edge_cases(sched):
 def test_group_barrier_time_out_reports_every_frame_failed():
     """Forced from the host: with a zero wait bound, a group barrier that is not
     complete when a workgroup arrives gives up at once; the launch still ends and
-    every frame of that decode is reported with ok = 0.  With the default bound
-    restored the next decode equals the persistent decoder's."""
+    every frame of that decode is reported abandoned (iters = -1, ok = 0), which
+    the binding turns into an error.  With the default bound restored the next
+    decode equals the persistent decoder's."""
     print("[decode group barrier time-out]", flush=True)
     n, F = 16384, 12
     qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=321)
@@ -376,7 +377,11 @@ def test_group_barrier_time_out_reports_every_frame_failed():
     finally:
         api.debug_group_wait_ticks()
     assert (failed["ok"] == 0).all()
+    assert (failed["iters"] == -1).all()
+    with pytest.raises(api._lib.CvrError, match="abandoned"):
+        api.check_abandoned({k: torch.from_numpy(v) for k, v in failed.items()})
     good = _decode_gpu(code, F, L, syn, p)
+    assert (good["iters"] >= 0).all()
     ref = _decode_gpu(code, F, L, syn, api.Params(algo=api.SP, max_iter=30, early_stop=False, math=api.F32,
                                                   store=api.F32, schedule=api.SCHED_PERSISTENT))
     for k in ("bits", "post", "iters", "ok"):
