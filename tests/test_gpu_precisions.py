@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from paper_2108_08418_amd import api, inputs
-from tests._parity import compare_trace, has_margin
+from tests._parity import LayerIndex, compare_trace, flood_half_step_bound, has_margin, layered_half_step_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -85,28 +85,40 @@ def _after(code, qc, p, llr1, syn1, t):
 def _one_step_parity(qc, p, llr, syn, layered, T, algo):
     """From the decoder's own state after t iterations (t < T), one iteration of
     the fp64 oracle with binary16 storage emulated: the decoder's posteriors
-    after t + 1 iterations within 2 binary16 units of the scale, and every
-    stored message equal to the oracle's or its binary16 neighbour."""
+    and stored messages after t + 1 iterations lie within the forward error
+    bound of one binary32 iteration with binary16 messages from that state
+    (tests/_parity.py), computed from the oracle's values.  The bound is a few
+    binary16 units of the scale at most places: a stored message may round to
+    the other binary16 neighbour in one precision, and the binary32 rounding
+    of the posterior enters the next check rule; on the layered schedule,
+    later layers of the iteration also read what earlier ones wrote."""
     csr = qc.to_csr()
     code = api.Code.from_qc(qc)
     lay = oracle.qc_layers(qc.mb, qc.Z)
+    lix = LayerIndex(csr, lay if layered else np.array([0, csr.m], dtype=np.int32))
     kw = dict(algo=algo, store_half=True, alpha=float(np.float32(p.alpha)))
+    wedge = np.full(csr.n_edges, float(np.float32(p.alpha)))
     worst_post = worst_msg = 0.0
+    tight = []
     for f in range(llr.shape[0]):
         l64 = llr[f].astype(np.float32).astype(np.float64)
         post, c2v = _after(code, qc, p, llr[f], syn[f], 0)
         for t in range(T):
             if layered:
                 c_o, p_o = oracle.layered_step(csr, l64, syn[f], c2v, post, t, layers=lay, **kw)
+                E, B = layered_half_step_bound(lix, l64, c2v, post, c_o, wedge, algo)
             else:
                 c_o, p_o = oracle.flood_step(csr, l64, syn[f], c2v, t, **kw)
-            post, c2v = _after(code, qc, p, llr[f], syn[f], t + 1)
+                E, B = flood_half_step_bound(lix, l64, c2v, post, c_o, wedge, algo)
             sc = np.abs(l64).copy()
             np.add.at(sc, csr.col_idx, np.abs(c_o))
-            worst_post = max(worst_post, float(np.max(np.abs(post - p_o) / _half_units(sc, 2.0))))
-            worst_msg = max(worst_msg, float(np.max(np.abs(c2v - c_o) / _half_units(c_o, 1.0))))
-    assert worst_post <= 1.0, f"posterior deviation {worst_post:.3g} x (2 binary16 units of the scale)"
-    assert worst_msg <= 1.0, f"message deviation {worst_msg:.3g} x (1 binary16 unit)"
+            tight.append(float(np.median(E / _half_units(sc, 1.0))))
+            post, c2v = _after(code, qc, p, llr[f], syn[f], t + 1)
+            worst_post = max(worst_post, float(np.max(np.abs(post - p_o) / E)))
+            worst_msg = max(worst_msg, float(np.max(np.abs(c2v - c_o) / B)))
+    assert worst_post <= 1.0, f"posterior deviation {worst_post:.3g} x its bound"
+    assert worst_msg <= 1.0, f"message deviation {worst_msg:.3g} x its bound"
+    assert max(tight) < 4.0, f"bound too loose to test anything: median {max(tight):.3g} binary16 units"
 
 
 def _decisions_on_margin_frames(csr, res, ref, F, syn, rel=2.0 ** -4, min_margin=0.5):
@@ -161,7 +173,10 @@ def test_sp_f16_storage_against_fp64_oracle():
     _one_step_parity(qc, p, llr[:3], syn[:3], False, 12, oracle.SP)
     res = _decode(api.Code.from_qc(qc), F, llr, syn, p)
     ref = oracle.decode(csr, llr, syn, algo=oracle.SP, max_iter=30, trace=True, store_half=True)
-    _decisions_on_margin_frames(csr, res, ref, F, syn)
+    # over whole decodes the oracle's binary32 mode (the decoder's arithmetic)
+    # stays within 2^-9.5 of the scale of the fp64 mode on these frames: a
+    # margin of 2^-6 leaves 8x room
+    _decisions_on_margin_frames(csr, res, ref, F, syn, rel=2.0 ** -6)
 
 
 @pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_PASSES, api.SCHED_LAYERED])
@@ -174,12 +189,13 @@ def test_nms_f64_math_against_fp64_oracle(sched):
     F = 6
     llr, syn = _frames(qc, F, seed=45)
     p = api.Params(algo=api.NMS, max_iter=30, math=api.F64, store=api.F64, alpha=0.8, schedule=sched)
+    a32 = float(np.float32(0.8))      # the ABI carries alpha as binary32
     res = _decode(api.Code.from_qc(qc), F, llr, syn, p)
     if sched == api.SCHED_LAYERED:
         ref = oracle.decode_layered(csr, llr, syn, layers=oracle.qc_layers(qc.mb, qc.Z), algo=oracle.NMS,
-                                    alpha=0.8, max_iter=30, trace=True)
+                                    alpha=a32, max_iter=30, trace=True)
     else:
-        ref = oracle.decode(csr, llr, syn, algo=oracle.NMS, alpha=0.8, max_iter=30, trace=True)
+        ref = oracle.decode(csr, llr, syn, algo=oracle.NMS, alpha=a32, max_iter=30, trace=True)
     margin, worst = 0, 0.0
     for f in range(F):
         t_o, t_g = int(ref["iters"][f]), int(res["iters"][f])
