@@ -313,6 +313,25 @@ cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_params* params,
                              void* llr_post_out, int32_t* iters_out, uint8_t* ok_out,
                              void* workspace, size_t ws_bytes, void* stream);
 
+/* The same decode for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument; the workspace is a static device array of
+ * CVR_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends.  Calls no hipMalloc / hipFree (the batch and codes are
+ * created beforehand, as for ldpc_decode_batch).  Same arguments, outputs and
+ * results as ldpc_decode_batch.  A batch whose cvr_decode_workspace_size
+ * exceeds CVR_NOALLOC_SCRATCH_BYTES returns CVR_ENOMEM before anything is
+ * enqueued.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, or two host threads, without ordering
+ * between them) race and give undefined results; calls in one stream are
+ * ordered and safe.  Each call reinitialises what the decode reads from the
+ * array, so no clearing is needed between calls.                           */
+#define CVR_NOALLOC_SCRATCH_BYTES (64u << 20)
+cvr_status ldpc_decode_batch_noalloc(cvr_batch_t batch, const cvr_decode_params* params,
+                                     const void* llr, const uint8_t* syndrome, uint8_t* bits_out,
+                                     void* llr_post_out, int32_t* iters_out, uint8_t* ok_out,
+                                     void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Differentiable unrolled normalized min-sum (learning per-iteration,        */
 /* per-edge-type scales)                                                      */

@@ -51,6 +51,7 @@ SIGNATURES = {
     "cvr_batch_destroy": ([_P], C.c_int),
     "cvr_decode_workspace_size": ([_P, _P, _P], C.c_int),
     "ldpc_decode_batch": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int),
+    "ldpc_decode_batch_noalloc": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
     "nms_unrolled_sizes": ([_P, _I32, _I32, _P, _P, _P], C.c_int),
     "nms_unrolled_fwd": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int),
     "nms_unrolled_bwd": ([_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P], C.c_int),

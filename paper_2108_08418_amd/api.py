@@ -369,6 +369,38 @@ def ldpc_decode_batch(batch: Batch, params: Params, llr: torch.Tensor, syndrome:
     return out
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20      # the library's static decode workspace per GPU
+
+
+def ldpc_decode_batch_noalloc(batch: Batch, params: Params, llr: torch.Tensor, syndrome: torch.Tensor | None,
+                              out: dict, trace: torch.Tensor | None = None, stream=None) -> dict:
+    """ldpc_decode_batch with the library's static workspace: the caller passes
+    preallocated outputs (dict of bits, post or None, iters, ok) and nothing is
+    allocated.  Calls that overlap on one GPU race (they share the array)."""
+    mdt = _TORCH_OF[params.math]
+    if llr.dtype != mdt or llr.numel() < batch.total_n:
+        raise ValueError(f"llr must be {mdt} with >= total_n entries")
+    if syndrome is not None and (syndrome.dtype != torch.uint8 or syndrome.numel() < batch.total_m):
+        raise ValueError("syndrome must be uint8 with >= total_m entries")
+    if out["bits"].dtype != torch.uint8 or out["bits"].numel() < batch.total_n:
+        raise ValueError("out['bits'] must be uint8 with >= total_n entries")
+    if out.get("post") is not None and (out["post"].dtype != mdt or out["post"].numel() < batch.total_n):
+        raise ValueError(f"out['post'] must be {mdt} with >= total_n entries")
+    if out["iters"].dtype != torch.int32 or out["iters"].numel() < batch.F:
+        raise ValueError("out['iters'] must be int32 with >= F entries")
+    if out["ok"].dtype != torch.uint8 or out["ok"].numel() < batch.F:
+        raise ValueError("out['ok'] must be uint8 with >= F entries")
+    if trace is not None and (trace.dtype != mdt or trace.numel() < (params.max_iter + 1) * batch.total_n):
+        raise ValueError("trace must have (max_iter + 1) * total_n entries of the math dtype")
+    if params.weights is not None:
+        _check_weights(params.weights, params.max_iter, batch.n_types, "ldpc_decode_batch_noalloc")
+    p = params.c_struct(trace)
+    check(load().ldpc_decode_batch_noalloc(batch.handle, C.byref(p), _ptr(llr), _ptr(syndrome), _ptr(out["bits"]),
+                                           _ptr(out.get("post")), _ptr(out["iters"]), _ptr(out["ok"]),
+                                           _stream(stream)), "ldpc_decode_batch_noalloc")
+    return out
+
+
 def check_abandoned(out: dict) -> None:
     """Raises CvrError(CVR_EHIP) when the decode that wrote ``out`` was abandoned
     (iters = -1: a barrier of the group schedule gave up because its workgroups

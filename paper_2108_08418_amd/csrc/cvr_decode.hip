@@ -23,6 +23,7 @@
 #include "cvr_decode_impl.h"
 
 #include <atomic>
+#include <mutex>
 
 namespace cvr {
 
@@ -219,6 +220,57 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
     if (params->store == CVR_F32)
         return sp ? decode_f32_sp(batch, a, s, qc, mode, queue, gridws, sh) : decode_f32_nms(batch, a, s, qc, mode, queue, gridws, sh);
     return sp ? decode_f16_sp(batch, a, s, qc, mode, queue, gridws, sh) : decode_f16_nms(batch, a, s, qc, mode, queue, gridws, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Decoding without allocation: the workspace is a static device array
+// ---------------------------------------------------------------------------
+// Every GPU the library runs on holds its own copy of `scratch` until the
+// process ends.  Host code never names the array as an address (on the host
+// it is only a stand-in symbol): its device address is looked up once per
+// device, with that device current, and kept here.
+namespace cvr {
+static __device__ __align__(256) char scratch[CVR_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices];
+
+static cvr_status scratch_for_current_device(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(CVR_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(CVR_EUNSUPPORTED, "ldpc_decode_batch_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CVR_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CVR_OK;
+}
+}  // namespace cvr
+
+extern "C" cvr_status ldpc_decode_batch_noalloc(cvr_batch_t batch, const cvr_decode_params* params,
+                                                const void* llr, const uint8_t* syndrome, uint8_t* bits_out,
+                                                void* llr_post_out, int32_t* iters_out, uint8_t* ok_out,
+                                                void* stream)
+{
+    if (cvr_status st = check_params(batch, params)) return st;
+    if (batch->F == 0) return CVR_OK;
+    const size_t need = layout(batch, params).total;
+    if (need > size_t(CVR_NOALLOC_SCRATCH_BYTES))
+        return fail(CVR_ENOMEM, "ldpc_decode_batch_noalloc: the batch needs " + std::to_string(need) +
+                                    " bytes of workspace, more than the static " +
+                                    std::to_string(size_t(CVR_NOALLOC_SCRATCH_BYTES)) + "; use ldpc_decode_batch");
+    void* ws = nullptr;
+    if (cvr_status st = scratch_for_current_device(&ws)) return st;
+    return ldpc_decode_batch(batch, params, llr, syndrome, bits_out, llr_post_out, iters_out, ok_out, ws,
+                             size_t(CVR_NOALLOC_SCRATCH_BYTES), stream);
 }
 
 extern "C" cvr_status syndrome_check(cvr_code_t code, int32_t F, const uint8_t* bits, const uint8_t* syndrome,
