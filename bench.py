@@ -57,13 +57,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="recon-2^27-nR2^16", choices=sorted(WORKLOADS))
-    ap.add_argument("--decoder", default="sp", choices=["sp", "nms"])
+    ap.add_argument("--decoder", default="both", choices=["both", "sp", "nms"],
+                    help="both: learned min-sum (the headline) and plain sum-product, timed one after the other")
+    ap.add_argument("--sp-schedule", dest="sp_schedule", default="auto",
+                    choices=["auto", "passes", "persistent", "group", "layered"],
+                    help="schedule of the plain sum-product decoder in --decoder both")
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
                     "(weights/<prefix>_slice<j>.json per coded slice); iterations past their T reuse "
                     "the last learned row up to --max-iter")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent", "group"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent", "group", "layered"])
     ap.add_argument("--group-wgs", dest="group_wgs", type=int, default=0,
                     help="workgroups per frame of the group schedule (0 = auto)")
     ap.add_argument("--wg", type=int, default=0, help="persistent decoder workgroup size (0 = default)")
@@ -78,6 +82,11 @@ def parse():
                     help="block-size sweep: every recon-2^27 workload with SP and with learned min-sum "
                          "(--weights, default 'learned'); prints one JSON line per point")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (untimed)")
+    ap.add_argument("--no-rate-selection", action="store_true",
+                    help="use the stored rate table instead of running the Sec. V-B selection loop (untimed)")
+    ap.add_argument("--rate-frames", type=int, default=256, help="test sub-blocks of the rate-selection loop")
+    ap.add_argument("--fer-seeds", type=int, default=5,
+                    help="input seeds over which frame-error rates are counted (the timed one and more, untimed)")
     ap.add_argument("--llr-forms", action="store_true",
                     help="only time Alice's three LLR forms for slice 3 at 2^27 pairs (hard lower slices, "
                          "slice 2 as a soft prior, binary-symmetric hard LLR) and exit")
@@ -150,6 +159,17 @@ def frame_decode_bytes(iters, n, m, E, s_msg):
     return float((it * (2 * s_msg * E + 12 * n) + (it + 1) * m + 13 * n).sum())
 
 
+def layered_decode_bytes(iters, n, m, E, s_msg):
+    """Algorithmic bytes of a whole layered decode of frames that stopped at
+    ``iters``: per iteration every stored message is read and written once and,
+    since a block row updates the running posterior of each of its variables,
+    that posterior is read and written once per edge (2 s_msg E + 8 E); per
+    syndrome test m syndrome bytes (the decisions live on chip); set-up (L_ch
+    read, L written) and output bits 9 n."""
+    it = iters.astype(np.int64)
+    return float((it * (2 * s_msg * E + 8 * E) + (it + 1) * m + 9 * n).sum())
+
+
 def stage_bytes(iters, T, n, m, E, s_msg):
     """Algorithmic bytes of the check pass and of a full flooding iteration for
     frames that stopped at ``iters``.
@@ -171,7 +191,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
-                          "(frames shard across GPUs with no exchange, see the design notes)"}))
+                          "(sub-blocks shard across GPUs with no exchange; one GPU's share is what it measures)"}))
         sys.exit(2)
     import torch
 
@@ -199,6 +219,7 @@ def main():
             for dec, wts in (("sp", ""), ("nms", args.weights or "learned")):
                 a = copy.copy(args)
                 a.workload, a.decoder, a.weights, a.no_cpu_baseline = name, dec, wts, True
+                a.fer_seeds, a.no_rate_selection = 1, True
                 a.wg = a.min_waves = a.lds_cache_kb = 0
                 res = recon(a, WORKLOADS[name], dev)
                 print(json.dumps(res), flush=True)
@@ -268,8 +289,25 @@ def llr_forms(args, dev):
     return {"llr_forms": res, "n": N, "slice": 3, "bsc_p": p3, "steps": args.steps, "warmup": args.warmup}
 
 
+def _decoder_configs(args, api):
+    """(key, {coded slice: (algo, store, schedule name, weights prefix)}) of the
+    decoders one run times.  --decoder both (default): plain sum-product (the
+    headline: the paper's belief propagation), learned min-sum on both coded
+    slices, and the mixed pipeline (learned min-sum on slice 2, sum-product on
+    slice 3)."""
+    sp = (api.SP, api.F32, args.sp_schedule if args.decoder == "both" else args.schedule, "")
+    nms = (api.NMS, api.F16, args.schedule, args.weights or ("learned" if args.decoder == "both" else ""))
+    if args.decoder == "both":
+        return [("sp", {2: sp, 3: sp}), ("nms", {2: nms, 3: nms}), ("mixed", {2: nms, 3: sp})]
+    if args.decoder == "sp":
+        return [("sp", {2: sp, 3: sp})]
+    return [("nms", {2: nms, 3: nms})]
+
+
 def recon(args, wl, dev):
     """The slice-reconciliation step on N pairs in sub-blocks of n; returns the result dict."""
+    from dataclasses import replace
+
     import torch
 
     from paper_2108_08418_amd import api, inputs
@@ -280,34 +318,29 @@ def recon(args, wl, dev):
     th = inputs.equiprobable_thresholds(M_BITS, 1.0 + 1.0 / SNR)
     print(f"# workload {args.workload}: N={N} n={n} F={F} decoder={args.decoder}", file=sys.stderr, flush=True)
 
-    # ---- inputs (untimed) ----
+    # ---- inputs and codes (untimed) ----
     t0 = time.time()
+    rate_sel = None
+    if not args.no_rate_selection:
+        # the Sec. V-B loop on its own seeded test sub-blocks of 2^16 (untimed);
+        # the codes the step decodes are the ones it selects
+        from paper_2108_08418_amd import rates
+        rate_sel = {}
+        for j in (2, 3):
+            r = rates.select_slice_rate(j, 1 << 16, frames=args.rate_frames)
+            if r["selected"] is None:
+                raise SystemExit(f"rate selection found no passing code for slice {j}")
+            rate_sel[j] = r
+        mbs = {j: rate_sel[j]["selected"]["mb"] for j in (2, 3)}
+        print(f"# rate selection: {mbs} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    else:
+        mbs = dict(inputs.SLICE_MB)
     x_np, y_np = inputs.gaussian_pairs(N, SNR, seed=args.seed)
     x = torch.from_numpy(x_np).to(dev)
     y = torch.from_numpy(y_np).to(dev)
-    qcs = {j: inputs.slice_code_spec(j, n) for j in (2, 3)}
+    qcs = {j: inputs.slice_code_at(j, n, mbs[j]) for j in (2, 3)}
     codes = {j: api.Code.from_qc(qcs[j]) for j in (2, 3)}
     batches = {j: api.Batch.uniform(codes[j], F) for j in (2, 3)}
-    algo = api.SP if args.decoder == "sp" else api.NMS
-    store = api.F32 if args.decoder == "sp" else api.F16
-    sched = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT,
-             "group": api.SCHED_GROUP}[args.schedule]
-    params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        schedule=sched, wg_threads=args.wg, min_waves=args.min_waves,
-                        lds_cache_kb=args.lds_cache_kb, group_wgs=args.group_wgs)
-    stage_params = {2: params, 3: params}
-    if args.weights:
-        if algo != api.NMS:
-            raise SystemExit("--weights needs --decoder nms")
-        from dataclasses import replace
-
-        from paper_2108_08418_amd.train import load_weights
-        stage_params = {}
-        for j in (2, 3):
-            w = load_weights(f"{args.weights}_slice{j}", extend_to=args.max_iter)
-            stage_params[j] = replace(params, max_iter=int(w.shape[0]), weights=torch.from_numpy(w).to(dev))
-    ws_bytes = max(api.decode_workspace_size(batches[j], stage_params[j]) for j in (2, 3))
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     bob = torch.empty((M_BITS, N), dtype=torch.uint8, device=dev)
     alice = torch.empty((M_BITS, N), dtype=torch.uint8, device=dev)
     syn = {j: torch.empty(F * codes[j].m, dtype=torch.uint8, device=dev) for j in (2, 3)}
@@ -315,6 +348,31 @@ def recon(args, wl, dev):
     llr3 = (torch.empty(N, dtype=torch.float32, device=dev), torch.empty(N, dtype=torch.float32, device=dev))
     outs = {j: dict(bits=alice[j], post=None, iters=torch.empty(F, dtype=torch.int32, device=dev),
                     ok=torch.empty(F, dtype=torch.uint8, device=dev)) for j in (2, 3)}
+    sched_of = {"auto": api.SCHED_AUTO, "passes": api.SCHED_PASSES, "persistent": api.SCHED_PERSISTENT,
+                "group": api.SCHED_GROUP, "layered": api.SCHED_LAYERED}
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+
+    decs = []
+    for key, spec in _decoder_configs(args, api):
+        stage_params = {}
+        for j in (2, 3):
+            algo, store, sched_name, wts = spec[j]
+            stage_params[j] = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store,
+                                         alpha=args.alpha, schedule=sched_of[sched_name], wg_threads=args.wg,
+                                         min_waves=args.min_waves, lds_cache_kb=args.lds_cache_kb,
+                                         group_wgs=args.group_wgs)
+            if wts:
+                from paper_2108_08418_amd.train import load_weights, weights_meta
+                meta = weights_meta(f"{wts}_slice{j}")
+                if meta.get("mb") not in (None, mbs[j]):
+                    raise SystemExit(f"weights {wts}_slice{j} were trained for mb = {meta['mb']}, "
+                                     f"the slice-{j} code has mb = {mbs[j]}")
+                w = load_weights(f"{wts}_slice{j}", extend_to=args.max_iter)
+                stage_params[j] = replace(stage_params[j], max_iter=int(w.shape[0]),
+                                          weights=torch.from_numpy(w).to(dev))
+        decs.append(dict(key=key, spec=spec, stage_params=stage_params))
+    ws_bytes = max(api.decode_workspace_size(batches[j], d["stage_params"][j]) for d in decs for j in (2, 3))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     print(f"# inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
@@ -322,71 +380,164 @@ def recon(args, wl, dev):
     # beside Alice's fp64-bound LLR pass; the decoders wait for both.
     side = torch.cuda.Stream(device=dev)
 
-    def step():
-        main = torch.cuda.current_stream()
-        api.slice_quantize(y, th, M_BITS, out=bob)                                    # Bob: M(.) and slices
-        side.wait_stream(main)
-        for j in (2, 3):                                                                # Bob: syndromes
-            api.syndrome_check(codes[j], bob[j], want_unsat=False, out_syndrome=syn[j], stream=side)
-        alice[0:2].copy_(bob[0:2])                                                     # disclosed slices
-        # Alice: slice 2, and in the same pass slice 3 for either value of slice 2
-        api.slice_llr_next(x, sig, th, M_BITS, 2, 0b11, alice, out=(llr, *llr3))
-        main.wait_stream(side)
-        api.ldpc_decode_batch(batches[2], stage_params[2], llr, syn[2], workspace=ws, out=outs[2])
-        api.slice_llr_choose(llr3[0], llr3[1], alice[2], out=llr)                      # slice 3 given decoded slice 2
-        api.ldpc_decode_batch(batches[3], stage_params[3], llr, syn[3], workspace=ws, out=outs[3])
+    def make_step(stage_params, xs, ys):
+        def step():
+            main = torch.cuda.current_stream()
+            api.slice_quantize(ys, th, M_BITS, out=bob)                                   # Bob: M(.) and slices
+            side.wait_stream(main)
+            for j in (2, 3):                                                               # Bob: syndromes
+                api.syndrome_check(codes[j], bob[j], want_unsat=False, out_syndrome=syn[j], stream=side)
+            alice[0:2].copy_(bob[0:2])                                                    # disclosed slices
+            # Alice: slice 2, and in the same pass slice 3 for either value of slice 2
+            api.slice_llr_next(xs, sig, th, M_BITS, 2, 0b11, alice, out=(llr, *llr3))
+            main.wait_stream(side)
+            api.ldpc_decode_batch(batches[2], stage_params[2], llr, syn[2], workspace=ws, out=outs[2])
+            api.slice_llr_choose(llr3[0], llr3[1], alice[2], out=llr)                     # slice 3 given decoded slice 2
+            api.ldpc_decode_batch(batches[3], stage_params[3], llr, syn[3], workspace=ws, out=outs[3])
+        return step
 
-    tuned = None
-    cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    persistent = args.schedule == "persistent" or (args.schedule == "auto" and batches[2].F >= cus)
-    group = args.schedule == "group" or (args.schedule == "auto" and batches[2].F < cus)
-    if not args.no_tune and ((persistent and args.wg == 0) or (group and args.min_waves == 0 and args.group_wgs == 0)):
-        # pick the launch shape on this workload's own slice-2 decode (untimed)
-        step()
-        api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
-        from paper_2108_08418_amd import tune
-        knobs = tune.KNOBS if persistent else tune.GROUP_KNOBS
-        best, tim = tune.tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2],
-                                     candidates=tune.CANDIDATES if persistent else tune.GROUP_CANDIDATES, knobs=knobs)
-        for pp in {id(v): v for v in (params, *stage_params.values())}.values():
-            for k, v in zip(knobs, best):
-                setattr(pp, k, v)
-        for k, v in zip(knobs, best):
-            setattr(args, "wg" if k == "wg_threads" else k, v)
-        tuned = {"/".join(f"{k}={v}" for k, v in zip(knobs, c)): round(t, 3) for c, t in tim.items()}
-        print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print("# warmup done", file=sys.stderr, flush=True)
-    api.profile_enable(True)
-    for k in range(8):
-        api.profile_read(k, reset=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    api.profile_enable(False)
-    prof = {name: api.profile_read(k, reset=True) for k, name in enumerate(
-        ["quantize", "slice_llr", "syndrome", "check", "var", "dec_setup", "decode_persistent", "adjoint"])}
-    ms_step = 1e3 * t_total / args.steps
-    decoded_bits = 2 * N
-    value = decoded_bits / (t_total / args.steps)
+    def counts():
+        """Failures and bit errors of the last step, per coded slice."""
+        for j in (2, 3):
+            api.check_abandoned(outs[j])
+        r = {}
+        for j in (2, 3):
+            okj = outs[j]["ok"].cpu().numpy()
+            r[j] = dict(iters=outs[j]["iters"].cpu().numpy(), ok=okj,
+                        bit_errors=int((alice[j] != bob[j]).sum().item()))
+        return r
 
-    # ---- correctness summary of the last step ----
-    for j in (2, 3):
-        api.check_abandoned(outs[j])
-    iters = {j: outs[j]["iters"].cpu().numpy() for j in (2, 3)}
-    ok = {j: outs[j]["ok"].cpu().numpy() for j in (2, 3)}
-    bit_err = {j: int((alice[j] != bob[j]).sum().item()) for j in (2, 3)}
+    results = {}
+    for d in decs:
+        stage_params = d["stage_params"]
+        step = make_step(stage_params, x, y)
+        sched = stage_params[2].schedule
+        layered = sched == api.SCHED_LAYERED
+        persistent = sched == api.SCHED_PERSISTENT or (sched == api.SCHED_AUTO and F >= cus)
+        group = sched == api.SCHED_GROUP or (sched == api.SCHED_AUTO and F < cus)
+        tuned = None
+        if not args.no_tune and ((persistent and args.wg == 0) or (layered and args.wg == 0)
+                                 or (group and args.min_waves == 0 and args.group_wgs == 0)):
+            # pick the launch shape per coded slice on this workload's own decode (untimed)
+            step()
+            from paper_2108_08418_amd import tune
+            knobs, cands = ((tune.LAYERED_KNOBS, tune.LAYERED_CANDIDATES) if layered else
+                            (tune.KNOBS, tune.CANDIDATES) if persistent else (tune.GROUP_KNOBS, tune.GROUP_CANDIDATES))
+            tuned = {}
+            for j in (2, 3):
+                if j == 2:
+                    api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
+                else:
+                    api.slice_llr(x, sig, th, M_BITS, 3, 0b111, alice, out=llr)
+                best, tim = tune.tune_decode(batches[j], stage_params[j], llr, syn[j], ws, outs[j],
+                                             candidates=cands, knobs=knobs)
+                for k, v in zip(knobs, best):
+                    setattr(stage_params[j], k, v)
+                tuned[str(j)] = {"/".join(f"{k}={v}" for k, v in zip(knobs, c)): round(t, 3) for c, t in tim.items()}
+            print(f"# {d['key']} tuned: {[tuple(getattr(stage_params[j], k) for k in knobs) for j in (2, 3)]}",
+                  file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        api.profile_enable(True)
+        for k in range(8):
+            api.profile_read(k, reset=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        api.profile_enable(False)
+        prof = {name: api.profile_read(k, reset=True) for k, name in enumerate(
+            ["quantize", "slice_llr", "syndrome", "check", "var", "dec_setup", "decode_persistent", "adjoint"])}
+        c = counts()
+        # each coded slice's decode alone (untimed step; the same inputs: slice 2
+        # from the disclosed slices, slice 3 given the decoded slice 2)
+        per_slice = {}
+        for j in (2, 3):
+            api.slice_llr(x, sig, th, M_BITS, j, (1 << j) - 1, alice, out=llr)
+            saved = outs[j]["bits"].clone()
+            torch.cuda.synchronize()
+            api.profile_enable(True)
+            api.profile_read(api.PROF_FRAMES, reset=True)
+            api.profile_read(api.PROF_CHECK, reset=True)
+            api.profile_read(api.PROF_VAR, reset=True)
+            for _ in range(3):
+                api.ldpc_decode_batch(batches[j], stage_params[j], llr, syn[j], workspace=ws, out=outs[j])
+            torch.cuda.synchronize()
+            api.profile_enable(False)
+            ms = sum(api.profile_read(k, reset=True)[0] for k in (api.PROF_FRAMES, api.PROF_CHECK, api.PROF_VAR))
+            per_slice[str(j)] = ms / 3
+            outs[j]["bits"].copy_(saved)
+        res = summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, persistent, group, layered)
+        res["decode_ms_per_slice"] = per_slice
+        res["autotune_ms_per_decode"] = tuned
+        results[d["key"]] = res
+        print(f"# {d['key']}: {res['ms_per_step']:.2f} ms/step, {res['value']:.3e} bits/s", file=sys.stderr, flush=True)
+
+    # ---- frame-error rates over more seeds (untimed) ----
+    fer = {d["key"]: {j: [0, 0] for j in (2, 3)} for d in decs}
+    for d in decs:
+        for j in (2, 3):
+            okj = results[d["key"]]["_counts"][j]["ok"]
+            fer[d["key"]][j] = [int((okj == 0).sum()), int(okj.size)]
+    for s in range(1, args.fer_seeds):
+        xs_np, ys_np = inputs.gaussian_pairs(N, SNR, seed=args.seed + 7919 * s)
+        xs = torch.from_numpy(xs_np).to(dev)
+        ys = torch.from_numpy(ys_np).to(dev)
+        del xs_np, ys_np
+        for d in decs:
+            make_step(d["stage_params"], xs, ys)()
+            torch.cuda.synchronize()
+            c = counts()
+            for j in (2, 3):
+                fer[d["key"]][j][0] += int((c[j]["ok"] == 0).sum())
+                fer[d["key"]][j][1] += int(c[j]["ok"].size)
+        del xs, ys
+        print(f"# FER seed {s}: {fer}", file=sys.stderr, flush=True)
+    for d in decs:
+        r = results[d["key"]]
+        r.pop("_counts")
+        r["fer_frames"] = {str(j): {"failures": fer[d["key"]][j][0], "frames": fer[d["key"]][j][1],
+                                    "fer": fer[d["key"]][j][0] / fer[d["key"]][j][1],
+                                    "wilson95": wilson95(*fer[d["key"]][j])} for j in (2, 3)}
+
+    head = results[decs[0]["key"]]
+    result = dict(head)
+    result["config"]["rate_selection"] = (
+        {str(j): {"capacity": round(rate_sel[j]["capacity"], 4), "test_sub_blocks": args.rate_frames,
+                  "trail": [{k: c[k] for k in ("rate", "mb", "failures", "mean_iters")} for c in rate_sel[j]["trail"]]}
+         for j in (2, 3)} if rate_sel else "fixed table (inputs.SLICE_MB)")
+    others = {}
+    for d in decs[1:]:
+        r = results[d["key"]]
+        same = {}
+        for j in (2, 3):
+            lo, hi = head["fer_frames"][str(j)]["wilson95"]
+            same[str(j)] = bool(lo <= r["fer_frames"][str(j)]["fer"] <= hi)
+        others[d["key"]] = {
+            **{k: r[k] for k in ("value", "ms_per_step", "dtype", "roofline", "decode_iteration",
+                                 "decode_ms_per_slice", "kernel_ms_per_step", "mean_iters", "fer_frames",
+                                 "bit_errors_vs_bob", "autotune_ms_per_decode")},
+            "config": {k: r["config"][k] for k in ("decoder", "max_iter", "schedule", "launch_shape")},
+            "bits_per_s_vs_sp": r["value"] / head["value"],
+            "decoder_speedup_vs_sp_per_slice": {
+                str(j): head["decode_ms_per_slice"][str(j)] / r["decode_ms_per_slice"][str(j)] for j in (2, 3)},
+            "same_fer_as_sp": same,
+        }
+    if others:
+        result["learned_min_sum"] = others
+        result["learned_min_sum_rule"] = (
+            "nms: learned min-sum on both coded slices; mixed: learned min-sum on slice 2 and sum-product on "
+            "slice 3.  same_fer_as_sp: the FER over fer_frames lies inside sum-product's 95 % Wilson interval")
     # the Gaussian-approximation iteration count (host model) beside the measured
     # mean: a binary-input AWGN channel carrying the capacity that Alice's LLRs
     # (given Bob's true lower slices) carry about Bob's bits, the code's own
     # degree distributions, target bit error ratio 1/n
     from paper_2108_08418_amd import ga
     ga_pred = {}
+    api.slice_quantize(y, th, M_BITS, out=bob)
     for j in (2, 3):
         api.slice_llr(x, sig, th, M_BITS, j, (1 << j) - 1, bob, out=llr)
         sgn = 1.0 - 2.0 * bob[j].to(torch.float64)
@@ -396,43 +547,73 @@ def recon(args, wl, dev):
         m0 = ga.biawgn_mean_for_capacity(cap)
         ga_pred[str(j)] = {"capacity": round(cap, 4), "m0": round(m0, 4),
                            "iters_to_ber_1_over_n": ga.iterations_to(1.0 / n, m0, lam, rho)}
-    s_msg = 4 if store == api.F32 else 2
-    chk_bytes = 0.0
-    iter_bytes = 0.0
-    dec_bytes = 0.0
+    result["ga_iterations"] = ga_pred
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args, x_np, y_np, qcs, th, sig, n, decs[0])
+    return result
+
+
+def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, persistent, group, layered):
+    """Result dict of one decoder's timed steps."""
+    from paper_2108_08418_amd import api
+    spec = d["spec"]
+    algo, store, _, wts = spec[2]
+    uniform = spec[2] == spec[3]
+    ms_step = 1e3 * t_total / args.steps
+    value = 2 * N / (t_total / args.steps)
+    iters = {j: c[j]["iters"] for j in (2, 3)}
+    ok = {j: c[j]["ok"] for j in (2, 3)}
+    chk_bytes = iter_bytes = dec_bytes = 0.0
     edge_updates = 0
     for j in (2, 3):
+        s_msg = 4 if spec[j][1] == api.F32 else 2
         cb, ib = stage_bytes(iters[j], stage_params[j].max_iter, n, codes[j].m, codes[j].n_edges, s_msg)
         chk_bytes += cb
         iter_bytes += ib
-        dec_bytes += frame_decode_bytes(iters[j], n, codes[j].m, codes[j].n_edges, s_msg)
+        dec_bytes += (layered_decode_bytes if layered else frame_decode_bytes)(
+            iters[j], n, codes[j].m, codes[j].n_edges, s_msg)
         edge_updates += int(iters[j].astype(np.int64).sum()) * codes[j].n_edges
     chk_ms, chk_n = prof["check"]
     var_ms, var_n = prof["var"]
     per_ms, per_n = prof["decode_persistent"]
     dom = max(("check", "var", "slice_llr", "decode_persistent"), key=lambda k: prof[k][0])
     traffic = traffic_src = None
-    if per_ms > 0:
-        wg = args.wg or 512
+    shape = {j: (stage_params[j].wg_threads, stage_params[j].min_waves, stage_params[j].lds_cache_kb,
+                 stage_params[j].group_wgs) for j in (2, 3)}
+    if per_ms > 0 and not uniform:
+        roof_kernel = "per coded slice: " + ", ".join(
+            f"slice {j} {'sum-product' if spec[j][0] == api.SP else 'min-sum'}" for j in (2, 3))
+        achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
+        launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
+        iter_gbs = achieved
+    elif per_ms > 0:
+        wg, mw, lk, _ = shape[2]
+        wg = wg or 512
         mt = "float, float" if store == api.F32 else "float, __half"
-        if persistent:
-            inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
-                    f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
+        a = 0 if algo == api.SP else 1
+        if layered:
+            inst = f"void cvr::k_layered_qc<{mt}, {a}, 8, {wg}, true>"
+        elif persistent:
+            inst = (f"void cvr::k_frames_qc<{mt}, {a}, 8, {wg}, true, {8 if mw == 8 else 1}, "
+                    f"{'false' if lk < 0 else 'true'}>")
         else:                                   # group schedule (workgroups per frame on one XCD)
-            inst = f"void cvr::k_group_qc<{mt}, {0 if algo == api.SP else 1}, 8, 1024, true, {8 if args.min_waves == 8 else 1}>"
+            inst = f"void cvr::k_group_qc<{mt}, {a}, 8, 1024, true, {8 if mw == 8 else 1}>"
         roof_kernel = inst
         achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
         iter_gbs = achieved
-        traffic, traffic_src = recorded_traffic(inst, args.workload, args.decoder, args.weights)
+        if shape[2] == shape[3]:
+            traffic, traffic_src = recorded_traffic(inst, args.workload, d["key"], wts)
     else:
         roof_kernel = "decoder check-node pass (k_check_qc)"
         achieved = (args.steps * chk_bytes) / (chk_ms * 1e-3) / 1e9 if chk_ms > 0 else None
         launches, launch_ms, launch_bytes = chk_n, chk_ms, args.steps * chk_bytes
         iter_gbs = (args.steps * iter_bytes) / ((chk_ms + var_ms) * 1e-3) / 1e9 if chk_ms + var_ms > 0 else None
-
-    result = {
-        "metric": "decoded bits/s (slice reconciliation, coded slices) and HBM GB/s of the decoder",
+    sched_name = {api.SCHED_AUTO: "auto", api.SCHED_PASSES: "passes", api.SCHED_PERSISTENT: "persistent",
+                  api.SCHED_GROUP: "group", api.SCHED_LAYERED: "layered"}[stage_params[2].schedule]
+    return {
+        "metric": "decoded bits/s (slice reconciliation, coded slices) and HBM GB/s of the decoder at fixed FER; "
+                  "learned min-sum vs plain sum-product",
         "value": value,
         "unit": "bits/s",
         "n_gpus": 1,
@@ -442,16 +623,19 @@ def recon(args, wl, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.decoder == "sp" else "f32 math / f16 messages",
+        "dtype": ("f32" if algo == api.SP else "f32 math / f16 messages") if uniform else
+                 "f32 (slice 3) and f32 math / f16 messages (slice 2)",
         "data": "synthetic: seeded Gaussian pairs, SNR 3, seeded QC-LDPC slice codes",
         "config": {
             "workload": args.workload, "pairs": N, "sub_block": n, "sub_blocks_per_slice": F,
             "slices": ("16 equiprobable Gray intervals; slices 0-1 disclosed, "
                        f"2 (R={1 - qcs[2].m / n:.4f}) and 3 (R={1 - qcs[3].m / n:.4f}) decoded"),
-            "decoder": ("sum-product" if algo == api.SP else
-                        (f"learned normalized min-sum ({args.weights})" if args.weights else
-                         f"normalized min-sum alpha={args.alpha}")),
-            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": args.schedule, "wg_threads": args.wg, "min_waves": args.min_waves, "lds_cache_kb": args.lds_cache_kb, "group_wgs": args.group_wgs,
+            "decoder": {str(j): ("sum-product" if spec[j][0] == api.SP else
+                                 (f"learned normalized min-sum ({spec[j][3]}_slice{j})" if spec[j][3] else
+                                  f"normalized min-sum alpha={args.alpha}")) for j in (2, 3)},
+            "max_iter": {str(j): stage_params[j].max_iter for j in (2, 3)}, "schedule": sched_name,
+            "launch_shape": {str(j): dict(zip(("wg_threads", "min_waves", "lds_cache_kb", "group_wgs"), shape[j]))
+                             for j in (2, 3)},
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -469,7 +653,7 @@ def recon(args, wl, dev):
             "algorithmic_bytes_per_launch": launch_bytes / launches if launches else None,
             "note": ("group schedule: the decoder state stays in the L2 / Infinity Cache (HBM traffic far "
                      "below the algorithmic bytes), so an iteration is bound by barrier and pass latency, "
-                     "not HBM" if (per_ms > 0 and not persistent) else None),
+                     "not HBM" if (per_ms > 0 and group and not layered) else None),
         },
         "paper_context": PAPER_CONTEXT,
         "decode_iteration": {
@@ -482,19 +666,12 @@ def recon(args, wl, dev):
             "decode_ms_per_step": (per_ms + chk_ms + var_ms) / args.steps,
         },
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof.items()},
-        "autotune_ms_per_decode": tuned,
         "dominant_kernel": dom,
-        "fer": {str(j): float(1.0 - ok[j].mean()) for j in (2, 3)},
-        "fer_wilson95": {str(j): wilson95(int((ok[j] == 0).sum()), len(ok[j])) for j in (2, 3)},
         "mean_iters": {str(j): float(iters[j].mean()) for j in (2, 3)},
-        "ga_iterations": ga_pred,
-        "bit_errors_vs_bob": bit_err,
+        "bit_errors_vs_bob": {str(j): c[j]["bit_errors"] for j in (2, 3)},
         "reconciled_pairs_per_s": N / (t_total / args.steps),
+        "_counts": c,
     }
-
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params)
-    return result
 
 
 def ragged(args, wl, dev):
@@ -702,15 +879,16 @@ def train_step(args, wl, dev):
     print(json.dumps(result))
 
 
-def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
+def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, dec):
     """The fp64 oracle on a bounded sample of the same workload (the first
-    ``cpu_frames`` sub-blocks of both coded slices), all host threads."""
+    ``cpu_frames`` sub-blocks of both coded slices) with the headline
+    decoder's rule and weights, all host threads."""
     import oracle
     Fs = min(args.cpu_frames, len(x_np) // n)
     Ns = Fs * n
     xs, ys = x_np[:Ns], y_np[:Ns]
     csr = {j: qcs[j].to_csr() for j in (2, 3)}
-    algo = oracle.SP if args.decoder == "sp" else oracle.NMS
+    from paper_2108_08418_amd import api
     t0 = time.perf_counter()
     edge_updates = 0
     S = oracle.quantize(ys, th, M_BITS)
@@ -719,7 +897,8 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
     A[0:2] = S[0:2]
     for j in (2, 3):
         L = oracle.slice_llr(xs, sig, th, M_BITS, oracle.GRAY, j, (1 << j) - 1, A)
-        sp = stage_params[j]
+        sp = dec["stage_params"][j]
+        algo = oracle.SP if sp.algo == api.SP else oracle.NMS
         w = None if sp.weights is None else sp.weights.cpu().numpy().astype(np.float64)
         r = oracle.decode(csr[j], L.reshape(Fs, n), syn[j], algo=algo, max_iter=sp.max_iter,
                           alpha=args.alpha, weights=w, store_half=(algo == oracle.NMS))
@@ -727,10 +906,12 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, stage_params):
         edge_updates += int(np.asarray(r["iters"]).astype(np.int64).sum()) * csr[j].n_edges
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rule = " / ".join("sum-product" if dec["stage_params"][j].algo == api.SP else
+                      "min-sum with the same weights and binary16 messages" for j in (2, 3))
     return {"value": 2 * Ns / dt, "unit": "bits/s", "cores": min(cores, os.cpu_count() or cores),
             "kind": "oracle", "seconds": dt, "edge_updates_per_s": edge_updates / dt,
             "sample": f"first {Fs} of the {len(x_np) // n} sub-blocks of {n} bits of both coded slices: fp64 "
-                      f"quantiser, syndromes, slice LLRs and decoding; decode threads across sub-blocks"}
+                      f"quantiser, syndromes, slice LLRs and flooding {rule}; decode threads across sub-blocks"}
 
 
 if __name__ == "__main__":

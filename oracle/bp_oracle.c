@@ -5,7 +5,7 @@
  * never does.  It shares no code, header or table with the HIP library.
  *
  * Conventions (the paper names the belief-propagation decoder but fixes no
- * variant; the readings taken here are listed in the design notes):
+ * variant; these are the readings taken here):
  *   - an LLR is ln P(bit = 0) / P(bit = 1); hard decision b = 1 iff L < 0;
  *   - sign(x) = -1 iff x < 0 (so -0.0 counts as +);
  *   - syndrome decoding: every check-to-variable message of check c is

@@ -24,7 +24,7 @@ from scipy.special import ndtri
 __all__ = [
     "CsrCode", "QcCode", "largest_remainder", "regular_code", "irregular_code",
     "qc_protograph_code", "gaussian_pairs", "bpsk_llr", "random_bits",
-    "equiprobable_thresholds", "LAMBDA_NODE_FRACTIONS", "slice_code_spec",
+    "equiprobable_thresholds", "LAMBDA_NODE_FRACTIONS", "slice_code_spec", "SLICE_MB",
     "met_low_rate_spec", "lambda_half_rate_spec", "slice_code_at",
 ]
 
@@ -319,17 +319,24 @@ def _lambda_qc_code(nb: int, mb: int, Z: int, seed: int, name: str) -> QcCode:
     return QcCode(nb, mb, Z, shift.astype(np.int32), btype, 3, name=name)
 
 
+# Block rows (of nb = 128) of the coded slices' codes, as the rate-selection
+# loop of Sec. V-B picks them (rates.select_slice_rate with 256 test
+# sub-blocks of n = 65536 on the GPU path): start 10 % below the slice
+# capacity and step down by 0.05 while a test sub-block fails.
+#   slice 2 (C = 0.3156): R = 0.2813 fails 256/256, 0.2344 fails 91/256,
+#                         0.1875 (mb = 104) fails none;
+#   slice 3 (C = 0.5468): R = 0.4922 (mb = 65) fails none.
+SLICE_MB = {2: 104, 3: 65}
+
+
 def slice_code_spec(slice_j: int, n: int, seed: int = 2108) -> QcCode:
     """Seeded QC code for coded slice ``slice_j`` (2 or 3) of the 16-level,
     4-slice setup at SNR 3: lambda(x) = 0.25x + 0.3x^2 + 0.45x^7 over nb = 128
-    block columns, degree-2 columns chained (see ``_chain_base_matrix``).
-
-    Rates follow the selection loop of Sec. V-B: start 10 % below the slice
-    capacity and step down by 0.05 while the code fails its frame-error test.
-    Slice 2 (C = 0.3153): 0.284 and 0.234 fail, 0.184 passes -> mb = 104,
-    R = 0.1875.  Slice 3 (C = 0.5469): 0.492 fails, 0.442 passes -> mb = 71,
-    R = 0.4453125.  Column permutation, row order and shifts are seeded."""
-    return slice_code_at(slice_j, n, {2: 104, 3: 71}[slice_j], seed)
+    block columns, degree-2 columns chained (see ``_chain_base_matrix``), at
+    the rate the selection loop picks (``SLICE_MB``): slice 2 R = 0.1875,
+    slice 3 R = 0.4921875.  Column permutation, row order and shifts are
+    seeded."""
+    return slice_code_at(slice_j, n, SLICE_MB[slice_j], seed)
 
 
 def slice_code_at(slice_j: int, n: int, mb: int, seed: int = 2108) -> QcCode:
@@ -360,7 +367,7 @@ def met_low_rate_spec(n: int, seed: int = 16) -> QcCode:
     spread evenly over the core.  Rate (16 - 12) / 64 = 0.0625.  Edge types:
     0 = core checks, 1 = extension checks to the core, 2 = degree-1 edges.
     Rates 5/64 and 6/64 of this family did not decode at SNR 0.16 (n = 16384),
-    4/64 did (no failure in 16 frames); see the design notes.  The protograph
+    4/64 did (no failure in 16 frames).  The protograph
     depends on ``seed`` only, the circulant shifts on (seed, Z).
     """
     nb, n_core, mc = 64, 16, 12

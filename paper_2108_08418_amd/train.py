@@ -50,11 +50,11 @@ class BpskFrames:
 
 
 class SliceFrames:
-    def __init__(self, j, n, F, snr, dev, m_bits=4):
+    def __init__(self, j, n, F, snr, dev, m_bits=4, mb=None):
         self.j, self.n, self.F, self.snr, self.dev, self.m = j, n, F, snr, dev, m_bits
         self.th = inputs.equiprobable_thresholds(m_bits, 1.0 + 1.0 / snr)
         self.sig = math.sqrt(1.0 / snr)
-        self.qc = inputs.slice_code_spec(j, n)
+        self.qc = inputs.slice_code_spec(j, n) if mb is None else inputs.slice_code_at(j, n, mb)
         self.code = api.Code.from_qc(self.qc)
 
     def batch(self, step):
@@ -99,6 +99,13 @@ def save(path, name, weights, meta):
                                     weights=np.asarray(weights, dtype=float).round(7).tolist(), **meta), indent=1))
 
 
+def weights_meta(name: str) -> dict:
+    """The stored record of a weight set without its weights (code, mb, training)."""
+    d = json.loads((WEIGHTS_DIR / f"{name}.json").read_text())
+    d.pop("weights", None)
+    return d
+
+
 def load_weights(name: str, extend_to: int | None = None) -> np.ndarray:
     """Weights [T, n_types] stored under ``weights/<name>.json``; with
     ``extend_to`` > T the last learned row is held for the extra iterations."""
@@ -113,6 +120,7 @@ def main():
     ap = argparse.ArgumentParser(description="learn normalized min-sum scales")
     ap.add_argument("--source", choices=["bpsk", "slice"], required=True)
     ap.add_argument("--slice", type=int, default=2)
+    ap.add_argument("--mb", type=int, default=0, help="block rows of the slice code (0 = the selected rate)")
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--frames", type=int, default=256)
     ap.add_argument("--T", type=int, default=20)
@@ -128,8 +136,8 @@ def main():
         fr = BpskFrames(inputs.lambda_half_rate_spec(a.n), a.frames, (1.5, 3.0), 0.5, dev)
         meta = dict(source="bpsk", code=fr.qc.name, ebn0_db=[1.5, 3.0])
     else:
-        fr = SliceFrames(a.slice, a.n, a.frames, 3.0, dev)
-        meta = dict(source="slice", code=fr.qc.name, slice=a.slice, snr=3.0)
+        fr = SliceFrames(a.slice, a.n, a.frames, 3.0, dev, mb=a.mb or None)
+        meta = dict(source="slice", code=fr.qc.name, slice=a.slice, snr=3.0, mb=int(fr.qc.mb), T_train=a.T)
     w, hist = train(fr, a.T, a.K, a.steps, a.lr, a.init, log=lambda s: print(s, flush=True))
     meta.update(frames=a.frames, n=a.n, steps=a.steps, lr=a.lr, init=a.init, ckpt_every=a.K, history=hist)
     save(a.out, a.name, w, meta)

@@ -4,7 +4,8 @@ Times ``ldpc_decode_batch`` for every candidate on the caller's own batch and
 inputs with HIP events on the launch stream (the library's launch timing) and
 returns the fastest.  Persistent schedule: (workgroup size, minimum waves per
 SIMD, LDS posterior cache); group schedule: (minimum waves per SIMD, which
-sets the workgroups per CU, and workgroups per frame).  The knobs change the
+sets the workgroups per CU, and workgroups per frame); layered schedule
+(workgroup size, LDS posterior cache).  The knobs change the
 launch configuration only, never the results.
 """
 from __future__ import annotations
@@ -18,6 +19,9 @@ KNOBS = ("wg_threads", "min_waves", "lds_cache_kb")
 # group_wgs: 0 = the workgroups an XCD holds divided by its frames
 GROUP_CANDIDATES = [(0, 0), (8, 0), (0, 8)]
 GROUP_KNOBS = ("min_waves", "group_wgs")
+# layered schedule: workgroup size (rows of a block row per thread) and LDS cache
+LAYERED_CANDIDATES = [(256, 0), (512, 0), (1024, 0), (512, -1), (1024, 150)]
+LAYERED_KNOBS = ("wg_threads", "lds_cache_kb")
 
 
 def tune_decode(batch, params, llr, syndrome, workspace, out, repeats: int = 2, candidates=CANDIDATES,

@@ -110,7 +110,7 @@ def test_iteration_count_behaviour():
 def test_slice_code_family_contains_the_chosen_codes():
     """The rate-selection candidates and the codes the pipeline uses are one family."""
     from paper_2108_08418_amd import inputs
-    for j, mb in ((2, 104), (3, 71)):
+    for j, mb in ((2, 104), (3, 65)):
         a = inputs.slice_code_spec(j, 4096)
         b = inputs.slice_code_at(j, 4096, mb)
         assert (a.shift == b.shift).all() and a.mb == b.mb == mb

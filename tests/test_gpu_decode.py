@@ -73,11 +73,18 @@ def test_config0_regular_sp_fp64():
     print(f"margin frames {m}/{F}; oracle failures {(ref['ok'] == 0).sum()}")
 
 
-def _slice_stage(j, n, F, seed):
+# Kernel tests with small iteration caps decode the slice-3 family member at
+# mb = 71 (R = 0.445), on which these frames converge within the caps; the
+# pipeline's slice-3 code (R = 0.492, about 34 sum-product iterations at
+# n = 65536) is decoded by the tests of the 2^20- and 2^27-pair stages.
+KERNEL_MB3 = 71
+
+
+def _slice_stage(j, n, F, seed, mb=None):
     x, y = inputs.gaussian_pairs(n * F, SNR, seed=seed)
     S = oracle.quantize(y, TH4, 4)
     L = oracle.slice_llr(x, SIG, TH4, 4, oracle.GRAY, j, (1 << j) - 1, S).reshape(F, n)
-    qc = inputs.slice_code_spec(j, n)
+    qc = inputs.slice_code_spec(j, n) if mb is None else inputs.slice_code_at(j, n, mb)
     csr = qc.to_csr()
     syn, _ = oracle.syndrome(csr, S[j].reshape(F, n))
     return qc, csr, L, syn, S[j].reshape(F, n)
@@ -118,7 +125,7 @@ def test_layouts_and_schedules_are_bit_identical():
     same order and must agree bit for bit."""
     print("[decode layouts/schedules]", flush=True)
     n, F = 16384, 6
-    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=99)
+    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=99, mb=KERNEL_MB3)
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8),
                  dict(algo=api.NMS, store=api.F32, alpha=0.7)):
         runs = []
@@ -205,7 +212,7 @@ def test_group_schedule_frames_from_queue(gw, mw):
     equal the persistent decoder's bit for bit, trace included."""
     print(f"[decode group queue gw={gw} mw={mw}]", flush=True)
     n, F = 16384, 37                  # Z = 128: two rows (variables) per thread and body
-    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=123)
+    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=123, mb=KERNEL_MB3)
     code = api.Code.from_qc(qc)
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8)):
         ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=40, math=api.F32, schedule=api.SCHED_PERSISTENT, **base),
@@ -225,7 +232,7 @@ def test_multi_row_bodies_at_non_power_of_two_Z(Z):
     schedule equal the per-pass kernels bit for bit."""
     print(f"[decode multi-row Z={Z}]", flush=True)
     n, F = 128 * Z, 3 if Z > 768 else 5
-    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=Z)
+    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=Z, mb=KERNEL_MB3)
     code = api.Code.from_qc(qc)
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.8)):
         ref = _decode_gpu(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_PASSES, **base))
@@ -367,7 +374,7 @@ def test_group_barrier_time_out_reports_every_frame_failed():
     decode equals the persistent decoder's."""
     print("[decode group barrier time-out]", flush=True)
     n, F = 16384, 12
-    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=321)
+    qc, csr, L, syn, _ = _slice_stage(3, n, F, seed=321, mb=KERNEL_MB3)
     code = api.Code.from_qc(qc)
     p = api.Params(algo=api.SP, max_iter=30, early_stop=False, math=api.F32, store=api.F32,
                    schedule=api.SCHED_GROUP)

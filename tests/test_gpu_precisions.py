@@ -3,7 +3,6 @@ binary16 message storage for min-sum and sum-product, binary64 min-sum, and
 the workspace-size error path."""
 from __future__ import annotations
 
-from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -11,6 +10,7 @@ import torch
 
 import oracle
 from paper_2108_08418_amd import api, inputs
+from tests._gpu_state import decoded_for
 from tests._parity import LayerIndex, compare_trace, flood_half_step_bound, has_margin, layered_half_step_bound
 
 pytestmark = pytest.mark.gpu
@@ -47,41 +47,6 @@ def _half_units(scale, k):
     return k * 2.0 ** (np.floor(np.log2(np.maximum(np.abs(scale), 2.0 ** -14))) - 10)
 
 
-def _state_csr(qc, msg):
-    """Messages of one frame from the decoder's [block][k] layout (blocks in
-    row-major protograph order) to the CSR edge order of qc.to_csr()."""
-    csr = qc.to_csr()
-    out = np.zeros(csr.n_edges)
-    Z = qc.Z
-    k = np.arange(Z)
-    q = 0
-    for i in range(qc.mb):
-        cols = np.nonzero(qc.shift[i] >= 0)[0]
-        base = csr.row_ptr[i * Z + k]
-        for qq in range(len(cols)):
-            out[base + qq] = msg[(q + qq) * Z + k]
-        q += len(cols)
-    return out
-
-
-def _after(code, qc, p, llr1, syn1, t):
-    """One frame decoded for exactly t iterations: (posteriors, stored messages
-    in CSR order as fp64).  The messages are the decoder's state at the start
-    of its workspace (zero before the first iteration)."""
-    batch = api.Batch.uniform(code, 1)
-    pt = replace(p, max_iter=t, early_stop=False)
-    ws = api.alloc_workspace(batch, pt)
-    out = api.ldpc_decode_batch(batch, pt, _g(llr1.astype(np.float32)), _g(syn1), workspace=ws)
-    torch.cuda.synchronize()
-    post = out["post"].cpu().numpy().astype(np.float64)
-    if t == 0:
-        return post, np.zeros(qc.to_csr().n_edges)
-    sdt, size = (torch.float16, 2) if p.store == api.F16 else (torch.float32, 4)
-    nb_z = int((qc.shift >= 0).sum()) * qc.Z
-    msg = ws[: nb_z * size].view(sdt).cpu().numpy().astype(np.float64)
-    return post, _state_csr(qc, msg)
-
-
 def _one_step_parity(qc, p, llr, syn, layered, T, algo):
     """From the decoder's own state after t iterations (t < T), one iteration of
     the fp64 oracle with binary16 storage emulated: the decoder's posteriors
@@ -102,7 +67,7 @@ def _one_step_parity(qc, p, llr, syn, layered, T, algo):
     tight = []
     for f in range(llr.shape[0]):
         l64 = llr[f].astype(np.float32).astype(np.float64)
-        post, c2v = _after(code, qc, p, llr[f], syn[f], 0)
+        post, c2v = decoded_for(code, qc, p, llr[f], syn[f], 0)
         for t in range(T):
             if layered:
                 c_o, p_o = oracle.layered_step(csr, l64, syn[f], c2v, post, t, layers=lay, **kw)
@@ -113,7 +78,7 @@ def _one_step_parity(qc, p, llr, syn, layered, T, algo):
             sc = np.abs(l64).copy()
             np.add.at(sc, csr.col_idx, np.abs(c_o))
             tight.append(float(np.median(E / _half_units(sc, 1.0))))
-            post, c2v = _after(code, qc, p, llr[f], syn[f], t + 1)
+            post, c2v = decoded_for(code, qc, p, llr[f], syn[f], t + 1)
             worst_post = max(worst_post, float(np.max(np.abs(post - p_o) / E)))
             worst_msg = max(worst_msg, float(np.max(np.abs(c2v - c_o) / B)))
     assert worst_post <= 1.0, f"posterior deviation {worst_post:.3g} x its bound"

@@ -189,7 +189,7 @@ def test_log_domain_llr_is_finite_where_linear_domain_underflows():
     assert np.isfinite(Lfar).all() and abs(Lfar[0] - ref) < 1e-12 * abs(ref)
 
 
-@pytest.mark.parametrize("j,code_rate", [(2, 0.1875), (3, 0.4453125)])
+@pytest.mark.parametrize("j,code_rate", [(2, 0.1875), (3, 0.4921875)])
 def test_slice_code_rates_respect_slepian_wolf(j, code_rate):
     """Syndrome bits per slice bit, 1 - R_j, must exceed H(S_j | X, S_<j)
     (Slepian-Wolf bound, Sec. III-B)."""

