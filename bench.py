@@ -58,10 +58,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="recon-2^27-nR2^16", choices=sorted(WORKLOADS))
     ap.add_argument("--decoder", default="both", choices=["both", "sp", "nms"],
-                    help="both: learned min-sum (the headline) and plain sum-product, timed one after the other")
-    ap.add_argument("--sp-schedule", dest="sp_schedule", default="auto",
-                    choices=["auto", "passes", "persistent", "group", "layered"],
-                    help="schedule of the plain sum-product decoder in --decoder both")
+                    help="both: layered sum-product (the headline), flooding sum-product and learned min-sum, "
+                         "timed one after the other")
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--alpha", type=float, default=0.75)
     ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
@@ -79,8 +77,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2108)
     ap.add_argument("--graph", action="store_true", help="replay the decode from a captured HIP graph")
     ap.add_argument("--sweep", action="store_true",
-                    help="block-size sweep: every recon-2^27 workload with SP and with learned min-sum "
-                         "(--weights, default 'learned'); prints one JSON line per point")
+                    help="block-size sweep: every recon-2^27 workload with flooding and layered sum-product and "
+                         "with learned min-sum (--weights, default 'learned'); prints one JSON line per point")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (untimed)")
     ap.add_argument("--no-rate-selection", action="store_true",
                     help="use the stored rate table instead of running the Sec. V-B selection loop (untimed)")
@@ -216,9 +214,9 @@ def main():
     if args.sweep:
         import copy
         for name in sorted(k for k in WORKLOADS if k.startswith("recon-2^27")):
-            for dec, wts in (("sp", ""), ("nms", args.weights or "learned")):
+            for dec, wts, sched in (("sp", "", "auto"), ("sp", "", "layered"), ("nms", args.weights or "learned", "auto")):
                 a = copy.copy(args)
-                a.workload, a.decoder, a.weights, a.no_cpu_baseline = name, dec, wts, True
+                a.workload, a.decoder, a.weights, a.no_cpu_baseline, a.schedule = name, dec, wts, True, sched
                 a.fer_seeds, a.no_rate_selection = 1, True
                 a.wg = a.min_waves = a.lds_cache_kb = 0
                 res = recon(a, WORKLOADS[name], dev)
@@ -291,14 +289,17 @@ def llr_forms(args, dev):
 
 def _decoder_configs(args, api):
     """(key, {coded slice: (algo, store, schedule name, weights prefix)}) of the
-    decoders one run times.  --decoder both (default): plain sum-product (the
-    headline: the paper's belief propagation), learned min-sum on both coded
-    slices, and the mixed pipeline (learned min-sum on slice 2, sum-product on
-    slice 3)."""
-    sp = (api.SP, api.F32, args.sp_schedule if args.decoder == "both" else args.schedule, "")
-    nms = (api.NMS, api.F16, args.schedule, args.weights or ("learned" if args.decoder == "both" else ""))
+    decoders one run times.  --decoder both (default): sum-product on the
+    layered schedule (the headline), plain flooding sum-product (the baseline
+    the paper's belief propagation names) and learned min-sum (flooding, binary16
+    messages) on both coded slices."""
+    sp = (api.SP, api.F32, args.schedule, "")
+    nms = (api.NMS, api.F16, args.schedule, args.weights)
     if args.decoder == "both":
-        return [("sp", {2: sp, 3: sp}), ("nms", {2: nms, 3: nms}), ("mixed", {2: nms, 3: sp})]
+        lay = (api.SP, api.F32, "layered", "")
+        flood = (api.SP, api.F32, "auto", "")
+        learned = (api.NMS, api.F16, "auto", args.weights or "learned")
+        return [("sp_layered", {2: lay, 3: lay}), ("sp", {2: flood, 3: flood}), ("nms", {2: learned, 3: learned})]
     if args.decoder == "sp":
         return [("sp", {2: sp, 3: sp})]
     return [("nms", {2: nms, 3: nms})]
@@ -418,22 +419,20 @@ def recon(args, wl, dev):
         tuned = None
         if not args.no_tune and ((persistent and args.wg == 0) or (layered and args.wg == 0)
                                  or (group and args.min_waves == 0 and args.group_wgs == 0)):
-            # pick the launch shape per coded slice on this workload's own decode (untimed)
+            # pick the launch shape on this workload's own decode (untimed)
             step()
             from paper_2108_08418_amd import tune
             knobs, cands = ((tune.LAYERED_KNOBS, tune.LAYERED_CANDIDATES) if layered else
                             (tune.KNOBS, tune.CANDIDATES) if persistent else (tune.GROUP_KNOBS, tune.GROUP_CANDIDATES))
-            tuned = {}
+            # one shape for both coded slices, picked on slice 2 (so that one
+            # kernel instance, and its recorded HBM traffic, covers the step)
+            api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
+            best, tim = tune.tune_decode(batches[2], stage_params[2], llr, syn[2], ws, outs[2],
+                                         candidates=cands, knobs=knobs)
             for j in (2, 3):
-                if j == 2:
-                    api.slice_llr(x, sig, th, M_BITS, 2, 0b11, alice, out=llr)
-                else:
-                    api.slice_llr(x, sig, th, M_BITS, 3, 0b111, alice, out=llr)
-                best, tim = tune.tune_decode(batches[j], stage_params[j], llr, syn[j], ws, outs[j],
-                                             candidates=cands, knobs=knobs)
                 for k, v in zip(knobs, best):
                     setattr(stage_params[j], k, v)
-                tuned[str(j)] = {"/".join(f"{k}={v}" for k, v in zip(knobs, c)): round(t, 3) for c, t in tim.items()}
+            tuned = {"/".join(f"{k}={v}" for k, v in zip(knobs, c)): round(t, 3) for c, t in tim.items()}
             print(f"# {d['key']} tuned: {[tuple(getattr(stage_params[j], k) for k in knobs) for j in (2, 3)]}",
                   file=sys.stderr, flush=True)
         for _ in range(args.warmup):
@@ -509,28 +508,30 @@ def recon(args, wl, dev):
         {str(j): {"capacity": round(rate_sel[j]["capacity"], 4), "test_sub_blocks": args.rate_frames,
                   "trail": [{k: c[k] for k in ("rate", "mb", "failures", "mean_iters")} for c in rate_sel[j]["trail"]]}
          for j in (2, 3)} if rate_sel else "fixed table (inputs.SLICE_MB)")
-    others = {}
-    for d in decs[1:]:
-        r = results[d["key"]]
-        same = {}
-        for j in (2, 3):
-            lo, hi = head["fer_frames"][str(j)]["wilson95"]
-            same[str(j)] = bool(lo <= r["fer_frames"][str(j)]["fer"] <= hi)
-        others[d["key"]] = {
-            **{k: r[k] for k in ("value", "ms_per_step", "dtype", "roofline", "decode_iteration",
-                                 "decode_ms_per_slice", "kernel_ms_per_step", "mean_iters", "fer_frames",
-                                 "bit_errors_vs_bob", "autotune_ms_per_decode")},
-            "config": {k: r["config"][k] for k in ("decoder", "max_iter", "schedule", "launch_shape")},
-            "bits_per_s_vs_sp": r["value"] / head["value"],
-            "decoder_speedup_vs_sp_per_slice": {
-                str(j): head["decode_ms_per_slice"][str(j)] / r["decode_ms_per_slice"][str(j)] for j in (2, 3)},
-            "same_fer_as_sp": same,
-        }
-    if others:
-        result["learned_min_sum"] = others
-        result["learned_min_sum_rule"] = (
-            "nms: learned min-sum on both coded slices; mixed: learned min-sum on slice 2 and sum-product on "
-            "slice 3.  same_fer_as_sp: the FER over fer_frames lies inside sum-product's 95 % Wilson interval")
+    if len(decs) > 1:
+        base = results["sp"]
+        comp = {}
+        for d in decs:
+            r = results[d["key"]]
+            same = {}
+            for j in (2, 3):
+                lo, hi = base["fer_frames"][str(j)]["wilson95"]
+                same[str(j)] = bool(lo <= r["fer_frames"][str(j)]["fer"] <= hi)
+            comp[d["key"]] = {
+                **{k: r[k] for k in ("value", "ms_per_step", "dtype", "roofline", "decode_iteration",
+                                     "decode_ms_per_slice", "kernel_ms_per_step", "mean_iters", "fer_frames",
+                                     "bit_errors_vs_bob", "autotune_ms_per_decode")},
+                "config": {k: r["config"][k] for k in ("decoder", "max_iter", "schedule", "launch_shape")},
+                "bits_per_s_vs_flooding_sp": r["value"] / base["value"],
+                "decoder_speedup_vs_flooding_sp_per_slice": {
+                    str(j): base["decode_ms_per_slice"][str(j)] / r["decode_ms_per_slice"][str(j)] for j in (2, 3)},
+                "same_fer_as_flooding_sp": same,
+            }
+        result["decoders"] = comp
+        result["decoders_rule"] = (
+            "sp_layered: sum-product, layered schedule (the value above); sp: sum-product, flooding schedule "
+            "(the baseline); nms: learned normalized min-sum, flooding, binary16 messages.  same_fer_as_flooding_sp: "
+            "the FER over fer_frames lies inside flooding sum-product's 95 % Wilson interval")
     # the Gaussian-approximation iteration count (host model) beside the measured
     # mean: a binary-input AWGN channel carrying the capacity that Alice's LLRs
     # (given Bob's true lower slices) carry about Bob's bits, the code's own
@@ -603,7 +604,7 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
         launches, launch_ms, launch_bytes = per_n, per_ms, args.steps * dec_bytes
         iter_gbs = achieved
         if shape[2] == shape[3]:
-            traffic, traffic_src = recorded_traffic(inst, args.workload, d["key"], wts)
+            traffic, traffic_src = recorded_traffic(inst, args.workload, "sp" if algo == api.SP else "nms", wts)
     else:
         roof_kernel = "decoder check-node pass (k_check_qc)"
         achieved = (args.steps * chk_bytes) / (chk_ms * 1e-3) / 1e9 if chk_ms > 0 else None

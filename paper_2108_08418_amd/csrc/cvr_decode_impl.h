@@ -463,6 +463,8 @@ struct LdsMap {
     int32_t rptr, cptr, row, col, cslot, cache;   // word offsets
     int32_t cache_bytes;
     int32_t hard;                                 // layered schedule: hard-decision bits
+    int32_t synb;                                 // layered schedule: syndrome bits
+    int32_t grp;                                  // layered schedule: layer groups
 };
 constexpr int32_t kCached = 1 << 29;
 
@@ -1292,6 +1294,15 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
 // row [NB] (shift | loc << 16 | type << 25 | cached << 29, as the persistent
 // decoder's), col [NB] (block column of row entry q), cslot [nb], hard
 // [n / 32], then the posterior cache.
+// Consecutive block rows that share no block column update disjoint
+// variables, so their rows can run in one step between two barriers with
+// results identical to updating them one after another.  Layer groups:
+// greedy runs of up to kGroupRows consecutive block rows with pairwise
+// disjoint columns (one block row per group when Z % 64 != 0, where a
+// wavefront's rows would span two block rows).  s_grp[0..ng] holds the first
+// block row of each group and mb; s_grp[kMaxLdsDim + 1] holds ng.
+constexpr int kGroupRows = 4;
+
 template <typename M, int NT>
 __device__ __forceinline__ void load_layer_tables(const LdsMap& lm, int32_t* dsm, const DevCode& cd)
 {
@@ -1300,9 +1311,11 @@ __device__ __forceinline__ void load_layer_tables(const LdsMap& lm, int32_t* dsm
     int32_t* s_row = dsm + lm.row;
     int32_t* s_lcol = dsm + lm.col;
     int32_t* s_cslot = dsm + lm.cslot;
+    int32_t* s_grp = dsm + lm.grp;
     const int nslot = min(cd.nb, int(lm.cache_bytes / (int64_t(cd.Z) * int64_t(sizeof(M)))));
     for (int q = tid; q <= cd.mb; q += NT) s_rptr[q] = cd.qrow_ptr[q];
     for (int q = tid; q < cd.nb; q += NT) s_cslot[q] = -1;
+    for (int q = tid; q < cd.NB; q += NT) s_lcol[q] = cd.qrow[q].other;
     __syncthreads();
     for (int q = tid; q < nslot; q += NT) s_cslot[cd.qcol_rank[q]] = q;
     __syncthreads();
@@ -1311,7 +1324,21 @@ __device__ __forceinline__ void load_layer_tables(const LdsMap& lm, int32_t* dsm
         const int slot = s_cslot[br.other];
         const int loc = slot >= 0 ? slot : br.other;
         s_row[q] = br.shift | (loc << 16) | (br.type << 25) | (slot >= 0 ? kCached : 0);
-        s_lcol[q] = br.other;
+    }
+    if (tid == 0) {
+        const int cap = (cd.Z % 64 == 0) ? kGroupRows : 1;
+        int ng = 0, first = 0;
+        for (int i = 1; i <= cd.mb; ++i) {
+            bool split = i == cd.mb || i - first >= cap;
+            for (int q = s_rptr[i]; !split && q < s_rptr[i + 1]; ++q)
+                for (int qp = s_rptr[first]; qp < s_rptr[i]; ++qp) split |= s_lcol[qp] == s_lcol[q];
+            if (split) {
+                s_grp[ng++] = first;
+                first = i;
+            }
+        }
+        s_grp[ng] = cd.mb;
+        s_grp[kMaxLdsDim + 1] = ng;
     }
     __syncthreads();
 }
@@ -1322,6 +1349,43 @@ struct LayerCtx {
     uint32_t* s_hard;
     int32_t* s_nan;
 };
+
+// The update of rows k[0..R) of the layer whose table entries start at q0,
+// with exactly D edges, from their loaded posteriors lr and stored messages
+// mr: x = L - c2v, the check rule, c2v and L written back, decision bits
+// flipped where the sign changed.
+template <typename M, typename S, int ALGO, int D, bool CACHE, int R>
+__device__ __forceinline__ void layer_update(const FrameCtx<M, S>& c, const LayerCtx& lc, int q0, const int (&k)[R],
+                                             const int (&sraw)[R], const int32_t (&e)[D], const int32_t (&jc)[D],
+                                             const int (&idx)[R][D], const M (&lr)[R][D], const S (&mr)[R][D])
+{
+    bool nan = false;
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+        M x[D], nl[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) x[q] = lr[h][q] - M(StoreT<S>::get(mr[h][q]));
+        auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
+        auto emit = [&](int q, M v) {
+            const S sv = StoreT<S>::put(v);
+            at(c.msg, uint32_t((q0 + q) * c.Z + k[h])) = sv;
+            nl[q] = x[q] + M(StoreT<S>::get(sv));
+        };
+        check_rule<M, ALGO, D>(x, D, sraw[h] & 1, M(c.clamp), weight, emit);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+            const int at_loc = ((e[q] >> 16) & 0x1ff) * c.Z + idx[h][q];
+            if (CACHE && (e[q] & kCached)) c.s_post[at_loc] = nl[q];
+            else at(c.Lp, uint32_t(at_loc)) = nl[q];
+            nan |= nl[q] != nl[q];
+            if ((lr[h][q] < M(0)) != (nl[q] < M(0))) {
+                const uint32_t b = uint32_t(jc[q] * c.Z + idx[h][q]);
+                atomicXor(lc.s_hard + (b >> 5), 1u << (b & 31));
+            }
+        }
+    }
+    if (nan) *lc.s_nan = 1;
+}
 
 // Rows k[0..R) of the layer whose table entries start at q0, with exactly D
 // edges: all R x D posteriors and stored messages are loaded before any
@@ -1364,32 +1428,7 @@ __device__ __forceinline__ void layer_rows(const FrameCtx<M, S>& c, const LayerC
             for (int q = 0; q < D; ++q) mr[h][q] = S(0);
         }
     }
-    bool nan = false;
-#pragma unroll
-    for (int h = 0; h < R; ++h) {
-        M x[D], nl[D];
-#pragma unroll
-        for (int q = 0; q < D; ++q) x[q] = lr[h][q] - M(StoreT<S>::get(mr[h][q]));
-        auto weight = [&](int q) -> M { return c.weighted ? M(c.s_w[(e[q] >> 25) & 0xf]) : M(c.alpha); };
-        auto emit = [&](int q, M v) {
-            const S sv = StoreT<S>::put(v);
-            at(c.msg, uint32_t((q0 + q) * c.Z + k[h])) = sv;
-            nl[q] = x[q] + M(StoreT<S>::get(sv));
-        };
-        check_rule<M, ALGO, D>(x, D, sraw[h] & 1, M(c.clamp), weight, emit);
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            const int at_loc = ((e[q] >> 16) & 0x1ff) * c.Z + idx[h][q];
-            if (CACHE && (e[q] & kCached)) c.s_post[at_loc] = nl[q];
-            else at(c.Lp, uint32_t(at_loc)) = nl[q];
-            nan |= nl[q] != nl[q];
-            if ((lr[h][q] < M(0)) != (nl[q] < M(0))) {
-                const uint32_t b = uint32_t(jc[q] * c.Z + idx[h][q]);
-                atomicXor(lc.s_hard + (b >> 5), 1u << (b & 31));
-            }
-        }
-    }
-    if (nan) *lc.s_nan = 1;
+    layer_update<M, S, ALGO, D, CACHE, R>(c, lc, q0, k, sraw, e, jc, idx, lr, mr);
 }
 
 // The same for any degree d <= MAXD (one row, masked).
@@ -1470,6 +1509,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
     c.alpha = a.alpha;
     c.clamp = a.clamp;
     LayerCtx lc{dsm + lm.col, reinterpret_cast<uint32_t*>(dsm + lm.hard), &s_nan};
+    uint32_t* s_synb = reinterpret_cast<uint32_t*>(dsm + lm.synb);
     const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
     M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
     auto column = [&](int v) { return zsh >= 0 ? (v >> zsh) : v / Z; };
@@ -1479,7 +1519,17 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
         const int slot = slot_of(j);
         return slot >= 0 ? c.s_post[slot * Z + (v - j * Z)] : at(c.Lp, v);
     };
+    auto syn_bit = [&](int r) -> int { return int(s_synb[r >> 5] >> (r & 31)) & 1; };
     for (int w = tid; w < (n + 31) / 32; w += NT) lc.s_hard[w] = 0u;
+    // Bob's syndrome of the frame as a bit array in LDS (read once)
+    for (int w = tid; w < (m + 31) / 32; w += NT) {
+        uint32_t bits = 0u;
+        if (syn) {
+            const int r0 = w * 32;
+            for (int b = 0; b < 32 && r0 + b < m; ++b) bits |= uint32_t(at(syn, r0 + b) & 1) << b;
+        }
+        s_synb[w] = bits;
+    }
     if (tid == 0) {
         s_unsat[0] = 0;
         s_unsat[1] = 0;
@@ -1496,9 +1546,8 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
         if (l < M(0)) atomicOr(lc.s_hard + (v >> 5), 1u << (v & 31));
         if (l != l) s_nan = 1;
     }
-    // rows per thread and body: R rows k0 + h Z / R of a layer, so that R x D
-    // loads are in flight together when a layer has more rows than threads
-    const int R = (Z >= 4 * NT && Z % 4 == 0) ? 4 : ((Z >= 2 * NT && Z % 2 == 0) ? 2 : 1);
+    const int32_t* s_grp = dsm + lm.grp;
+    const int ng = s_grp[kMaxLdsDim + 1];
     for (int t = 0;; ++t) {
         c.t = t;
         // the weights of iteration t (every read of the previous ones ended at
@@ -1511,7 +1560,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
             const int i = zsh >= 0 ? (r >> zsh) : r / Z;
             const int k = r - i * Z;
             const int q1 = s_rptr[i + 1];
-            int par = syn ? int(at(syn, r)) & 1 : 0;
+            int par = syn_bit(r);
             for (int q = s_rptr[i]; q < q1; ++q) {
                 int p = k + (c.s_row[q] & 0xffff);
                 p = p >= Z ? p - Z : p;
@@ -1531,41 +1580,31 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
             break;
         }
         if (tid == 0) s_unsat[(t + 1) & 1] = 0;
-        for (int i = 0; i < mb; ++i) {
-            const int q0 = __builtin_amdgcn_readfirstlane(s_rptr[i]);
-            const int d = __builtin_amdgcn_readfirstlane(s_rptr[i + 1]) - q0;
-            const uint8_t* si = syn ? syn + i * Z : nullptr;
-            auto rows = [&](auto rc) {
-                constexpr int RR = decltype(rc)::value;
-                const int qz = Z / RR;
-                for (int p = tid; p < qz; p += NT) {
-                    int kk[RR], ss[RR];
-#pragma unroll
-                    for (int h = 0; h < RR; ++h) {
-                        kk[h] = p + h * qz;
-                        ss[h] = si ? int(at(si, kk[h])) : 0;
-                    }
-                    switch (d) {
-                    case 1: layer_rows<M, S, ALGO, 1, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 2: layer_rows<M, S, ALGO, 2, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 3: layer_rows<M, S, ALGO, 3, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 4: layer_rows<M, S, ALGO, 4, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 5: layer_rows<M, S, ALGO, 5, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 6: layer_rows<M, S, ALGO, 6, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 7: layer_rows<M, S, ALGO, 7, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    case 8: layer_rows<M, S, ALGO, 8, CACHE, RR>(c, lc, q0, kk, ss); break;
-                    default:
-                        if constexpr (MAXD > 8) {
-                            for (int h = 0; h < RR; ++h)
-                                layer_row_any<M, S, ALGO, MAXD, CACHE>(c, lc, q0, d, kk[h], ss[h]);
-                        }
-                        break;
-                    }
+        // the layer groups in order; the rows of a group in one step
+        for (int g = 0; g < ng; ++g) {
+            const int i0 = s_grp[g];
+            const int rows = (s_grp[g + 1] - i0) * Z;
+            for (int r = tid; r < rows; r += NT) {
+                const int di = zsh >= 0 ? (r >> zsh) : r / Z;       // wave-uniform (Z % 64 == 0 or one block row)
+                const int k = r - di * Z;
+                const int i = i0 + di;
+                const int q0 = __builtin_amdgcn_readfirstlane(s_rptr[i]);
+                const int d = __builtin_amdgcn_readfirstlane(s_rptr[i + 1]) - q0;
+                const int kk[1] = {k}, ss[1] = {syn_bit(i * Z + k)};
+                switch (d) {
+                case 1: layer_rows<M, S, ALGO, 1, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 2: layer_rows<M, S, ALGO, 2, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 3: layer_rows<M, S, ALGO, 3, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 4: layer_rows<M, S, ALGO, 4, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 5: layer_rows<M, S, ALGO, 5, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 6: layer_rows<M, S, ALGO, 6, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 7: layer_rows<M, S, ALGO, 7, CACHE, 1>(c, lc, q0, kk, ss); break;
+                case 8: layer_rows<M, S, ALGO, 8, CACHE, 1>(c, lc, q0, kk, ss); break;
+                default:
+                    if constexpr (MAXD > 8) layer_row_any<M, S, ALGO, MAXD, CACHE>(c, lc, q0, d, k, ss[0]);
+                    break;
                 }
-            };
-            if (R == 4) rows(std::integral_constant<int, 4>{});
-            else if (R == 2) rows(std::integral_constant<int, 2>{});
-            else rows(std::integral_constant<int, 1>{});
+            }
             __syncthreads();
         }
         if (tr)
@@ -1587,7 +1626,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
 }
 
 template <typename M, typename S, int ALGO, int MAXD, int NT, bool CACHE>
-__global__ __launch_bounds__(NT) void k_layered_qc(DecArgs a, LdsMap lm, int32_t* queue, int32_t F,
+__global__ __launch_bounds__(NT, MAXD <= 8 ? 4 : 1) void k_layered_qc(DecArgs a, LdsMap lm, int32_t* queue, int32_t F,
                                                    const int32_t* order)
 {
     extern __shared__ __align__(16) int32_t dsm[];
@@ -1920,10 +1959,14 @@ static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue
     }
     int64_t max_n = 0;
     for (const cvr_code_t c : b->codes) max_n = std::max<int64_t>(max_n, c->dev.n);
+    int64_t max_m = 0;
+    for (const cvr_code_t c : b->codes) max_m = std::max<int64_t>(max_m, int64_t(c->dev.mb) * c->dev.Z);
     auto map = [&](int cache_bytes) {
         LdsMap lm = lds_map(b, cache_bytes);
         lm.hard = lm.cache;
-        lm.cache = int32_t((lm.hard + (max_n + 31) / 32 + 3) / 4 * 4);
+        lm.synb = int32_t(lm.hard + (max_n + 31) / 32);
+        lm.grp = int32_t(lm.synb + (max_m + 31) / 32);
+        lm.cache = int32_t((lm.grp + kMaxLdsDim + 2 + 3) / 4 * 4);
         return lm;
     };
     const int tab = map(0).cache * 4;

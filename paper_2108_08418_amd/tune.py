@@ -20,7 +20,7 @@ KNOBS = ("wg_threads", "min_waves", "lds_cache_kb")
 GROUP_CANDIDATES = [(0, 0), (8, 0), (0, 8)]
 GROUP_KNOBS = ("min_waves", "group_wgs")
 # layered schedule: workgroup size (rows of a block row per thread) and LDS cache
-LAYERED_CANDIDATES = [(256, 0), (512, 0), (1024, 0), (512, -1), (1024, 150)]
+LAYERED_CANDIDATES = [(256, 0), (512, 0), (1024, 0), (512, 150), (256, -1)]
 LAYERED_KNOBS = ("wg_threads", "lds_cache_kb")
 
 
