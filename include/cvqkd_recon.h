@@ -252,9 +252,12 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            stored c2v_e, so later block rows see the updated L.  L starts
  *            as the channel LLRs; the syndrome test, stop rule and outputs are
  *            those of flooding.  One workgroup decodes a frame (the codes of
- *            the persistent schedule, else CVR_EUNSUPPORTED); wg_threads may be
- *            0 (= 512), 256, 512 or 1024 and lds_cache_kb applies; min_waves
- *            and group_wgs are ignored.
+ *            the persistent schedule whose decision and syndrome bits fit in
+ *            LDS beside the code tables, else CVR_EUNSUPPORTED); consecutive
+ *            block rows with no block column in common run in one step (their
+ *            updates commute, so results equal one block row at a time);
+ *            wg_threads may be 0 (= 512), 256, 512 or 1024 and lds_cache_kb
+ *            applies; min_waves and group_wgs are ignored.
  *  wg_threads, min_waves  tuning knobs of the persistent decoder that do
  *            not change results: workgroup size 512 or 1024 (0 = 512);
  *            min_waves 8 compiles for 8 resident waves per SIMD, 0 lets the
