@@ -219,7 +219,10 @@ def main():
                 a.workload, a.decoder, a.weights, a.no_cpu_baseline, a.schedule = name, dec, wts, True, sched
                 a.fer_seeds, a.no_rate_selection = 1, True
                 a.wg = a.min_waves = a.lds_cache_kb = 0
-                res = recon(a, WORKLOADS[name], dev)
+                try:
+                    res = recon(a, WORKLOADS[name], dev)
+                except api._lib.CvrError as e:      # a schedule that does not take this sub-block size
+                    res = {"workload": name, "decoder": dec, "schedule": sched, "error": str(e)}
                 print(json.dumps(res), flush=True)
         return
     wl = WORKLOADS[args.workload]
