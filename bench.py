@@ -294,15 +294,18 @@ def _decoder_configs(args, api):
     """(key, {coded slice: (algo, store, schedule name, weights prefix)}) of the
     decoders one run times.  --decoder both (default): sum-product on the
     layered schedule (the headline), plain flooding sum-product (the baseline
-    the paper's belief propagation names) and learned min-sum (flooding, binary16
-    messages) on both coded slices."""
+    the paper's belief propagation names), and learned min-sum with binary16
+    messages on the flooding and on the layered schedule, on both coded
+    slices."""
     sp = (api.SP, api.F32, args.schedule, "")
     nms = (api.NMS, api.F16, args.schedule, args.weights)
     if args.decoder == "both":
         lay = (api.SP, api.F32, "layered", "")
         flood = (api.SP, api.F32, "auto", "")
         learned = (api.NMS, api.F16, "auto", args.weights or "learned")
-        return [("sp_layered", {2: lay, 3: lay}), ("sp", {2: flood, 3: flood}), ("nms", {2: learned, 3: learned})]
+        learned_lay = (api.NMS, api.F16, "layered", args.weights or "learned")
+        return [("sp_layered", {2: lay, 3: lay}), ("sp", {2: flood, 3: flood}), ("nms", {2: learned, 3: learned}),
+                ("nms_layered", {2: learned_lay, 3: learned_lay})]
     if args.decoder == "sp":
         return [("sp", {2: sp, 3: sp})]
     return [("nms", {2: nms, 3: nms})]
@@ -533,8 +536,9 @@ def recon(args, wl, dev):
         result["decoders"] = comp
         result["decoders_rule"] = (
             "sp_layered: sum-product, layered schedule (the value above); sp: sum-product, flooding schedule "
-            "(the baseline); nms: learned normalized min-sum, flooding, binary16 messages.  same_fer_as_flooding_sp: "
-            "the FER over fer_frames lies inside flooding sum-product's 95 % Wilson interval")
+            "(the baseline); nms: learned normalized min-sum, flooding, binary16 messages; nms_layered: the same "
+            "learned min-sum on the layered schedule.  same_fer_as_flooding_sp: the FER over fer_frames lies inside "
+            "flooding sum-product's 95 % Wilson interval")
     # the Gaussian-approximation iteration count (host model) beside the measured
     # mean: a binary-input AWGN channel carrying the capacity that Alice's LLRs
     # (given Bob's true lower slices) carry about Bob's bits, the code's own

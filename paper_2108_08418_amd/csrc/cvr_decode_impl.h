@@ -1301,7 +1301,7 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
 // disjoint columns (one block row per group when Z % 64 != 0, where a
 // wavefront's rows would span two block rows).  s_grp[0..ng] holds the first
 // block row of each group and mb; s_grp[kMaxLdsDim + 1] holds ng.
-constexpr int kGroupRows = 4;
+constexpr int kGroupRows = 8;
 
 template <typename M, int NT>
 __device__ __forceinline__ void load_layer_tables(const LdsMap& lm, int32_t* dsm, const DevCode& cd)
@@ -1483,6 +1483,29 @@ __device__ __forceinline__ void layer_row_any(const FrameCtx<M, S>& c, const Lay
     if (nan) *lc.s_nan = 1;
 }
 
+// Rows k[0..R) of one block row with d edges: the exact-degree body.
+template <typename M, typename S, int ALGO, int MAXD, bool CACHE, int R>
+__device__ __forceinline__ void layer_rows_d(const FrameCtx<M, S>& c, const LayerCtx& lc, int q0, int d,
+                                             const int (&k)[R], const int (&ss)[R])
+{
+    switch (d) {
+    case 1: layer_rows<M, S, ALGO, 1, CACHE, R>(c, lc, q0, k, ss); break;
+    case 2: layer_rows<M, S, ALGO, 2, CACHE, R>(c, lc, q0, k, ss); break;
+    case 3: layer_rows<M, S, ALGO, 3, CACHE, R>(c, lc, q0, k, ss); break;
+    case 4: layer_rows<M, S, ALGO, 4, CACHE, R>(c, lc, q0, k, ss); break;
+    case 5: layer_rows<M, S, ALGO, 5, CACHE, R>(c, lc, q0, k, ss); break;
+    case 6: layer_rows<M, S, ALGO, 6, CACHE, R>(c, lc, q0, k, ss); break;
+    case 7: layer_rows<M, S, ALGO, 7, CACHE, R>(c, lc, q0, k, ss); break;
+    case 8: layer_rows<M, S, ALGO, 8, CACHE, R>(c, lc, q0, k, ss); break;
+    default:
+        if constexpr (MAXD > 8) {
+#pragma unroll
+            for (int h = 0; h < R; ++h) layer_row_any<M, S, ALGO, MAXD, CACHE>(c, lc, q0, d, k[h], ss[h]);
+        }
+        break;
+    }
+}
+
 // One frame, all iterations, on the layered schedule.
 template <typename M, typename S, int ALGO, int MAXD, int NT, bool CACHE>
 __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const LdsMap& lm, int32_t* dsm,
@@ -1491,7 +1514,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
 {
     const int tid = int(threadIdx.x);
     const int Z = cd.Z;
-    const int mb = cd.mb, m = cd.mb * Z, n = cd.nb * Z;
+    const int m = cd.mb * Z, n = cd.nb * Z;
     const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
     const int32_t* s_rptr = dsm + lm.rptr;
     FrameCtx<M, S> c;
@@ -1556,18 +1579,41 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
         __syncthreads();
         // syndrome test of the hard decisions of L
         int bad = 0;
-        for (int r = tid; r < m; r += NT) {
-            const int i = zsh >= 0 ? (r >> zsh) : r / Z;
-            const int k = r - i * Z;
-            const int q1 = s_rptr[i + 1];
-            int par = syn_bit(r);
-            for (int q = s_rptr[i]; q < q1; ++q) {
-                int p = k + (c.s_row[q] & 0xffff);
-                p = p >= Z ? p - Z : p;
-                const uint32_t b = uint32_t(lc.s_lcol[q] * Z + p);
-                par ^= int(lc.s_hard[b >> 5] >> (b & 31)) & 1;
+        if (Z % 32 == 0) {
+            // 32 rows k0 .. k0 + 31 of a block row per thread: an edge with
+            // shift s reads the decision bits of variables k0 + s .. k0 + s + 31
+            // (mod Z) of its column as one rotated 32-bit window
+            const int W = Z >> 5;
+            for (int u = tid; u < (m >> 5); u += NT) {
+                const int i = zsh >= 0 ? (u >> (zsh - 5)) : u / W;
+                const int k0 = (u - i * W) << 5;
+                const int q1 = s_rptr[i + 1];
+                uint32_t par = s_synb[u];
+                for (int q = s_rptr[i]; q < q1; ++q) {
+                    int st = k0 + (c.s_row[q] & 0xffff);
+                    st = st >= Z ? st - Z : st;
+                    const uint32_t* colw = lc.s_hard + lc.s_lcol[q] * W;
+                    const int w = st >> 5, off = st & 31;
+                    const uint32_t lo = colw[w];
+                    const uint32_t hi = colw[w + 1 == W ? 0 : w + 1];
+                    par ^= off ? (lo >> off) | (hi << (32 - off)) : lo;
+                }
+                bad += __popc(par);
             }
-            bad += par;
+        } else {
+            for (int r = tid; r < m; r += NT) {
+                const int i = zsh >= 0 ? (r >> zsh) : r / Z;
+                const int k = r - i * Z;
+                const int q1 = s_rptr[i + 1];
+                int par = syn_bit(r);
+                for (int q = s_rptr[i]; q < q1; ++q) {
+                    int p = k + (c.s_row[q] & 0xffff);
+                    p = p >= Z ? p - Z : p;
+                    const uint32_t b = uint32_t(lc.s_lcol[q] * Z + p);
+                    par ^= int(lc.s_hard[b >> 5] >> (b & 31)) & 1;
+                }
+                bad += par;
+            }
         }
         if (bad) atomicAdd(&s_unsat[t & 1], bad);
         __syncthreads();
@@ -1591,19 +1637,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
                 const int q0 = __builtin_amdgcn_readfirstlane(s_rptr[i]);
                 const int d = __builtin_amdgcn_readfirstlane(s_rptr[i + 1]) - q0;
                 const int kk[1] = {k}, ss[1] = {syn_bit(i * Z + k)};
-                switch (d) {
-                case 1: layer_rows<M, S, ALGO, 1, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 2: layer_rows<M, S, ALGO, 2, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 3: layer_rows<M, S, ALGO, 3, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 4: layer_rows<M, S, ALGO, 4, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 5: layer_rows<M, S, ALGO, 5, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 6: layer_rows<M, S, ALGO, 6, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 7: layer_rows<M, S, ALGO, 7, CACHE, 1>(c, lc, q0, kk, ss); break;
-                case 8: layer_rows<M, S, ALGO, 8, CACHE, 1>(c, lc, q0, kk, ss); break;
-                default:
-                    if constexpr (MAXD > 8) layer_row_any<M, S, ALGO, MAXD, CACHE>(c, lc, q0, d, k, ss[0]);
-                    break;
-                }
+                layer_rows_d<M, S, ALGO, MAXD, CACHE, 1>(c, lc, q0, d, kk, ss);
             }
             __syncthreads();
         }

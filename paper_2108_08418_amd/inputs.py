@@ -305,16 +305,45 @@ def _chain_base_matrix(col_deg: np.ndarray, mb: int, rng: np.random.Generator) -
     return base
 
 
+def layer_order(base: np.ndarray, group: int = 8) -> np.ndarray:
+    """An order of the block rows of a protograph in runs of at most ``group``
+    rows that pairwise share no block column.  Rows of such a run touch
+    disjoint variables, so a layered decoder may update them together; the
+    order only lists the same checks differently.  Greedy: each run takes the
+    remaining rows in order of most column conflicts with the other remaining
+    rows (ties by index) that conflict with none already in the run."""
+    mb = base.shape[0]
+    b = (base != 0).astype(np.int64)
+    conflict = (b @ b.T) > 0
+    np.fill_diagonal(conflict, False)
+    left = list(range(mb))
+    order = []
+    while left:
+        run = []
+        for r in sorted(left, key=lambda r: (-int(conflict[r, left].sum()), r)):
+            if len(run) == group:
+                break
+            if not any(conflict[r, q] for q in run):
+                run.append(r)
+        for r in run:
+            left.remove(r)
+        order.extend(run)
+    return np.asarray(order, dtype=np.int64)
+
+
 def _lambda_qc_code(nb: int, mb: int, Z: int, seed: int, name: str) -> QcCode:
     """The protograph depends on ``seed`` only, so that every lifting size Z
     shares it (and per-edge-type decoder weights carry over between sub-block
-    lengths); the circulant shifts depend on (seed, Z)."""
+    lengths); the circulant shifts depend on (seed, Z).  Block rows are listed
+    in ``layer_order``: runs of up to 8 rows with disjoint columns, the layers
+    a layered schedule updates together."""
     col_deg, col_type = _lambda_columns(nb)
     rng = np.random.default_rng(seed)
     p = rng.permutation(nb)
     col_deg, col_type = col_deg[p], col_type[p]
     base = _chain_base_matrix(col_deg, mb, rng)
     shift = _assign_shifts(base, Z, np.random.default_rng([seed, Z]))
+    shift = shift[layer_order(base)]
     btype = np.where(shift >= 0, col_type[None, :], 0).astype(np.uint8)
     return QcCode(nb, mb, Z, shift.astype(np.int32), btype, 3, name=name)
 
@@ -334,8 +363,8 @@ def slice_code_spec(slice_j: int, n: int, seed: int = 2108) -> QcCode:
     4-slice setup at SNR 3: lambda(x) = 0.25x + 0.3x^2 + 0.45x^7 over nb = 128
     block columns, degree-2 columns chained (see ``_chain_base_matrix``), at
     the rate the selection loop picks (``SLICE_MB``): slice 2 R = 0.1875,
-    slice 3 R = 0.4921875.  Column permutation, row order and shifts are
-    seeded."""
+    slice 3 R = 0.4921875.  Column permutation and shifts are seeded; block
+    rows are listed in ``layer_order``."""
     return slice_code_at(slice_j, n, SLICE_MB[slice_j], seed)
 
 
