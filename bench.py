@@ -115,16 +115,22 @@ def wilson95(k: int, F: int):
     return [max(0.0, mid - half), min(1.0, mid + half)]
 
 
-def csrc_hash() -> str:
-    """Hash of the sources the decoder kernels are built from (a recorded
-    traffic figure is valid while it is unchanged)."""
+# sources each recorded kernel is built from: the decoders, and the adjoint
+# of unrolled min-sum, which adds its own translation unit
+DECODER_SOURCES = ("cvr_decode_impl.h", "cvr_internal.h", "cvr_decode.hip", "cvr_codes.hip")
+ADJOINT_SOURCES = DECODER_SOURCES + ("cvr_nms_grad.hip",)
+
+
+def csrc_hash(kernel_name: str = "") -> str:
+    """Hash of the sources a kernel is built from (a recorded traffic figure
+    is valid while it is unchanged): the adjoint kernel's, or the decoders'."""
     import hashlib
     from pathlib import Path
+    names = ADJOINT_SOURCES if "k_nms_bwd" in kernel_name else DECODER_SOURCES
     h = hashlib.sha256()
     csrc = Path(ROOT) / "paper_2108_08418_amd" / "csrc"
     for p in sorted(csrc.glob("*")):
-        if p.name in ("cvr_decode_impl.h", "cvr_internal.h", "cvr_decode.hip", "cvr_codes.hip",
-                      "cvr_nms_grad.hip") or p.name.startswith("cvr_dec_"):
+        if p.name in names or p.name.startswith("cvr_dec_"):
             h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
@@ -135,7 +141,7 @@ def recorded_traffic(kernel_name: str, workload: str, decoder: str, weights: str
     no record exists or the decoder sources changed since the counters were
     taken."""
     from pathlib import Path
-    sha = csrc_hash()
+    sha = csrc_hash(kernel_name)
     for p in sorted((Path(ROOT) / "profiles").glob("*_hbm_traffic.md")):
         text = p.read_text()
         if "```json" not in text:
@@ -146,6 +152,27 @@ def recorded_traffic(kernel_name: str, workload: str, decoder: str, weights: str
                 and rec.get("weights", "") == (weights or "")):
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], p.name
     return None, None
+
+
+def recorded_valu(kernel_name: str, workload: str, decoder: str, weights: str):
+    """Fraction of the chip's VALU issue slots (plain, and with quarter-rate
+    transcendentals counted as four slots) recorded under profiles/ from
+    rocprofv3 instruction counters for this kernel, workload, decoder and
+    weights, or None when no record exists or the sources changed since."""
+    from pathlib import Path
+    sha = csrc_hash(kernel_name)
+    for p in sorted((Path(ROOT) / "profiles").glob("*_valu_counts.md")):
+        text = p.read_text()
+        if "```json" not in text:
+            continue
+        for line in text.split("```json", 1)[1].split("```", 1)[0].strip().splitlines():
+            rec = json.loads(line)
+            if (rec.get("source_sha") == sha and kernel_name.startswith(rec.get("kernel", "?"))
+                    and rec.get("workload") == workload and rec.get("decoder") == decoder
+                    and rec.get("weights", "") == (weights or "")):
+                return {"issue": rec["valu_issue"], "issue_with_transcendentals": rec["valu_issue_with_transcendentals"],
+                        "source": p.name}
+    return None
 
 
 def frame_decode_bytes(iters, n, m, E, s_msg):
@@ -585,7 +612,7 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
     var_ms, var_n = prof["var"]
     per_ms, per_n = prof["decode_persistent"]
     dom = max(("check", "var", "slice_llr", "decode_persistent"), key=lambda k: prof[k][0])
-    traffic = traffic_src = None
+    traffic = traffic_src = valu = None
     shape = {j: (stage_params[j].wg_threads, stage_params[j].min_waves, stage_params[j].lds_cache_kb,
                  stage_params[j].group_wgs) for j in (2, 3)}
     if per_ms > 0 and not uniform:
@@ -612,6 +639,7 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
         iter_gbs = achieved
         if shape[2] == shape[3]:
             traffic, traffic_src = recorded_traffic(inst, args.workload, "sp" if algo == api.SP else "nms", wts)
+            valu = recorded_valu(inst, args.workload, "sp" if algo == api.SP else "nms", wts)
     else:
         roof_kernel = "decoder check-node pass (k_check_qc)"
         achieved = (args.steps * chk_bytes) / (chk_ms * 1e-3) / 1e9 if chk_ms > 0 else None
@@ -659,9 +687,15 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
             "traffic_over_algorithmic": (traffic / (launch_bytes / launches)) if (traffic and launches) else None,
             "avg_launch_us": 1e3 * launch_ms / launches if launches else None,
             "algorithmic_bytes_per_launch": launch_bytes / launches if launches else None,
+            "valu_issue_frac": valu["issue"] if valu else None,
+            "valu_issue_frac_with_transcendentals": valu["issue_with_transcendentals"] if valu else None,
+            "valu_source": valu["source"] if valu else None,
             "note": ("group schedule: the decoder state stays in the L2 / Infinity Cache (HBM traffic far "
                      "below the algorithmic bytes), so an iteration is bound by barrier and pass latency, "
-                     "not HBM" if (per_ms > 0 and group and not layered) else None),
+                     "not HBM" if (per_ms > 0 and group and not layered) else
+                     "layered schedule: the LDS posterior cache keeps HBM traffic below the algorithmic bytes; "
+                     "rocprofv3 instruction counters put the kernel near its VALU issue limit "
+                     "(valu_issue_frac), which bounds it before HBM does" if (layered and valu) else None),
         },
         "paper_context": PAPER_CONTEXT,
         "decode_iteration": {
