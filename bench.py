@@ -942,18 +942,23 @@ def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, dec):
         sp = dec["stage_params"][j]
         algo = oracle.SP if sp.algo == api.SP else oracle.NMS
         w = None if sp.weights is None else sp.weights.cpu().numpy().astype(np.float64)
-        r = oracle.decode(csr[j], L.reshape(Fs, n), syn[j], algo=algo, max_iter=sp.max_iter,
-                          alpha=args.alpha, weights=w, store_half=(algo == oracle.NMS))
+        kw = dict(algo=algo, max_iter=sp.max_iter, alpha=args.alpha, weights=w, store_half=(algo == oracle.NMS))
+        if sp.schedule == api.SCHED_LAYERED:
+            r = oracle.decode_layered(csr[j], L.reshape(Fs, n), syn[j], layers=oracle.qc_layers(qcs[j].mb, qcs[j].Z),
+                                      **kw)
+        else:
+            r = oracle.decode(csr[j], L.reshape(Fs, n), syn[j], **kw)
         A[j] = r["bits"].reshape(-1)
         edge_updates += int(np.asarray(r["iters"]).astype(np.int64).sum()) * csr[j].n_edges
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rule = " / ".join("sum-product" if dec["stage_params"][j].algo == api.SP else
-                      "min-sum with the same weights and binary16 messages" for j in (2, 3))
+    sched = "layered" if dec["stage_params"][2].schedule == api.SCHED_LAYERED else "flooding"
+    rule = sched + " " + " / ".join("sum-product" if dec["stage_params"][j].algo == api.SP else
+                                    "min-sum with the same weights and binary16 messages" for j in (2, 3))
     return {"value": 2 * Ns / dt, "unit": "bits/s", "cores": min(cores, os.cpu_count() or cores),
             "kind": "oracle", "seconds": dt, "edge_updates_per_s": edge_updates / dt,
             "sample": f"first {Fs} of the {len(x_np) // n} sub-blocks of {n} bits of both coded slices: fp64 "
-                      f"quantiser, syndromes, slice LLRs and flooding {rule}; decode threads across sub-blocks"}
+                      f"quantiser, syndromes, slice LLRs and {rule} (slice 2 / slice 3); decode threads across sub-blocks"}
 
 
 if __name__ == "__main__":
