@@ -78,7 +78,8 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay the decode from a captured HIP graph")
     ap.add_argument("--sweep", action="store_true",
                     help="block-size sweep: every recon-2^27 workload with flooding and layered sum-product and "
-                         "with learned min-sum (--weights, default 'learned'); prints one JSON line per point")
+                         "with learned min-sum (--weights, default 'learned'), flooding and layered; prints one JSON "
+                         "line per point")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (untimed)")
     ap.add_argument("--no-rate-selection", action="store_true",
                     help="use the stored rate table instead of running the Sec. V-B selection loop (untimed)")
@@ -241,7 +242,8 @@ def main():
     if args.sweep:
         import copy
         for name in sorted(k for k in WORKLOADS if k.startswith("recon-2^27")):
-            for dec, wts, sched in (("sp", "", "auto"), ("sp", "", "layered"), ("nms", args.weights or "learned", "auto")):
+            for dec, wts, sched in (("sp", "", "auto"), ("sp", "", "layered"), ("nms", args.weights or "learned", "auto"),
+                                    ("nms", args.weights or "learned", "layered")):
                 a = copy.copy(args)
                 a.workload, a.decoder, a.weights, a.no_cpu_baseline, a.schedule = name, dec, wts, True, sched
                 a.fer_seeds, a.no_rate_selection = 1, True

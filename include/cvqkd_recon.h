@@ -252,8 +252,9 @@ cvr_status cvr_batch_destroy(cvr_batch_t batch);
  *            stored c2v_e, so later block rows see the updated L.  L starts
  *            as the channel LLRs; the syndrome test, stop rule and outputs are
  *            those of flooding.  One workgroup decodes a frame (the codes of
- *            the persistent schedule whose decision and syndrome bits fit in
- *            LDS beside the code tables, else CVR_EUNSUPPORTED); consecutive
+ *            the persistent schedule whose decision bits fit in LDS beside the
+ *            code tables, else CVR_EUNSUPPORTED; Bob's syndrome bits go to the
+ *            workspace when they do not fit as well); consecutive
  *            block rows with no block column in common run in one step (their
  *            updates commute, so results equal one block row at a time);
  *            wg_threads may be 0 (= 512), 256, 512 or 1024 and lds_cache_kb
@@ -295,7 +296,10 @@ typedef struct {
     void* trace;
 } cvr_decode_params;
 
-/* Bytes of device workspace ldpc_decode_batch needs for this batch/params. */
+/* Bytes of device workspace ldpc_decode_batch needs for this batch/params
+ * (messages, posteriors, per-frame flags and counters; on the layered
+ * schedule also room for Bob's syndrome bits of frames whose decision and
+ * syndrome bits do not fit in LDS together). */
 cvr_status cvr_decode_workspace_size(cvr_batch_t batch, const cvr_decode_params* params,
                                      size_t* bytes);
 

@@ -180,6 +180,7 @@ extern "C" cvr_status ldpc_decode_batch(cvr_batch_t batch, const cvr_decode_para
     a.ok = ok_out;
     a.active = reinterpret_cast<int32_t*>(ws + w.active);
     a.unsat = reinterpret_cast<int32_t*>(ws + w.unsat);
+    a.synw = reinterpret_cast<uint32_t*>(ws + w.synw);
     a.weights = params->weights;
     a.total_n = batch->total_n;
     a.alpha = params->alpha;

@@ -158,6 +158,7 @@ struct DecArgs {
     uint8_t* ok;
     int32_t* active;          // [F]
     int32_t* unsat;           // [F][2]
+    uint32_t* synw;           // layered schedule, when LDS is short: syndrome bit arrays, frame f at word chk_off / 32 + f
     const float* weights;     // [T][n_types] or NULL
     int64_t total_n;
     float alpha;
@@ -1298,9 +1299,9 @@ __global__ __launch_bounds__(NT, MINW) void k_group_qc(DecArgs a, LdsMap lm, Gro
 // variables, so their rows can run in one step between two barriers with
 // results identical to updating them one after another.  Layer groups:
 // greedy runs of up to kGroupRows consecutive block rows with pairwise
-// disjoint columns (one block row per group when Z % 64 != 0, where a
-// wavefront's rows would span two block rows).  s_grp[0..ng] holds the first
-// block row of each group and mb; s_grp[kMaxLdsDim + 1] holds ng.
+// disjoint columns (when Z % 64 != 0 a wavefront's rows span block rows and
+// take the masked body).  s_grp[0..ng] holds the first block row of each group
+// and mb; s_grp[kMaxLdsDim + 1] holds ng.
 constexpr int kGroupRows = 8;
 
 template <typename M, int NT>
@@ -1326,7 +1327,7 @@ __device__ __forceinline__ void load_layer_tables(const LdsMap& lm, int32_t* dsm
         s_row[q] = br.shift | (loc << 16) | (br.type << 25) | (slot >= 0 ? kCached : 0);
     }
     if (tid == 0) {
-        const int cap = (cd.Z % 64 == 0) ? kGroupRows : 1;
+        const int cap = kGroupRows;
         int ng = 0, first = 0;
         for (int i = 1; i <= cd.mb; ++i) {
             bool split = i == cd.mb || i - first >= cap;
@@ -1431,8 +1432,9 @@ __device__ __forceinline__ void layer_rows(const FrameCtx<M, S>& c, const LayerC
     layer_update<M, S, ALGO, D, CACHE, R>(c, lc, q0, k, sraw, e, jc, idx, lr, mr);
 }
 
-// The same for any degree d <= MAXD (one row, masked).
-template <typename M, typename S, int ALGO, int MAXD, bool CACHE>
+// The same for any degree d <= MAXD (one row, masked).  With WU the block row
+// (q0, d) is wave-uniform; without, each lane reads its own table entries.
+template <typename M, typename S, int ALGO, int MAXD, bool CACHE, bool WU = true>
 __device__ __forceinline__ void layer_row_any(const FrameCtx<M, S>& c, const LayerCtx& lc, int q0, int d, int k,
                                               int sraw)
 {
@@ -1441,8 +1443,8 @@ __device__ __forceinline__ void layer_row_any(const FrameCtx<M, S>& c, const Lay
     S mr[MAXD];
 #pragma unroll
     for (int q = 0; q < MAXD; ++q) {
-        e[q] = (q < d) ? __builtin_amdgcn_readfirstlane(c.s_row[q0 + q]) : 0;
-        jc[q] = (q < d) ? __builtin_amdgcn_readfirstlane(lc.s_lcol[q0 + q]) : 0;
+        e[q] = (q < d) ? uni<WU>(c.s_row[q0 + q]) : 0;
+        jc[q] = (q < d) ? uni<WU>(lc.s_lcol[q0 + q]) : 0;
         lr[q] = M(0);
         mr[q] = S(0);
         idx[q] = 0;
@@ -1532,7 +1534,12 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
     c.alpha = a.alpha;
     c.clamp = a.clamp;
     LayerCtx lc{dsm + lm.col, reinterpret_cast<uint32_t*>(dsm + lm.hard), &s_nan};
-    uint32_t* s_synb = reinterpret_cast<uint32_t*>(dsm + lm.synb);
+    // Bob's syndrome bits: in LDS, or in the workspace when LDS is short
+    const bool syn_lds = lm.synb >= 0;
+    uint32_t* s_synb = syn_lds ? reinterpret_cast<uint32_t*>(dsm + lm.synb) : a.synw + ((fr.chk_off >> 5) + f);
+    auto syn_word = [&](int w) -> uint32_t {
+        return syn_lds ? lds_read(s_synb + w) : *(const __attribute__((address_space(1))) uint32_t*)(s_synb + w);
+    };
     const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
     M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
     auto column = [&](int v) { return zsh >= 0 ? (v >> zsh) : v / Z; };
@@ -1542,9 +1549,9 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
         const int slot = slot_of(j);
         return slot >= 0 ? c.s_post[slot * Z + (v - j * Z)] : at(c.Lp, v);
     };
-    auto syn_bit = [&](int r) -> int { return int(s_synb[r >> 5] >> (r & 31)) & 1; };
+    auto syn_bit = [&](int r) -> int { return int(syn_word(r >> 5) >> (r & 31)) & 1; };
     for (int w = tid; w < (n + 31) / 32; w += NT) lc.s_hard[w] = 0u;
-    // Bob's syndrome of the frame as a bit array in LDS (read once)
+    // Bob's syndrome of the frame as a bit array (read once)
     for (int w = tid; w < (m + 31) / 32; w += NT) {
         uint32_t bits = 0u;
         if (syn) {
@@ -1588,7 +1595,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
                 const int i = zsh >= 0 ? (u >> (zsh - 5)) : u / W;
                 const int k0 = (u - i * W) << 5;
                 const int q1 = s_rptr[i + 1];
-                uint32_t par = s_synb[u];
+                uint32_t par = syn_word(u);
                 for (int q = s_rptr[i]; q < q1; ++q) {
                     int st = k0 + (c.s_row[q] & 0xffff);
                     st = st >= Z ? st - Z : st;
@@ -1631,13 +1638,20 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
             const int i0 = s_grp[g];
             const int rows = (s_grp[g + 1] - i0) * Z;
             for (int r = tid; r < rows; r += NT) {
-                const int di = zsh >= 0 ? (r >> zsh) : r / Z;       // wave-uniform (Z % 64 == 0 or one block row)
+                const int di = zsh >= 0 ? (r >> zsh) : r / Z;
                 const int k = r - di * Z;
                 const int i = i0 + di;
-                const int q0 = __builtin_amdgcn_readfirstlane(s_rptr[i]);
-                const int d = __builtin_amdgcn_readfirstlane(s_rptr[i + 1]) - q0;
-                const int kk[1] = {k}, ss[1] = {syn_bit(i * Z + k)};
-                layer_rows_d<M, S, ALGO, MAXD, CACHE, 1>(c, lc, q0, d, kk, ss);
+                if (Z % 64 == 0) {
+                    // a wavefront's 64 rows lie in one block row: exact-degree bodies
+                    const int q0 = __builtin_amdgcn_readfirstlane(s_rptr[i]);
+                    const int d = __builtin_amdgcn_readfirstlane(s_rptr[i + 1]) - q0;
+                    const int kk[1] = {k}, ss[1] = {syn_bit(i * Z + k)};
+                    layer_rows_d<M, S, ALGO, MAXD, CACHE, 1>(c, lc, q0, d, kk, ss);
+                } else {
+                    // a wavefront spans block rows: the masked body, per-lane tables
+                    const int q0 = s_rptr[i];
+                    layer_row_any<M, S, ALGO, MAXD, CACHE, false>(c, lc, q0, s_rptr[i + 1] - q0, k, syn_bit(i * Z + k));
+                }
             }
             __syncthreads();
         }
@@ -1995,14 +2009,18 @@ static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue
     for (const cvr_code_t c : b->codes) max_n = std::max<int64_t>(max_n, c->dev.n);
     int64_t max_m = 0;
     for (const cvr_code_t c : b->codes) max_m = std::max<int64_t>(max_m, int64_t(c->dev.mb) * c->dev.Z);
+    // the syndrome bits go to the workspace when the tables, the decision bits
+    // and they do not fit in LDS together
+    bool syn_lds = true;
     auto map = [&](int cache_bytes) {
         LdsMap lm = lds_map(b, cache_bytes);
         lm.hard = lm.cache;
-        lm.synb = int32_t(lm.hard + (max_n + 31) / 32);
-        lm.grp = int32_t(lm.synb + (max_m + 31) / 32);
+        lm.synb = syn_lds ? int32_t(lm.hard + (max_n + 31) / 32) : -1;
+        lm.grp = int32_t(lm.hard + (max_n + 31) / 32 + (syn_lds ? (max_m + 31) / 32 : 0));
         lm.cache = int32_t((lm.grp + kMaxLdsDim + 2 + 3) / 4 * 4);
         return lm;
     };
+    if (lds_blk - static_lds - map(0).cache * 4 < 0) syn_lds = false;
     const int tab = map(0).cache * 4;
     const int room = lds_blk - static_lds - tab;
     if (room < 0) return fail(CVR_EUNSUPPORTED, "decode (layered): code tables and decision bits exceed LDS");
@@ -2077,7 +2095,7 @@ static inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 static inline size_t msize(int32_t p) { return p == CVR_F64 ? 8 : (p == CVR_F32 ? 4 : 2); }
 
 struct WsLayout {
-    size_t c2v, post, active, unsat, queue, grid, total;
+    size_t c2v, post, active, unsat, queue, grid, synw, total;
 };
 
 static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
@@ -2096,6 +2114,8 @@ static inline WsLayout layout(const cvr_batch_s* b, const cvr_decode_params* p)
     off = align256(off + 4);
     w.grid = off;               // group schedule: see k_group_qc
     off = align256(off + kGroupWsBytes);
+    w.synw = off;               // layered schedule: syndrome bits of frames whose bits exceed LDS
+    if (p->schedule == CVR_SCHED_LAYERED) off = align256(off + size_t((b->total_m + 31) / 32 + b->F + 1) * 4);
     w.total = off;
     return w;
 }

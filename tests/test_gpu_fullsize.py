@@ -344,13 +344,16 @@ def _sweep_sampled(R, n, j, qc, syn, out, frames, kind):
     return margin
 
 
-@pytest.mark.parametrize("n,kind", [(1 << 18, "flooding"), (1 << 18, "layered"), (1 << 20, "group")])
+@pytest.mark.parametrize("n,kind", [(1 << 18, "flooding"), (1 << 18, "layered"), (1 << 20, "group"),
+                                    (1 << 20, "layered")])
 def test_sweep_sub_block_sizes_sampled_against_oracle(recon_2p27, n, kind):
     """The block-size sweep's large sub-blocks over the same 2^27 pairs:
     n_R = 2^18 (512 sub-blocks per slice, Z = 2048) with flooding sum-product
     on the persistent kernel and with layered sum-product, and n_R = 2^20
     (128 sub-blocks, Z = 8192) on the group schedule (fewer sub-blocks than
-    CUs: a group of workgroups on one XCD per sub-block).  Each decode runs in
+    CUs: a group of workgroups on one XCD per sub-block) and on the layered
+    schedule (its decision bits fill the LDS, Bob's syndrome bits live in the
+    workspace).  Each decode runs in
     every shape its autotuner picks from (bit-identical), both coded slices
     (slice 3 given Bob's slice 2); two sampled sub-blocks per slice against
     the oracle."""

@@ -244,6 +244,39 @@ def test_layered_learned_weights_bit_exact():
     assert ref["ok"].sum() >= 1
 
 
+@pytest.mark.parametrize("n", [4096, 5120])
+def test_layered_wavefronts_spanning_block_rows(n):
+    """Z = 32 and Z = 40 (Z % 64 != 0): a wavefront's 64 rows span block rows of
+    one layer group, so each lane reads its own table entries (masked body);
+    at Z = 40 the syndrome test also runs one row per thread (Z % 32 != 0).
+    Min-sum with binary16 messages bit-exact against the binary32 layered
+    oracle at every iteration, in every workgroup size; sum-product in fp64
+    within 1e-12 of the scale at every iteration."""
+    print(f"[layered Z={n // 128}]", flush=True)
+    qc = inputs.lambda_half_rate_spec(n)
+    csr = qc.to_csr()
+    F = 6
+    llr, syn = _bpsk(qc, F, seed=n + 3)
+    code = api.Code.from_qc(qc)
+    ref = _layered(qc, csr, llr.astype(np.float32).astype(np.float64), syn, algo=oracle.NMS,
+                   alpha=float(np.float32(0.8)), max_iter=30, trace=True, store_half=True, prec32=True)
+    for wg in (0, 256, 1024):
+        p = api.Params(algo=api.NMS, max_iter=30, math=api.F32, store=api.F16, alpha=0.8, schedule=api.SCHED_LAYERED,
+                       wg_threads=wg)
+        res = _decode(code, F, llr, syn, p, trace=True)
+        np.testing.assert_array_equal(res["iters"], ref["iters"])
+        np.testing.assert_array_equal(res["ok"], ref["ok"])
+        np.testing.assert_array_equal(res["bits"].reshape(F, -1), ref["bits"])
+        for f in range(F):
+            t = int(ref["iters"][f])
+            np.testing.assert_array_equal(res["trace"][f, : t + 1].astype(np.float64), ref["post_trace"][f, : t + 1])
+    assert ref["ok"].sum() >= F // 2
+    p = api.Params(algo=api.SP, max_iter=40, math=api.F64, store=api.F64, schedule=api.SCHED_LAYERED)
+    res = _decode(code, F, llr, syn, p, trace=True)
+    ref = _layered(qc, csr, llr, syn, algo=oracle.SP, max_iter=40, trace=True)
+    _check_margin_frames(csr, res, ref, F, n, syn, 1e-12, 0.8)
+
+
 @pytest.mark.parametrize("Z", [384, 1536, 2048])
 def test_layered_launch_shapes_are_bit_identical(Z):
     """Workgroups of 256, 512 and 1024 threads (one, two or four rows of a
