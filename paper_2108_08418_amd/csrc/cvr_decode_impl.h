@@ -1508,12 +1508,14 @@ __device__ __forceinline__ void layer_rows_d(const FrameCtx<M, S>& c, const Laye
     }
 }
 
-// One frame, all iterations, on the layered schedule.
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool CACHE>
+// One frame, all iterations, on the layered schedule.  SYNL: Bob's syndrome
+// bits in LDS (else in the workspace, when LDS is short).
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool SYNL>
 __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const LdsMap& lm, int32_t* dsm,
                                                      int32_t (&s_unsat)[2], int32_t& s_nan, float (&s_w)[kMaxTypes],
                                                      int f, const DevFrame& fr, const DevCode& cd)
 {
+    constexpr bool CACHE = true;
     const int tid = int(threadIdx.x);
     const int Z = cd.Z;
     const int m = cd.mb * Z, n = cd.nb * Z;
@@ -1535,10 +1537,10 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
     c.clamp = a.clamp;
     LayerCtx lc{dsm + lm.col, reinterpret_cast<uint32_t*>(dsm + lm.hard), &s_nan};
     // Bob's syndrome bits: in LDS, or in the workspace when LDS is short
-    const bool syn_lds = lm.synb >= 0;
-    uint32_t* s_synb = syn_lds ? reinterpret_cast<uint32_t*>(dsm + lm.synb) : a.synw + ((fr.chk_off >> 5) + f);
+    uint32_t* s_synb = SYNL ? reinterpret_cast<uint32_t*>(dsm + lm.synb) : a.synw + ((fr.chk_off >> 5) + f);
     auto syn_word = [&](int w) -> uint32_t {
-        return syn_lds ? lds_read(s_synb + w) : *(const __attribute__((address_space(1))) uint32_t*)(s_synb + w);
+        if constexpr (SYNL) return lds_read(s_synb + w);
+        else return *(const __attribute__((address_space(1))) uint32_t*)(s_synb + w);
     };
     const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
     M* tr = a.trace ? static_cast<M*>(a.trace) + fr.vn_off : nullptr;
@@ -1673,7 +1675,7 @@ __device__ __forceinline__ void decode_frame_layered(const DecArgs& a, const Lds
     }
 }
 
-template <typename M, typename S, int ALGO, int MAXD, int NT, bool CACHE>
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool SYNL>
 __global__ __launch_bounds__(NT, MAXD <= 8 ? 4 : 1) void k_layered_qc(DecArgs a, LdsMap lm, int32_t* queue, int32_t F,
                                                    const int32_t* order)
 {
@@ -1698,7 +1700,7 @@ __global__ __launch_bounds__(NT, MAXD <= 8 ? 4 : 1) void k_layered_qc(DecArgs a,
             load_layer_tables<M, NT>(lm, dsm, cd);
             cur = fr.code;
         }
-        decode_frame_layered<M, S, ALGO, MAXD, NT, CACHE>(a, lm, dsm, s_unsat, s_nan, s_w, f, fr, cd);
+        decode_frame_layered<M, S, ALGO, MAXD, NT, SYNL>(a, lm, dsm, s_unsat, s_nan, s_w, f, fr, cd);
         __syncthreads();
     }
 }
@@ -1989,12 +1991,13 @@ static cvr_status run_group(const cvr_batch_s* b, DecArgs a, hipStream_t s, int3
 
 // Layered schedule (QC codes whose tables fit in LDS): one workgroup per frame
 // from the frame queue; NT threads (256, 512 or 1024); the LDS left after the
-// tables and the hard-decision bits caches posteriors (lds_kb as for the
-// persistent decoder).
-template <typename M, typename S, int ALGO, int MAXD, int NT>
-static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int lds_kb)
+// tables and the decision bits (and the syndrome bits when they fit as well)
+// caches posteriors (lds_kb as for the persistent decoder).
+template <typename M, typename S, int ALGO, int MAXD, int NT, bool SYNL>
+static cvr_status launch_layered_as(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int lds_kb,
+                                    int64_t max_n, int64_t max_m)
 {
-    auto kern = k_layered_qc<M, S, ALGO, MAXD, NT, true>;
+    auto kern = k_layered_qc<M, S, ALGO, MAXD, NT, SYNL>;
     static int lds_blk = 0, lds_cu = 0, static_lds = 0;
     if (lds_blk == 0) {
         lds_cu = device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 65536);
@@ -2005,25 +2008,21 @@ static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   lds_blk - static_lds);
     }
-    int64_t max_n = 0;
-    for (const cvr_code_t c : b->codes) max_n = std::max<int64_t>(max_n, c->dev.n);
-    int64_t max_m = 0;
-    for (const cvr_code_t c : b->codes) max_m = std::max<int64_t>(max_m, int64_t(c->dev.mb) * c->dev.Z);
-    // the syndrome bits go to the workspace when the tables, the decision bits
-    // and they do not fit in LDS together
-    bool syn_lds = true;
     auto map = [&](int cache_bytes) {
         LdsMap lm = lds_map(b, cache_bytes);
         lm.hard = lm.cache;
-        lm.synb = syn_lds ? int32_t(lm.hard + (max_n + 31) / 32) : -1;
-        lm.grp = int32_t(lm.hard + (max_n + 31) / 32 + (syn_lds ? (max_m + 31) / 32 : 0));
+        lm.synb = SYNL ? int32_t(lm.hard + (max_n + 31) / 32) : -1;
+        lm.grp = int32_t(lm.hard + (max_n + 31) / 32 + (SYNL ? (max_m + 31) / 32 : 0));
         lm.cache = int32_t((lm.grp + kMaxLdsDim + 2 + 3) / 4 * 4);
         return lm;
     };
-    if (lds_blk - static_lds - map(0).cache * 4 < 0) syn_lds = false;
     const int tab = map(0).cache * 4;
     const int room = lds_blk - static_lds - tab;
-    if (room < 0) return fail(CVR_EUNSUPPORTED, "decode (layered): code tables and decision bits exceed LDS");
+    if (room < 0) {
+        if constexpr (SYNL)   // the syndrome bits go to the workspace
+            return launch_layered_as<M, S, ALGO, MAXD, NT, false>(b, a, queue, s, lds_kb, max_n, max_m);
+        return fail(CVR_EUNSUPPORTED, "decode (layered): code tables and decision bits exceed LDS");
+    }
     auto occupancy = [&](int dyn) {
         int v = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kern, NT, size_t(dyn)) != hipSuccess || v < 1) v = 1;
@@ -2045,6 +2044,17 @@ static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue
     ProfScope prof(CVR_PROF_FRAMES, s);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), size_t(dyn), s, a, lm, queue, b->F, b->d_order);
     return check_launch("decode (layered)");
+}
+
+template <typename M, typename S, int ALGO, int MAXD, int NT>
+static cvr_status launch_layered(const cvr_batch_s* b, DecArgs a, int32_t* queue, hipStream_t s, int lds_kb)
+{
+    int64_t max_n = 0, max_m = 0;
+    for (const cvr_code_t c : b->codes) {
+        max_n = std::max<int64_t>(max_n, c->dev.n);
+        max_m = std::max<int64_t>(max_m, int64_t(c->dev.mb) * c->dev.Z);
+    }
+    return launch_layered_as<M, S, ALGO, MAXD, NT, true>(b, a, queue, s, lds_kb, max_n, max_m);
 }
 
 template <typename M, typename S, int ALGO, int MAXD>

@@ -7,8 +7,9 @@
 //
 // Backward, per frame and per segment [t0, t1) from the last one down:
 //   recompute c2v(t0+1 .. t1-1) from the checkpoint c2v(t0) (same arithmetic as
-//   the forward), then for t = t1-1 .. t0:
-//     L(t)  = L_ch + sum_e c2v(t)                               (recomputed)
+//   the forward, keeping the posteriors L(t0 .. t1-2) it forms on the way),
+//   then for t = t1-1 .. t0:
+//     L(t)  = L_ch + sum_e c2v(t)                   (kept, or formed for t1-1)
 //     v2c_e = L(t) - c2v(t)_e                                   (as the forward)
 //     through c2v(t+1)_e = w[t][type_e] * s_e * M_e with s_e the syndrome-and-
 //       sign product over the other edges and M_e = min_{k != e} |v2c_k|:
@@ -41,7 +42,8 @@ struct GradArgs {
     float* slots;              // [K - 1][stride]: c2v(t0 + 1 .. t0 + K - 1)
     float* G;                  // [stride]: dl/dc2v
     float* GV;                 // [stride]: dl/dv2c
-    float* Lp;                 // [total_n]
+    float* Lp;                 // [K][lstride]: L(t0 .. t0 + K - 1) of the current segment
+    int64_t lstride;           // total_n
     float* partials;           // [gridDim.x][T][n_types]
     int32_t T, K, n_types, F;
 };
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
         const int m = cd.mb * Z, n = cd.nb * Z;
         const int zsh = (Z & (Z - 1)) == 0 ? __ffs(Z) - 1 : -1;
         const float* Lc = a.llr + fr.vn_off;
-        float* Lp = a.Lp + fr.vn_off;
+        float* Lbase = a.Lp + fr.vn_off;
         const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
         float* G = a.G + fr.msg_off;
         float* GV = a.GV + fr.msg_off;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
             return uni<WU>(e.y) * Z + k;
         };
         // L = L_ch + sum of c2v, block rows ascending (the forward's order)
-        auto posterior = [&](const float* c2v) {
+        auto posterior = [&](const float* c2v, float* Lp) {
             for (int v = tid; v < n; v += NT) {
                 int qa, dv, u;
                 var_of(v, qa, dv, u);
@@ -139,7 +141,8 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
         // posteriors and messages of a row, and (with gp) the adjoints of its
         // messages, all loaded first; then the incoming v2c as the forward forms
         // it (L_post - c2v; the checkpoint at t = 0 holds zeros)
-        auto row_inputs = [&](const float* c2v, int q0, int d, int k, float (&x)[MAXD], float* gp, float (&g)[MAXD]) {
+        auto row_inputs = [&](const float* c2v, const float* Lp, int q0, int d, int k, float (&x)[MAXD], float* gp,
+                              float (&g)[MAXD]) {
             float lp[MAXD], cv[MAXD];
 #pragma unroll
             for (int q = 0; q < MAXD; ++q) {
@@ -178,11 +181,12 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
             auto c2v_at = [&](int t) -> const float* {
                 return t == t0 ? ck : a.slots + int64_t(t - t0 - 1) * a.stride + fr.msg_off;
             };
-            // recompute c2v(t0 + 1 .. t1 - 1)
+            auto L_at = [&](int t) -> float* { return Lbase + int64_t(t - t0) * a.lstride; };
+            // recompute c2v(t0 + 1 .. t1 - 1), keeping L(t0 .. t1 - 2) for the reverse sweep
             for (int t = t0; t < t1 - 1; ++t) {
                 const float* cin = c2v_at(t);
                 float* cout = a.slots + int64_t(t - t0) * a.stride + fr.msg_off;
-                posterior(cin);
+                posterior(cin, L_at(t));
                 __syncthreads();
                 const float* wt = a.weights + int64_t(t) * a.n_types;
                 for (int r = tid; r < m; r += NT) {
@@ -190,18 +194,21 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                     row_of(r, q0, d, k);
                     const int sbit = syn ? (syn[r] & 1) : 0;
                     float x[MAXD], unused[MAXD];
-                    row_inputs(cin, q0, d, k, x, nullptr, unused);
+                    row_inputs(cin, L_at(t), q0, d, k, x, nullptr, unused);
                     auto weight = [&](int q) -> float { return wt[uni<WU>(sc.row[q0 + q].y >> 20)]; };
                     auto emit = [&](int q, float v) { cout[(q0 + q) * Z + k] = v; };
                     check_rule<float, CVR_NMS, MAXD>(x, d, sbit, 0.0f, weight, emit);
                 }
                 __syncthreads();
             }
-            // reverse through t = t1 - 1 .. t0
+            // reverse through t = t1 - 1 .. t0 (L(t1 - 1) is the one posterior
+            // the recomputation did not form)
             for (int t = t1 - 1; t >= t0; --t) {
                 const float* cin = c2v_at(t);
-                posterior(cin);
-                __syncthreads();
+                if (t == t1 - 1) {
+                    posterior(cin, L_at(t));
+                    __syncthreads();
+                }
                 const float* wt = a.weights + int64_t(t) * a.n_types;
                 float acc[kGradTypes] = {0.0f, 0.0f, 0.0f, 0.0f};
                 for (int r = tid; r < m; r += NT) {
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                     row_of(r, q0, d, k);
                     const int sbit = syn ? (syn[r] & 1) : 0;
                     float x[MAXD], g[MAXD];
-                    row_inputs(cin, q0, d, k, x, G, g);
+                    row_inputs(cin, L_at(t), q0, d, k, x, G, g);
                     // signs, and the smallest and second smallest |x| with their
                     // first positions (branch-free, the forward's tie rule)
                     uint32_t negm = 0;
@@ -398,7 +405,7 @@ static UnrolledLayout unrolled_layout(const cvr_batch_s* b, int32_t T, int32_t K
     u.GV = off;
     off = align256(off + size_t(b->total_E) * 4);
     u.Lp = off;
-    off = align256(off + size_t(b->total_n) * 4);
+    off = align256(off + size_t(std::max<int32_t>(std::min<int32_t>(K, T), 1)) * size_t(b->total_n) * 4);
     u.partials = off;
     off = align256(off + size_t(std::max<int32_t>(b->F, 1)) * size_t(T) * size_t(b->max_types) * 4);
     u.total_bwd = off;
@@ -498,6 +505,7 @@ extern "C" cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckp
     g.G = reinterpret_cast<float*>(ws + u.G);
     g.GV = reinterpret_cast<float*>(ws + u.GV);
     g.Lp = reinterpret_cast<float*>(ws + u.Lp);
+    g.lstride = batch->total_n;
     g.partials = reinterpret_cast<float*>(ws + u.partials);
     g.T = T;
     g.K = ckpt_every;
