@@ -5,9 +5,10 @@ properties checked on every frame.
 * 2^27 Gaussian pairs at SNR 3 (16 equiprobable levels, 2048 sub-blocks of
   2^16 per coded slice): the benchmark's two-stage chain (slice 2 decoded,
   slice 3's LLRs picked by the decoded bits, slice 3 decoded) with each of
-  the benchmark's three decoders: sum-product on the layered schedule (the
+  the benchmark's four decoders: sum-product on the layered schedule (the
   headline), flooding sum-product (persistent kernel at 1024 threads) and
-  learned min-sum with binary16 messages (flooding, persistent kernel).
+  learned min-sum with binary16 messages on the flooding (persistent kernel)
+  and on the layered schedule.
 * The uneven batch: 4096 sub-blocks of the rate-0.0625 MET code at SNR 0.16
   (2176 x 4096, 1024 x 16384, 640 x 65536, 256 x 262144 bits), min-sum
   alpha 0.75 with binary16 messages, persistent kernel at 1024 threads.
@@ -284,6 +285,32 @@ def test_recon_2p27_learned_min_sum_chain_bit_exact(recon_2p27):
     ref = lambda j, csr, L, s: oracle.decode(csr, L.astype(np.float32).astype(np.float64)[None, :], s,
                                              algo=oracle.NMS, weights=w[j].astype(np.float64),
                                              max_iter=int(w[j].shape[0]), store_half=True, prec32=True)
+    chk = lambda j, csr, r, f, rj, s: _check_exact(r, f, rj["iters"], rj["ok"], rj["bits"], rj["post"])
+    exact = _follow_sampled(R, res, ref, chk)
+    assert exact[2] == len(R["frames"]) and exact[3] == len(R["frames"]), exact
+
+
+def test_recon_2p27_learned_min_sum_layered_chain_bit_exact(recon_2p27):
+    """The benchmark's learned min-sum on the layered schedule at 2^27 pairs
+    (binary16 messages, the per-iteration, per-edge-type weights of each slice
+    code), in the launch shapes its autotuner picks from (1024, 512 and 256
+    threads per frame; LDS posterior cache automatic, full or off), all
+    bit-identical.  16 sampled sub-blocks followed through the oracle's chain
+    with its binary32 layered min-sum (same weights, binary16 storage):
+    iteration counts, status, decisions and posteriors bit for bit."""
+    print("[full size: 2^27 pairs, slices 2 and 3, learned NMS f16, layered]", flush=True)
+    from paper_2108_08418_amd.train import load_weights
+    R = recon_2p27
+    w = {j: load_weights(f"learned_slice{j}", extend_to=100) for j in (2, 3)}
+    kws = {j: dict(algo=api.NMS, max_iter=int(w[j].shape[0]), math=api.F32, store=api.F16, weights=_g(w[j]))
+           for j in (2, 3)}
+    shapes = [dict(wg_threads=1024, lds_cache_kb=0), dict(wg_threads=512, lds_cache_kb=0),
+              dict(wg_threads=256, lds_cache_kb=-1), dict(wg_threads=512, lds_cache_kb=150)]
+    res = _run_chain(R, kws[2], shapes, schedule=api.SCHED_LAYERED, kw3=kws[3])
+    lay = {j: oracle.qc_layers(R["qcs"][j].mb, R["qcs"][j].Z) for j in (2, 3)}
+    ref = lambda j, csr, L, s: oracle.decode_layered(csr, L.astype(np.float32).astype(np.float64)[None, :], s,
+                                                     layers=lay[j], algo=oracle.NMS, weights=w[j].astype(np.float64),
+                                                     max_iter=int(w[j].shape[0]), store_half=True, prec32=True)
     chk = lambda j, csr, r, f, rj, s: _check_exact(r, f, rj["iters"], rj["ok"], rj["bits"], rj["post"])
     exact = _follow_sampled(R, res, ref, chk)
     assert exact[2] == len(R["frames"]) and exact[3] == len(R["frames"]), exact
