@@ -12,11 +12,16 @@ import pytest
 
 from paper_2108_08418_amd import keyrate as kr
 
-GAMMA = 2.2147                       # the paper's standard settings (gamma from its SNR equation)
-N = 1e9
-M_BITS = 5
-E_EC = E_PA = E_PE = 2.5e-10
-E_S = 1.25e-10
+import json
+from pathlib import Path
+
+# the paper's standard settings and its reported optimum (Sec. V), as printed
+GOLDEN = json.loads((Path(__file__).parent / "golden" / "paper_standard_settings.json").read_text())
+GAMMA = 2.2147                       # the SNR of the standard settings (gamma from the paper's SNR equation)
+N = GOLDEN["N"]
+M_BITS = GOLDEN["m_slices"]
+E_EC, E_PA, E_PE = GOLDEN["eps_EC"], GOLDEN["eps_PA"], GOLDEN["eps_PE"]
+E_S = GOLDEN["eps_s"]
 EPS = E_EC + 2 * E_S + E_PA + E_PE
 LAM = {2: 0.25, 3: 0.3, 8: 0.45}
 
@@ -25,7 +30,7 @@ def _setup(S_BE):
     I = kr.capacity(GAMMA)
     A = kr.dispersion(GAMMA)
     B1 = kr.b1(N, S_BE, kr.delta_aep(M_BITS, N, E_S, EPS), E_PA)
-    B2 = kr.b2(3.2e-9, [20] * M_BITS, [LAM] * M_BITS)
+    B2 = kr.b2(GOLDEN["c_h_seconds_per_operation"], [20] * M_BITS, [LAM] * M_BITS)
     return I, A, B1, B2
 
 
@@ -76,7 +81,7 @@ def test_leading_order_optimum_and_the_papers_value():
     r, _ = kr.optimal_nr(N, I, A, E_EC, B1, B2)
     lead = (3 * math.sqrt(A) * kr.q_inv(E_EC) / (2 * 1.5e-3)) ** 2
     assert abs(r / lead - 1) < 0.05, (r, lead)
-    assert abs(r / 3.6e7 - 1) < 0.1, r
+    assert abs(r / GOLDEN["optimal_sub_block_length_N_R"] - 1) < 0.1, r
     # N_R* does not depend on the hardware constant c_h or on the iteration counts (B_2 scales K')
     r2, _ = kr.optimal_nr(N, I, A, E_EC, B1, B2 * 1e-4)
     assert abs(r2 / r - 1) < 1e-9
