@@ -753,8 +753,10 @@ def ragged(args, wl, dev):
         syn[cidx] = s_c.view(-1)
     algo = api.SP if args.decoder == "sp" else api.NMS
     store = api.F32 if args.decoder == "sp" else api.F16
+    layered = args.schedule == "layered"
     params = api.Params(algo=algo, max_iter=args.max_iter, math=api.F32, store=store, alpha=args.alpha,
-                        wg_threads=args.wg, min_waves=args.min_waves, lds_cache_kb=args.lds_cache_kb)
+                        wg_threads=args.wg, min_waves=args.min_waves, lds_cache_kb=args.lds_cache_kb,
+                        schedule=api.SCHED_LAYERED if layered else api.SCHED_AUTO)
     ws = api.alloc_workspace(batch, params, dev)
     out = dict(bits=torch.empty(total_n, dtype=torch.uint8, device=dev), post=None,
                iters=torch.empty(F, dtype=torch.int32, device=dev), ok=torch.empty(F, dtype=torch.uint8, device=dev))
@@ -766,11 +768,13 @@ def ragged(args, wl, dev):
 
     tuned = None
     if not args.no_tune and args.wg == 0:
-        from paper_2108_08418_amd.tune import tune_decode
-        best, tim = tune_decode(batch, params, llr, syn, ws, out)
-        params.wg_threads, params.min_waves, params.lds_cache_kb = best
-        args.wg, args.min_waves, args.lds_cache_kb = best
-        tuned = {f"wg_threads={k[0]}/min_waves={k[1]}/lds_cache_kb={k[2]}": round(v, 3) for k, v in tim.items()}
+        from paper_2108_08418_amd import tune
+        knobs, cands = ((tune.LAYERED_KNOBS, tune.LAYERED_CANDIDATES) if layered else (tune.KNOBS, tune.CANDIDATES))
+        best, tim = tune.tune_decode(batch, params, llr, syn, ws, out, candidates=cands, knobs=knobs)
+        for k, v in zip(knobs, best):
+            setattr(params, k, v)
+            setattr(args, {"wg_threads": "wg", "min_waves": "min_waves", "lds_cache_kb": "lds_cache_kb"}[k], v)
+        tuned = {"/".join(f"{k}={v}" for k, v in zip(knobs, c)): round(t, 3) for c, t in tim.items()}
         print(f"# tuned: {best} {tuned}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -804,19 +808,22 @@ def ragged(args, wl, dev):
     fer = {}
     for c, q in enumerate(qcs):
         sel = order == c
-        dec_bytes += frame_decode_bytes(iters[sel], q.n, q.m, q.n_edges, s_msg)
+        dec_bytes += (layered_decode_bytes if layered else frame_decode_bytes)(iters[sel], q.n, q.m, q.n_edges, s_msg)
         fer[str(sizes[c])] = float(1.0 - ok[sel].mean())
     achieved = (args.steps * dec_bytes) / (per_ms * 1e-3) / 1e9 if per_ms > 0 else None
     if achieved is None:                  # graph replay: whole step timed by the host clock
         achieved = (args.steps * dec_bytes) / t_total / 1e9
     wg = args.wg or 512
     mt = "float, float" if store == api.F32 else "float, __half"
-    inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
-            f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
+    if layered:
+        inst = f"void cvr::k_layered_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true>"
+    else:
+        inst = (f"void cvr::k_frames_qc<{mt}, {0 if algo == api.SP else 1}, 8, {wg}, true, "
+                f"{8 if args.min_waves == 8 else 1}, {'false' if args.lds_cache_kb < 0 else 'true'}>")
     traffic, traffic_src = recorded_traffic(inst, args.workload, args.decoder, args.weights)
     value = total_n / (t_total / args.steps)
     result = {
-        "metric": "decoded bits/s of a batch of uneven sub-blocks (one persistent launch)",
+        "metric": "decoded bits/s of a batch of uneven sub-blocks (one launch)",
         "value": value, "unit": "bits/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * t_total / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if store == api.F32 else "f32 math / f16 messages",
@@ -824,7 +831,8 @@ def ragged(args, wl, dev):
         "config": {"workload": args.workload, "frames": F, "total_bits": total_n,
                    "sizes": list(sizes), "counts": list(counts), "code_rate": 0.0625,
                    "decoder": ("sum-product" if algo == api.SP else f"normalized min-sum alpha={args.alpha}"),
-                   "max_iter": args.max_iter, "graph": bool(args.graph), "wg_threads": wg, "lds_cache_kb": args.lds_cache_kb,
+                   "max_iter": args.max_iter, "graph": bool(args.graph), "schedule": "layered" if layered else "auto",
+                   "wg_threads": wg, "lds_cache_kb": args.lds_cache_kb,
                    "min_waves": args.min_waves,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": inst, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -395,6 +395,7 @@ def met_low_rate_spec(n: int, seed: int = 16) -> QcCode:
     of a core bit) or two (24 rows: a parity of two core bits) core columns,
     spread evenly over the core.  Rate (16 - 12) / 64 = 0.0625.  Edge types:
     0 = core checks, 1 = extension checks to the core, 2 = degree-1 edges.
+    Block rows are listed in ``layer_order`` (9 runs of column-disjoint rows).
     Rates 5/64 and 6/64 of this family did not decode at SNR 0.16 (n = 16384),
     4/64 did (no failure in 16 frames).  The protograph
     depends on ``seed`` only, the circulant shifts on (seed, Z).
@@ -420,6 +421,8 @@ def met_low_rate_spec(n: int, seed: int = 16) -> QcCode:
         base[mc + r, n_core + r] = 1
         btype[mc + r, n_core + r] = 2
     shift = _assign_shifts(base, Z, np.random.default_rng([seed, Z]))
+    order = layer_order(base)
+    shift, btype = shift[order], btype[order]
     btype = np.where(shift >= 0, btype, 0).astype(np.uint8)
     return QcCode(nb, mb, Z, shift.astype(np.int32), btype, 3, name=f"met-r0.0625-qc n{n}")
 
