@@ -411,8 +411,15 @@ def test_sweep_sub_block_sizes_sampled_against_oracle(recon_2p27, n, kind):
         del out
 
 
-def test_uneven_met_batch_4096_frames_sampled_against_oracle():
-    print("[full size: 4096 uneven MET frames, min-sum f16, persistent 1024 threads]", flush=True)
+@pytest.mark.parametrize("layered", [False, True])
+def test_uneven_met_batch_4096_frames_sampled_against_oracle(layered):
+    """The uneven batch in one launch, on the flooding schedule (persistent
+    kernel at 1024 threads) and on the layered schedule, in the shapes the
+    autotuner picks from (bit-identical); every frame: ok <=> its decisions
+    satisfy its syndrome; the first and last frame of each size bit-exact
+    against the oracle's binary32 min-sum of the same schedule."""
+    print(f"[full size: 4096 uneven MET frames, min-sum f16, {'layered' if layered else 'persistent 1024 threads'}]",
+          flush=True)
     sizes, counts = (4096, 16384, 65536, 262144), (2176, 1024, 640, 256)
     rng = np.random.default_rng(2108)
     order = rng.permutation(np.repeat(np.arange(len(sizes)), counts))
@@ -435,9 +442,13 @@ def test_uneven_met_batch_4096_frames_sampled_against_oracle():
         cidx = torch.cat([torch.arange(frames[i][2], frames[i][2] + q.m, device=DEV) for i in ids])
         s_c, _ = api.syndrome_check(codes[c], bits_g[vidx].contiguous(), want_unsat=False)
         syn[cidx] = s_c.view(-1)
-    out = _decode_in_shapes(batch, _g(llr), syn,
-                            dict(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75),
-                            [(0, 0), (0, 150), (8, -1)])
+    kw = dict(algo=api.NMS, max_iter=100, math=api.F32, store=api.F16, alpha=0.75)
+    if layered:
+        out = _decode_in_shapes(batch, _g(llr), syn, kw,
+                                [dict(wg_threads=1024, lds_cache_kb=0), dict(wg_threads=512, lds_cache_kb=0),
+                                 dict(wg_threads=256, lds_cache_kb=-1)], api.SCHED_LAYERED)
+    else:
+        out = _decode_in_shapes(batch, _g(llr), syn, kw, [(0, 0), (0, 150), (8, -1)])
     syn_np = syn.cpu().numpy()
     ok = out["ok"].cpu().numpy().astype(bool)
     iters = out["iters"].cpu().numpy()
@@ -459,9 +470,12 @@ def test_uneven_met_batch_4096_frames_sampled_against_oracle():
             n, m = sizes[c], qcs[c].m
             syn_f, _ = oracle.syndrome(csrs[c], bits[v0:v0 + n][None, :])
             np.testing.assert_array_equal(syn_np[c0:c0 + m], syn_f[0])
-            ref = oracle.decode(csrs[c], llr[v0:v0 + n][None, :].astype(np.float64), syn_f,
-                                algo=oracle.NMS, alpha=float(np.float32(0.75)), max_iter=100, store_half=True,
-                                prec32=True)
+            okw = dict(algo=oracle.NMS, alpha=float(np.float32(0.75)), max_iter=100, store_half=True, prec32=True)
+            if layered:
+                ref = oracle.decode_layered(csrs[c], llr[v0:v0 + n][None, :].astype(np.float64), syn_f,
+                                            layers=oracle.qc_layers(qcs[c].mb, qcs[c].Z), **okw)
+            else:
+                ref = oracle.decode(csrs[c], llr[v0:v0 + n][None, :].astype(np.float64), syn_f, **okw)
             assert int(iters[i]) == int(ref["iters"][0]), (i, n)
             assert int(ok[i]) == int(ref["ok"][0]), (i, n)
             np.testing.assert_array_equal(dec[v0:v0 + n], ref["bits"][0])
