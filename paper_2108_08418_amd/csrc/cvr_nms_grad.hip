@@ -17,7 +17,9 @@
 //         dl/dv2c_a += g_e w_e s_e sign(v2c_a), a = the lowest-index minimiser
 //         over k != e (min1's edge for every e but itself, min2's for it);
 //     through v2c_e = L_ch + sum_{e' != e} c2v(t)_{e'}:
-//         dl/dc2v(t)_{e'} = sum_{e != e'} dl/dv2c_e, dl/dL_ch += sum_e dl/dv2c_e.
+//         dl/dc2v(t)_{e'} = sum_{e != e'} dl/dv2c_e, dl/dL_ch += sum_e dl/dv2c_e;
+//         kept as the column sums S_v of dl/dv2c and dl/dv2c itself, the next
+//         step forming dl/dc2v_{e'} = S_v - dl/dv2c_{e'} as it reads its rows.
 // Sign products and the choice of minimiser are piecewise constant; |x| has
 // derivative sign(x) with sign(0) = +1.  Workgroups own fixed frame sets and
 // reduce the weight gradient in a fixed order (wave butterfly, waves in order,
@@ -40,7 +42,7 @@ struct GradArgs {
     const float* dpost;        // [total_n]
     float* dllr;               // [total_n] or NULL
     float* slots;              // [K - 1][stride]: c2v(t0 + 1 .. t0 + K - 1)
-    float* G;                  // [stride]: dl/dc2v
+    float* S;                  // [total_n]: column sums of dl/dv2c (so dl/dc2v_e = S[v(e)] - GV_e)
     float* GV;                 // [stride]: dl/dv2c
     float* Lp;                 // [K][lstride]: L(t0 .. t0 + K - 1) of the current segment
     int64_t lstride;           // total_n
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
         const float* Lc = a.llr + fr.vn_off;
         float* Lbase = a.Lp + fr.vn_off;
         const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
-        float* G = a.G + fr.msg_off;
+        float* S = a.S + fr.vn_off;
         float* GV = a.GV + fr.msg_off;
         const float* dpost = a.dpost + fr.vn_off;
         float* dllr = a.dllr ? a.dllr + fr.vn_off : nullptr;
@@ -138,38 +140,35 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                 Lp[v] = acc;
             }
         };
-        // posteriors and messages of a row, and (with gp) the adjoints of its
-        // messages, all loaded first; then the incoming v2c as the forward forms
-        // it (L_post - c2v; the checkpoint at t = 0 holds zeros)
-        auto row_inputs = [&](const float* c2v, const float* Lp, int q0, int d, int k, float (&x)[MAXD], float* gp,
-                              float (&g)[MAXD]) {
-            float lp[MAXD], cv[MAXD];
+        // posteriors and messages of a row and, with Sin, the adjoints of its
+        // messages dl/dc2v_e = Sin[v(e)] - GVin_e (GVin NULL: zero), all loaded
+        // first; then the incoming v2c as the forward forms it (L_post - c2v; the
+        // checkpoint at t = 0 holds zeros)
+        auto row_inputs = [&](const float* c2v, const float* Lp, int q0, int d, int k, float (&x)[MAXD],
+                              const float* Sin, const float* GVin, float (&g)[MAXD]) {
+            float lp[MAXD], cv[MAXD], sv[MAXD], gv[MAXD];
 #pragma unroll
             for (int q = 0; q < MAXD; ++q) {
                 lp[q] = 0.0f;
                 cv[q] = 0.0f;
-                g[q] = 0.0f;
+                sv[q] = 0.0f;
+                gv[q] = 0.0f;
                 if (q < d) {
-                    lp[q] = Lp[edge_var(q0 + q, k)];
+                    const int v = edge_var(q0 + q, k);
+                    lp[q] = Lp[v];
                     cv[q] = c2v[(q0 + q) * Z + k];
-                    if (gp) g[q] = gp[(q0 + q) * Z + k];
+                    if (Sin) sv[q] = Sin[v];
+                    if (GVin) gv[q] = GVin[(q0 + q) * Z + k];
                 }
             }
 #pragma unroll
             for (int q = 0; q < MAXD; ++q) x[q] = (q < d) ? opaque(lp[q]) - opaque(cv[q]) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < MAXD; ++q) g[q] = (q < d && Sin) ? opaque(sv[q]) - opaque(gv[q]) : 0.0f;
         };
 
-        // dl/dc2v(T) = dl/dL(T) on every edge; dl/dL_ch starts at dl/dL(T)
-        for (int r = tid; r < m; r += NT) {
-            int q0, d, k;
-            row_of(r, q0, d, k);
-            float dp[MAXD];
-#pragma unroll
-            for (int q = 0; q < MAXD; ++q) dp[q] = (q < d) ? dpost[edge_var(q0 + q, k)] : 0.0f;
-#pragma unroll
-            for (int q = 0; q < MAXD; ++q)
-                if (q < d) G[(q0 + q) * Z + k] = opaque(dp[q]);
-        }
+        // dl/dc2v(T)_e = dl/dL(T)_v(e): the first reverse step reads S = dl/dL(T)
+        // and no GV; dl/dL_ch starts at dl/dL(T)
         if (dllr)
             for (int v = tid; v < n; v += NT) dllr[v] = dpost[v];
         __syncthreads();
@@ -194,7 +193,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                     row_of(r, q0, d, k);
                     const int sbit = syn ? (syn[r] & 1) : 0;
                     float x[MAXD], unused[MAXD];
-                    row_inputs(cin, L_at(t), q0, d, k, x, nullptr, unused);
+                    row_inputs(cin, L_at(t), q0, d, k, x, nullptr, nullptr, unused);
                     auto weight = [&](int q) -> float { return wt[uni<WU>(sc.row[q0 + q].y >> 20)]; };
                     auto emit = [&](int q, float v) { cout[(q0 + q) * Z + k] = v; };
                     check_rule<float, CVR_NMS, MAXD>(x, d, sbit, 0.0f, weight, emit);
@@ -216,7 +215,8 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                     row_of(r, q0, d, k);
                     const int sbit = syn ? (syn[r] & 1) : 0;
                     float x[MAXD], g[MAXD];
-                    row_inputs(cin, L_at(t), q0, d, k, x, G, g);
+                    const bool first = seg == nseg - 1 && t == t1 - 1;
+                    row_inputs(cin, L_at(t), q0, d, k, x, first ? dpost : S, first ? nullptr : GV, g);
                     // signs, and the smallest and second smallest |x| with their
                     // first positions (branch-free, the forward's tie rule)
                     uint32_t negm = 0;
@@ -275,33 +275,23 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                         for (int w = 0; w < NT / 64; ++w) v += s_red[w][tt];
                         s_dw[t * kGradTypes + tt] += v;
                     }
-                // through the variable nodes: G = (sum of the column's GV) - GV
+                // through the variable nodes: S = the sum of the column's GV (the
+                // next reverse step forms dl/dc2v_e = S[v(e)] - GV_e from it)
                 for (int v = tid; v < n; v += NT) {
                     int qa, dv, u;
                     var_of(v, qa, dv, u);
                     float gsum = 0.0f;
                     if (dv <= 8) {
-                        int e[8];
                         float gv[8];
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) e[q] = (q < dv) ? col_edge(qa + q, u) : 0;
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) gv[q] = (q < dv) ? GV[e[q]] : 0.0f;
+                        for (int q = 0; q < 8; ++q) gv[q] = (q < dv) ? GV[col_edge(qa + q, u)] : 0.0f;
 #pragma unroll
                         for (int q = 0; q < 8; ++q)
                             if (q < dv) gsum += opaque(gv[q]);
-                        if (t > 0)
-#pragma unroll
-                            for (int q = 0; q < 8; ++q)
-                                if (q < dv) G[e[q]] = gsum - gv[q];
                     } else {
                         for (int q = 0; q < dv; ++q) gsum += GV[col_edge(qa + q, u)];
-                        if (t > 0)
-                            for (int q = 0; q < dv; ++q) {
-                                const int e = col_edge(qa + q, u);
-                                G[e] = gsum - GV[e];
-                            }
                     }
+                    if (t > 0) S[v] = gsum;
                     if (dllr) dllr[v] += gsum;
                 }
                 __syncthreads();
@@ -376,7 +366,7 @@ static cvr_status check_unrolled(const char* fn, const cvr_batch_s* b, int32_t T
 }
 
 struct UnrolledLayout {
-    size_t dec, bits, iters, ok, slots, G, GV, Lp, partials, total_fwd, total_bwd;
+    size_t dec, bits, iters, ok, slots, S, GV, Lp, partials, total_fwd, total_bwd;
 };
 
 static UnrolledLayout unrolled_layout(const cvr_batch_s* b, int32_t T, int32_t K)
@@ -400,8 +390,8 @@ static UnrolledLayout unrolled_layout(const cvr_batch_s* b, int32_t T, int32_t K
     off = 0;
     u.slots = off;
     off = align256(off + size_t(K > 1 ? K - 1 : 0) * size_t(b->total_E) * 4);
-    u.G = off;
-    off = align256(off + size_t(b->total_E) * 4);
+    u.S = off;
+    off = align256(off + size_t(b->total_n) * 4);
     u.GV = off;
     off = align256(off + size_t(b->total_E) * 4);
     u.Lp = off;
@@ -502,7 +492,7 @@ extern "C" cvr_status nms_unrolled_bwd(cvr_batch_t batch, int32_t T, int32_t ckp
     g.dpost = dloss_dpost;
     g.dllr = dllr;
     g.slots = reinterpret_cast<float*>(ws + u.slots);
-    g.G = reinterpret_cast<float*>(ws + u.G);
+    g.S = reinterpret_cast<float*>(ws + u.S);
     g.GV = reinterpret_cast<float*>(ws + u.GV);
     g.Lp = reinterpret_cast<float*>(ws + u.Lp);
     g.lstride = batch->total_n;
