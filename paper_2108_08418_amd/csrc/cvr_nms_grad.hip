@@ -42,7 +42,8 @@ struct GradArgs {
     const float* dpost;        // [total_n]
     float* dllr;               // [total_n] or NULL
     float* slots;              // [K - 1][stride]: c2v(t0 + 1 .. t0 + K - 1)
-    float* S;                  // [total_n]: column sums of dl/dv2c (so dl/dc2v_e = S[v(e)] - GV_e)
+    float* S;                  // [total_n]: column sums of dl/dv2c (so dl/dc2v_e = S[v(e)] - GV_e),
+                               // used when they do not fit in LDS
     float* GV;                 // [stride]: dl/dv2c
     float* Lp;                 // [K][lstride]: L(t0 .. t0 + K - 1) of the current segment
     int64_t lstride;           // total_n
@@ -62,9 +63,11 @@ struct LdsCode {
 // wavefront keeps them in flight together); with WU (Z % 64 == 0) the block
 // row / column of a wavefront, and so its degree and table entries, are
 // wave-uniform.
-template <int MAXD, bool WU, int NT>
+// SL: the column sums S of the frame in (dynamic) LDS, else in the workspace.
+template <int MAXD, bool WU, int NT, bool SL>
 __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
 {
+    extern __shared__ float s_S[];
     __shared__ LdsCode sc;
     __shared__ float s_red[NT / 64][kGradTypes];
     __shared__ float s_dw[kGradMaxT * kGradTypes];
@@ -94,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
         const float* Lc = a.llr + fr.vn_off;
         float* Lbase = a.Lp + fr.vn_off;
         const uint8_t* syn = a.syn ? a.syn + fr.chk_off : nullptr;
-        float* S = a.S + fr.vn_off;
+        float* S = SL ? s_S : a.S + fr.vn_off;
         float* GV = a.GV + fr.msg_off;
         const float* dpost = a.dpost + fr.vn_off;
         float* dllr = a.dllr ? a.dllr + fr.vn_off : nullptr;
@@ -169,6 +172,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
 
         // dl/dc2v(T)_e = dl/dL(T)_v(e): the first reverse step reads S = dl/dL(T)
         // and no GV; dl/dL_ch starts at dl/dL(T)
+        for (int v = tid; v < n; v += NT) S[v] = dpost[v];
         if (dllr)
             for (int v = tid; v < n; v += NT) dllr[v] = dpost[v];
         __syncthreads();
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(NT) void k_nms_bwd_qc(GradArgs a)
                     const int sbit = syn ? (syn[r] & 1) : 0;
                     float x[MAXD], g[MAXD];
                     const bool first = seg == nseg - 1 && t == t1 - 1;
-                    row_inputs(cin, L_at(t), q0, d, k, x, first ? dpost : S, first ? nullptr : GV, g);
+                    row_inputs(cin, L_at(t), q0, d, k, x, S, first ? nullptr : GV, g);
                     // signs, and the smallest and second smallest |x| with their
                     // first positions (branch-free, the forward's tie rule)
                     uint32_t negm = 0;
@@ -315,33 +319,58 @@ __global__ __launch_bounds__(256) void k_sum_partials(const float* partials, int
 // Rows of up to 8 edges run 1024 threads per workgroup (a frame per workgroup,
 // so batches of about one frame per CU still have 16 waves per CU); wider rows
 // need more registers than that leaves and run 512.
-template <int MAXD, bool WU, int NT>
-static int bwd_per_cu()
+template <int MAXD, bool WU, int NT, bool SL>
+static int bwd_per_cu(int dyn)
 {
-    static int per_cu = 0;
-    if (per_cu == 0) {
-        int v = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_nms_bwd_qc<MAXD, WU, NT>, NT, 0) != hipSuccess || v < 1)
-            v = 1;
-        per_cu = v;
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_nms_bwd_qc<MAXD, WU, NT, SL>, NT, size_t(dyn)) != hipSuccess ||
+        v < 1)
+        v = 1;
+    return v;
+}
+
+// Dynamic LDS of the adjoint for batch b: the column sums of its largest
+// frame when they fit beside the static tables, else none (they go to the
+// workspace).
+template <int MAXD, bool WU, int NT>
+static int bwd_dyn_lds(const cvr_batch_s* b)
+{
+    static int room = -1;
+    if (room < 0) {
+        const int lds_blk = std::min(device_attr(hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, 65536),
+                                     device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536));
+        hipFuncAttributes fa{};
+        const int st = hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_nms_bwd_qc<MAXD, WU, NT, true>)) ==
+                               hipSuccess ? int(fa.sharedSizeBytes) : 65536;
+        room = std::max(0, lds_blk - st);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_nms_bwd_qc<MAXD, WU, NT, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, room);
     }
-    return per_cu;
+    int64_t max_n = 0;
+    for (const cvr_code_t c : b->codes) max_n = std::max<int64_t>(max_n, c->dev.n);
+    return max_n * 4 <= room ? int(max_n * 4) : 0;
 }
 
 // The adjoint launch for batch b: grid (one partial weight-gradient row per
 // workgroup) and, when launch is true, the launch itself.
+template <int MAXD, bool WU>
+static int bwd_launch_wu(const cvr_batch_s* b, const GradArgs* g, hipStream_t s)
+{
+    constexpr int NT = MAXD <= 8 ? 1024 : 512;
+    const int dyn = bwd_dyn_lds<MAXD, WU, NT>(b);
+    const int per_cu = dyn > 0 ? bwd_per_cu<MAXD, WU, NT, true>(dyn) : bwd_per_cu<MAXD, WU, NT, false>(0);
+    const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
+    if (g) {
+        if (dyn > 0) hipLaunchKernelGGL((k_nms_bwd_qc<MAXD, WU, NT, true>), dim3(grid), dim3(NT), size_t(dyn), s, *g);
+        else hipLaunchKernelGGL((k_nms_bwd_qc<MAXD, WU, NT, false>), dim3(grid), dim3(NT), 0, s, *g);
+    }
+    return grid;
+}
+
 template <int MAXD>
 static int bwd_launch(const cvr_batch_s* b, const GradArgs* g, hipStream_t s)
 {
-    constexpr int NT = MAXD <= 8 ? 1024 : 512;
-    const bool wu = wave_uniform(b);
-    const int per_cu = wu ? bwd_per_cu<MAXD, true, NT>() : bwd_per_cu<MAXD, false, NT>();
-    const int grid = int(std::min<int64_t>(b->F, int64_t(device_cus()) * per_cu));
-    if (g) {
-        if (wu) hipLaunchKernelGGL((k_nms_bwd_qc<MAXD, true, NT>), dim3(grid), dim3(NT), 0, s, *g);
-        else hipLaunchKernelGGL((k_nms_bwd_qc<MAXD, false, NT>), dim3(grid), dim3(NT), 0, s, *g);
-    }
-    return grid;
+    return wave_uniform(b) ? bwd_launch_wu<MAXD, true>(b, g, s) : bwd_launch_wu<MAXD, false>(b, g, s);
 }
 
 static int grad_grid(const cvr_batch_s* b)
