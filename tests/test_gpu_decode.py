@@ -92,8 +92,15 @@ def _slice_stage(j, n, F, seed, mb=None):
 
 @pytest.mark.parametrize("j", [2, 3])
 def test_slice_stage_sp_fp32_qc(j):
-    """One coded slice of the 2^20-pair configuration (16 x 65536), SP fp32, 100 iterations.
-    Traces compared on 4 frames; bits/iters on all 16."""
+    """One coded slice of the 2^20-pair configuration (16 x 65536), SP fp32, 100 iterations,
+    every schedule bit-identical.  All 16 frames against the fp64 oracle:
+    - every frame, one iteration at a time from the decoder's own state (t = 0, 1, 5, 10
+      and the last): posteriors within 1e-4 of the scale of the fp64 step's;
+    - frames with margin (at least half of them): iteration counts, status and decisions
+      exact, and the whole binary32 trajectory within 1e-3 of the scale of the fp64 one
+      (the per-step differences compound over a decode: up to 1.3e-4 was seen on these
+      frames, so the whole-trajectory bound is not the per-step one);
+    - every frame reported ok satisfies Bob's syndrome."""
     print(f"[decode slice{j} SP f32 qc]", flush=True)
     n, F = 65536, 16
     qc, csr, L, syn, truth = _slice_stage(j, n, F, seed=12345)
@@ -106,13 +113,31 @@ def test_slice_stage_sp_fp32_qc(j):
                                                         schedule=sched), trace=True)
         for k in ("bits", "post", "iters", "ok", "trace"):
             np.testing.assert_array_equal(res[k], other[k])
-    Ft = 4
-    ref = oracle.decode(csr, L[:Ft], syn[:Ft], algo=oracle.SP, max_iter=100, trace=True)
-    sub = {k: (v.reshape(F, -1)[:Ft] if k in ("bits",) else v[:Ft]) for k, v in res.items() if v is not None and k != "post"}
-    _check_against_oracle(csr, sub, ref, Ft, n, syn[:Ft], 1e-4, expect_margin_frac=0.5)
-    ref_all = oracle.decode(csr, L, syn, algo=oracle.SP, max_iter=100)
-    agree = (res["iters"] == ref_all["iters"]).mean()
-    assert agree >= 0.75, f"iteration counts agree on {agree:.0%} of frames"
+    ref = oracle.decode(csr, L, syn, algo=oracle.SP, max_iter=100, trace=True)
+    margin = 0
+    for f in range(F):
+        t_o = int(ref["iters"][f])
+        if has_margin(csr, ref["post_trace"][f], ref["scale_trace"][f], t_o, syn[f], 1e-4):
+            margin += 1
+            assert int(res["iters"][f]) == t_o, f"frame {f}: iters gpu {int(res['iters'][f])} oracle {t_o}"
+            assert res["ok"][f] == ref["ok"][f]
+            np.testing.assert_array_equal(res["bits"].reshape(F, n)[f], ref["bits"][f])
+            worst = compare_trace(res["trace"][f], ref["post_trace"][f], ref["scale_trace"][f], t_o, 1e-3)
+            assert worst <= 1.0, f"frame {f}: trajectory deviation {worst:.3g} x 1e-3 of the scale"
+    print(f"  {margin}/{F} frames with margin", flush=True)
+    assert margin >= F // 2, f"only {margin}/{F} frames with margin"
+    from tests._gpu_state import decoded_for
+    worst = 0.0
+    for f in range(F):
+        l64 = L[f].astype(np.float32).astype(np.float64)
+        for t in sorted({0, 1, 5, 10, max(int(res["iters"][f]) - 1, 0)}):
+            post, c2v = decoded_for(code, qc, p, L[f], syn[f], t)
+            c_o, p_o = oracle.flood_step(csr, l64, syn[f], c2v, t, algo=oracle.SP)
+            post1, _ = decoded_for(code, qc, p, L[f], syn[f], t + 1)
+            sc = np.abs(l64).copy()
+            np.add.at(sc, csr.col_idx, np.abs(c_o))
+            worst = max(worst, float(np.max(np.abs(post1 - p_o) / (1e-4 * sc))))
+    assert worst <= 1.0, f"one-step posterior deviation {worst:.3g} x (1e-4 of the scale)"
     ok = res["ok"].astype(bool)
     bits = res["bits"].reshape(F, n)
     # every frame reported ok satisfies Bob's syndrome
