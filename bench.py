@@ -906,7 +906,7 @@ def train_step(args, wl, dev):
     E = qc.n_edges
     adj_bytes = adjoint_bytes(F, E, n, T, K)
     achieved = adj_bytes * adj_n / (adj_ms * 1e-3) / 1e9 if adj_ms > 0 else None
-    adj_kernel = "void cvr::k_nms_bwd_qc<8, true, 1024>"
+    adj_kernel = "void cvr::k_nms_bwd_qc<8, true, 1024, true>"   # column sums in LDS at n = 16384
     traffic, traffic_src = recorded_traffic(adj_kernel, args.workload, "adjoint", "")
     step_s = t_total / args.steps
     result = {
