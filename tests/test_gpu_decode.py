@@ -145,6 +145,53 @@ def test_slice_stage_sp_fp32_qc(j):
     np.testing.assert_array_equal(s_chk, syn[ok])
 
 
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_LAYERED])
+def test_sp_check_messages_across_the_phi_forms(sched):
+    """The binary32 sum-product check rule (Sec. III-C), message by message, against
+    the fp64 oracle, on inputs at and around the points where the device evaluation of
+    phi changes form (x = 1/8, and e^-x = 1/8 at x = ln 8) and over 1e-3 ... 40.  After
+    one iteration from zero messages every stored c2v is within 5e-6 x (1 + |c2v|) of
+    the oracle's (flooding): phi is good to about 1.3e-6 relative per evaluation (3e-6
+    at x = 40, from rounding x log2(e)), its exclusive sums add a few binary32 roundings
+    and |y phi'(y)| <= 1 carries a relative error of y into an absolute one of phi(y).
+    On the layered schedule later layers read posteriors rounded to binary32 after the
+    earlier layers' updates; there the bound is 2e-5 x (1 + |c2v|).  Every outer form
+    (Laurent quotient, logarithm, series) is hit by hundreds of messages."""
+    print(f"[phi forms sched={sched}]", flush=True)
+    from tests._gpu_state import decoded_for
+    n = 8192
+    qc = inputs.slice_code_spec(3, n)
+    csr = qc.to_csr()
+    code = api.Code.from_qc(qc)
+    rng = np.random.default_rng(81)
+    ln8 = math.log(8.0)
+    edges = [1e-3, 0.01, 0.05, 0.1, 0.124, 0.1249, 0.125, 0.1251, 0.126, 0.2, 0.5, 1.0, 1.5, 2.0, 2.07,
+             ln8 - 1e-3, ln8, ln8 + 1e-3, 2.1, 2.5, 3.0]
+    large = [4.0, 4.5, 5.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0, 40.0]
+    mag = np.where(rng.random(n) < 0.3, rng.choice(edges, n), rng.choice(large, n))
+    llr = (mag * rng.choice([-1.0, 1.0], n)).astype(np.float32)
+    syn = rng.integers(0, 2, qc.m, dtype=np.uint8)
+    l64 = llr.astype(np.float64)
+    p = api.Params(algo=api.SP, max_iter=1, math=api.F32, store=api.F32, schedule=sched)
+    _, c_gpu = decoded_for(code, qc, p, llr, syn, 1)
+    zero = np.zeros(csr.n_edges)
+    if sched == api.SCHED_LAYERED:
+        c_o, _ = oracle.layered_step(csr, l64, syn, zero, l64, 0, layers=oracle.qc_layers(qc.mb, qc.Z),
+                                     algo=oracle.SP)
+        tol = 2e-5
+    else:
+        c_o, _ = oracle.flood_step(csr, l64, syn, zero, 0, algo=oracle.SP)
+        tol = 5e-6
+    a = np.abs(c_o)
+    laurent, series = int((a > 2.7726).sum()), int((a < 0.2513).sum())
+    middle = a.size - laurent - series
+    worst = float(np.max(np.abs(c_gpu - c_o) / (tol * (1.0 + a))))
+    print(f"  outer forms: {laurent} Laurent, {middle} log, {series} series; worst {worst:.3g} x bound", flush=True)
+    assert min(laurent, middle, series) >= 100
+    np.testing.assert_array_equal(np.sign(c_gpu), np.sign(c_o))
+    assert worst <= 1.0
+
+
 def test_layouts_and_schedules_are_bit_identical():
     """Explicit CSR per-pass, QC per-pass and QC persistent decoding sum in the
     same order and must agree bit for bit."""
