@@ -79,7 +79,10 @@ template <> struct StoreT<__half> {
     __device__ static float get(__half s) { return __half2float(s); }
 };
 
-template <typename M> __device__ __forceinline__ M mabs(M v) { return v < M(0) ? -v : v; }
+// |v| as fabs gives it: the sign bit cleared, so -0 has magnitude +0 (phi(-0)
+// would otherwise take 1 / -0 = -inf into its logarithm).
+__device__ __forceinline__ float mabs(float v) { return __builtin_fabsf(v); }
+__device__ __forceinline__ double mabs(double v) { return __builtin_fabs(v); }
 
 // Check-node rule on d <= MAXD incoming v2c values x[] (sign flags in negm).
 // Writes the outgoing messages through `emit(k, value)`.

@@ -438,6 +438,42 @@ def test_failure_injection_and_edge_cases(sched):
     api.ldpc_decode_batch(empty, p, _g(np.zeros(1, np.float32)))
 
 
+@pytest.mark.parametrize("sched", [api.SCHED_PERSISTENT, api.SCHED_LAYERED])
+@pytest.mark.parametrize("math_", [api.F32, api.F64])
+@pytest.mark.parametrize("algo", [api.SP, api.NMS])
+def test_signed_zero_llrs_decode_like_the_oracle(algo, math_, sched):
+    """Channel LLRs of exactly +0 and -0 (no information, either sign bit): both
+    have magnitude 0 in the check rule (Sec. III-C), so a row holding one sends
+    zero to its other edges and nothing turns into NaN.  Every frame ends as the
+    fp64 oracle's does (status, iterations and decisions)."""
+    print(f"[signed zero LLRs algo={algo} math={math_} sched={sched}]", flush=True)
+    qc = inputs.lambda_half_rate_spec(4096)
+    csr = qc.to_csr()
+    code = api.Code.from_qc(qc)
+    F = 6
+    bits = inputs.random_bits((F, qc.n), seed=31)
+    llr = inputs.bpsk_llr(bits, 0.4, seed=32)
+    rng = np.random.default_rng(33)
+    pick = rng.random(llr.shape)
+    llr[pick < 0.02] = -0.0
+    llr[(pick >= 0.02) & (pick < 0.04)] = 0.0
+    assert np.signbit(llr[llr == 0]).any() and (~np.signbit(llr[llr == 0])).any()
+    syn, _ = oracle.syndrome(csr, bits)
+    dt = np.float64 if math_ == api.F64 else np.float32
+    llr = llr.astype(dt)
+    store = {api.F64: api.F64, api.F32: api.F32}[math_]
+    p = api.Params(algo=algo, max_iter=50, math=math_, store=store, schedule=sched)
+    res = _decode_gpu(code, F, llr, syn, p)
+    okw = dict(algo=oracle.SP if algo == api.SP else oracle.NMS, max_iter=50)
+    l64 = llr.astype(np.float64)
+    ref = (oracle.decode_layered(csr, l64, syn, layers=oracle.qc_layers(qc.mb, qc.Z), **okw)
+           if sched == api.SCHED_LAYERED else oracle.decode(csr, l64, syn, **okw))
+    assert (ref["ok"] == 1).all()
+    np.testing.assert_array_equal(res["ok"], ref["ok"])
+    np.testing.assert_array_equal(res["iters"], ref["iters"])
+    np.testing.assert_array_equal(res["bits"].reshape(F, -1), ref["bits"])
+
+
 def test_group_barrier_time_out_reports_every_frame_failed():
     """Forced from the host: with a zero wait bound, a group barrier that is not
     complete when a workgroup arrives gives up at once; the launch still ends and
