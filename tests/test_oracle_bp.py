@@ -137,6 +137,29 @@ def test_sum_product_on_trees_gives_exact_marginals(seed):
     np.testing.assert_allclose(r["post"][0], ref, rtol=1e-10, atol=1e-10)
 
 
+@pytest.mark.parametrize("zero", [0.0, -0.0])
+@pytest.mark.parametrize("algo", [oracle.SP, oracle.NMS])
+def test_a_zero_input_silences_the_other_edges_of_its_check(zero, algo):
+    """tanh(0) = 0 (and min |x| = 0): a check holding an input of magnitude zero,
+    of either sign bit, sends exactly zero to its other edges, and to that edge
+    the rule over the remaining inputs (tanh product, or scaled minimum)."""
+    H = np.ones((1, 4), np.uint8)
+    code = _csr_from_dense(H)
+    L = np.array([zero, 1.7, -0.6, 3.2])
+    for s in (0, 1):
+        r = oracle.decode(code, L[None, :], np.array([[s]], np.uint8), algo=algo, max_iter=1,
+                          early_stop=False, alpha=0.75)
+        c2v = r["post"][0] - L
+        assert np.all(np.isfinite(c2v))
+        np.testing.assert_array_equal(c2v[1:], 0.0)
+        sg = (1 - 2 * s) * -1.0
+        if algo == oracle.SP:
+            ref = sg * 2 * math.atanh(math.tanh(1.7 / 2) * math.tanh(0.6 / 2) * math.tanh(3.2 / 2))
+            assert abs(c2v[0] - ref) <= 1e-13
+        else:
+            assert c2v[0] == sg * 0.75 * 0.6
+
+
 def test_degree_two_check_passes_message_through():
     H = np.ones((1, 2), np.uint8)
     code = _csr_from_dense(H)
