@@ -22,7 +22,9 @@
  *    errors surface at a later call or at stream synchronisation.  The text of
  *    the last error of the calling thread is available from cvr_last_error().
  *  - An LLR is ln P(bit = 0) / P(bit = 1); bit 0 is sent as +1.  A hard
- *    decision is 1 iff the LLR is < 0.  Bits travel as one uint8 (0/1) per bit.
+ *    decision is 1 iff the LLR is < 0 (so +0 and -0 both decide 0, and both
+ *    have magnitude 0 in the check rules).  Bits travel as one uint8 (0/1)
+ *    per bit.
  *  - Only bit 0 of every input bit byte is used.
  */
 #ifndef CVQKD_RECON_H
