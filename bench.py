@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
                     "(weights/<prefix>_slice<j>.json per coded slice); iterations past their T reuse "
                     "the last learned row up to --max-iter")
+    ap.add_argument("--layered-weight-steps", type=int, default=2,
+                    help="on the layered schedule, iteration t uses the learned (flooding) weights of "
+                         "iteration steps * t (1: the same index)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent", "group", "layered"])
     ap.add_argument("--group-wgs", dest="group_wgs", type=int, default=0,
                     help="workgroups per frame of the group schedule (0 = auto)")
@@ -398,12 +401,14 @@ def recon(args, wl, dev):
                                          min_waves=args.min_waves, lds_cache_kb=args.lds_cache_kb,
                                          group_wgs=args.group_wgs)
             if wts:
-                from paper_2108_08418_amd.train import load_weights, weights_meta
+                from paper_2108_08418_amd.train import layered_weights, load_weights, weights_meta
                 meta = weights_meta(f"{wts}_slice{j}")
                 if meta.get("mb") not in (None, mbs[j]):
                     raise SystemExit(f"weights {wts}_slice{j} were trained for mb = {meta['mb']}, "
                                      f"the slice-{j} code has mb = {mbs[j]}")
                 w = load_weights(f"{wts}_slice{j}", extend_to=args.max_iter)
+                if sched_name == "layered":
+                    w = layered_weights(w, args.layered_weight_steps)
                 stage_params[j] = replace(stage_params[j], max_iter=int(w.shape[0]),
                                           weights=torch.from_numpy(w).to(dev))
         decs.append(dict(key=key, spec=spec, stage_params=stage_params))
@@ -566,7 +571,8 @@ def recon(args, wl, dev):
         result["decoders_rule"] = (
             "sp_layered: sum-product, layered schedule (the value above); sp: sum-product, flooding schedule "
             "(the baseline); nms: learned normalized min-sum, flooding, binary16 messages; nms_layered: the same "
-            "learned min-sum on the layered schedule.  same_fer_as_flooding_sp: the FER over fer_frames lies inside "
+            f"learned min-sum on the layered schedule, iteration t with the weights of flooding iteration "
+            f"{args.layered_weight_steps} t.  same_fer_as_flooding_sp: the FER over fer_frames lies inside "
             "flooding sum-product's 95 % Wilson interval")
     # the Gaussian-approximation iteration count (host model) beside the measured
     # mean: a binary-input AWGN channel carrying the capacity that Alice's LLRs

@@ -297,11 +297,13 @@ def test_recon_2p27_learned_min_sum_layered_chain_bit_exact(recon_2p27):
     threads per frame; LDS posterior cache automatic, full or off), all
     bit-identical.  16 sampled sub-blocks followed through the oracle's chain
     with its binary32 layered min-sum (same weights, binary16 storage):
-    iteration counts, status, decisions and posteriors bit for bit."""
+    iteration counts, status, decisions and posteriors bit for bit.  The
+    weights are the ones the benchmark gives this schedule: layered iteration
+    t with the learned weights of flooding iteration 2 t."""
     print("[full size: 2^27 pairs, slices 2 and 3, learned NMS f16, layered]", flush=True)
-    from paper_2108_08418_amd.train import load_weights
+    from paper_2108_08418_amd.train import layered_weights, load_weights
     R = recon_2p27
-    w = {j: load_weights(f"learned_slice{j}", extend_to=100) for j in (2, 3)}
+    w = {j: layered_weights(load_weights(f"learned_slice{j}", extend_to=100)) for j in (2, 3)}
     kws = {j: dict(algo=api.NMS, max_iter=int(w[j].shape[0]), math=api.F32, store=api.F16, weights=_g(w[j]))
            for j in (2, 3)}
     shapes = [dict(wg_threads=1024, lds_cache_kb=0), dict(wg_threads=512, lds_cache_kb=0),
