@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--weights", default="", help="learned min-sum weights: stored set name prefix "
                     "(weights/<prefix>_slice<j>.json per coded slice); iterations past their T reuse "
                     "the last learned row up to --max-iter")
+    ap.add_argument("--s-be", type=float, default=None,
+                    help="Holevo bound S_BE per pair: adds the experimental key rate K'_exp (Sec. V) of each "
+                         "reconciliation step to its line (with --sweep: K'_exp against the sub-block length)")
     ap.add_argument("--layered-weight-steps", type=int, default=2,
                     help="on the layered schedule, iteration t uses the learned (flooding) weights of "
                          "iteration steps * t (1: the same index)")
@@ -674,6 +677,7 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
             "workload": args.workload, "pairs": N, "sub_block": n, "sub_blocks_per_slice": F,
             "slices": ("16 equiprobable Gray intervals; slices 0-1 disclosed, "
                        f"2 (R={1 - qcs[2].m / n:.4f}) and 3 (R={1 - qcs[3].m / n:.4f}) decoded"),
+            "code_rates": {str(j): 1 - qcs[j].m / n for j in (2, 3)},
             "decoder": {str(j): ("sum-product" if spec[j][0] == api.SP else
                                  (f"learned normalized min-sum ({spec[j][3]}_slice{j})" if spec[j][3] else
                                   f"normalized min-sum alpha={args.alpha}")) for j in (2, 3)},
@@ -720,8 +724,26 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
         "mean_iters": {str(j): float(iters[j].mean()) for j in (2, 3)},
         "bit_errors_vs_bob": {str(j): c[j]["bit_errors"] for j in (2, 3)},
         "reconciled_pairs_per_s": N / (t_total / args.steps),
+        "key_rate_exp": key_rate_exp(args, N, sum(1 - qcs[j].m / n for j in (2, 3)), t_total / args.steps),
         "_counts": c,
     }
+
+
+def key_rate_exp(args, N, rate_sum, dt):
+    """The experimental key rate of Sec. V for this step (None without --s-be):
+    the N pairs reconciled by the coded slices' codes (disclosed slices carry
+    rate 0) in the step's time, with the paper's standard failure
+    probabilities (eps_EC = eps_PA = eps_PE = 2 eps_s = 2.5e-10) and
+    m = 4 slices in Delta_AEP.  S_BE, the Holevo bound, is an input."""
+    if args.s_be is None:
+        return None
+    from paper_2108_08418_amd import keyrate
+    eps_s, eps_x = 1.25e-10, 2.5e-10
+    d_aep = keyrate.delta_aep(M_BITS, N, eps_s, 3 * eps_x + 2 * eps_s)
+    return {"bits_per_s": keyrate.k_exp(N, rate_sum, args.s_be, d_aep, eps_x, dt), "S_BE": args.s_be,
+            "code_rate_sum": rate_sum, "pairs": N, "dt_s": dt,
+            "note": "Sec. V K'_exp with this step as the measured reconciliation time; the paper's codes meet "
+                    "eps_EC, here see fer_frames"}
 
 
 def ragged(args, wl, dev):

@@ -14,6 +14,8 @@ optimiser (Sec. IV).
   (Eq. for the simplified optimisation).
 * The optimal N_R: the root of the printed derivative on [1e5, N] (Brent),
   else the better end of the interval.
+* K'_exp (Sec. V): the key rate from the code rates actually used and the
+  measured reconciliation time, per sub-block length.
 
 S_BE (the Holevo-bound estimate of the appendix) is an input here: its
 derivation is not modelled.  Logarithms named log2 are base 2; ln is natural.
@@ -65,6 +67,26 @@ def b2(c_h: float, D: list[int], lam: list[dict]) -> float:
     decode.  G_j / N_R = 1 / sum_a(lambda_a / a), the edge count per bit
     (the printed m sum_b b rho_b equals it only for check-regular codes)."""
     return c_h * sum(7.0 * d / sum(f / a for a, f in l.items()) for d, l in zip(D, lam))
+
+
+def k_exp(N: float, rate_sum: float, S_BE: float, d_aep: float, eps_pa: float, dt_exp: float) -> float:
+    """K'_exp (Sec. V, the experimental key rate) in bits per second: the
+    block's N quadratures reconciled with codes of summed rate sum_j R_j
+    (0 for a disclosed slice) in the measured time dt_exp seconds,
+        (N (sum_j R_j - S_BE) - sqrt(N) Delta_AEP - 2 log2(1 / (2 eps_PA))) / dt_exp,
+    i.e. (N sum_j R_j - B_1) / dt_exp."""
+    if dt_exp <= 0.0:
+        raise ValueError("dt_exp must be positive")
+    return (N * rate_sum - b1(N, S_BE, d_aep, eps_pa)) / dt_exp
+
+
+def k_exp_curve(points: list[tuple[float, float, float]], N: float, S_BE: float, d_aep: float,
+                eps_pa: float) -> tuple[list[float], float]:
+    """K'_exp at each measured sub-block length: points are (N_R, sum_j R_j,
+    dt_exp seconds for the N quadratures).  Returns the rates and the N_R of
+    the largest."""
+    k = [k_exp(N, r, S_BE, d_aep, eps_pa, dt) for _, r, dt in points]
+    return k, points[int(max(range(len(k)), key=lambda i: k[i]))][0]
 
 
 def k_prime(N_R: float, N: float, I_AB: float, A: float, eps_ec: float, B1: float, B2: float) -> float:

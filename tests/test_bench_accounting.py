@@ -43,3 +43,15 @@ def test_wilson_interval_closed_forms():
         c, d = bench.wilson95(F - k, F)
         assert abs(a - (1 - d)) < 1e-12 and abs(b - (1 - c)) < 1e-12
         assert a <= k / F <= b
+
+
+def test_key_rate_exp_field_follows_the_key_rate_model():
+    """bench's K'_exp field: absent without --s-be; with it, keyrate.k_exp at
+    the paper's standard failure probabilities and m = 4 slices."""
+    import types
+    from paper_2108_08418_amd import keyrate
+    assert bench.key_rate_exp(types.SimpleNamespace(s_be=None), 2 ** 27, 0.68, 0.05) is None
+    r = bench.key_rate_exp(types.SimpleNamespace(s_be=0.5), 2 ** 27, 0.68, 0.05)
+    d_aep = keyrate.delta_aep(4, 2 ** 27, 1.25e-10, 1e-9)
+    assert r["bits_per_s"] == keyrate.k_exp(2 ** 27, 0.68, 0.5, d_aep, 2.5e-10, 0.05)
+    assert 0 < r["bits_per_s"] < 2 ** 27 * 0.18 / 0.05

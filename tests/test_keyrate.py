@@ -116,3 +116,26 @@ def test_delta_aep_and_b1_at_the_standard_settings_against_hand_evaluation():
     assert abs(kr.b1(N, 0.5, d, E_PA) - (5e8 + 13266811.5432)) < 1e-3
     # the paper's remark that the last AEP term is negligible at reasonable N
     assert abs(kr.delta_aep(M_BITS, 1e30, E_S, EPS) - d + 0.0000790569) < 1e-9
+
+
+def test_experimental_key_rate_is_the_finite_rate_with_measured_time_and_code_rates():
+    """K'_exp (Sec. V) shares B_1 with K'_Finite: with sum_j R_j = C_Finite(N_R)
+    and the model's time B_2 N_R it equals K'_Finite(N_R); it scales as
+    1 / dt_exp, grows by N / dt_exp per unit of summed rate, and is negative
+    when the codes carry less than S_BE per quadrature."""
+    S_BE = 0.9 * kr.capacity(GAMMA)
+    I, A, B1, B2 = _setup(S_BE)
+    d_aep = kr.delta_aep(M_BITS, N, E_S, EPS)
+    for N_R in (1e6, 3.6e7, 2e8):
+        c = kr.c_finite(N_R, I, A, E_EC)
+        ke = kr.k_exp(N, c, S_BE, d_aep, E_PA, B2 * N_R)
+        kf = kr.k_prime(N_R, N, I, A, E_EC, B1, B2)
+        assert abs(ke / kf - 1.0) < 1e-12, (N_R, ke, kf)
+    k1 = kr.k_exp(N, 0.5, S_BE, d_aep, E_PA, 10.0)
+    assert abs(kr.k_exp(N, 0.5, S_BE, d_aep, E_PA, 20.0) * 2.0 / k1 - 1.0) < 1e-14
+    assert abs((kr.k_exp(N, 0.6, S_BE, d_aep, E_PA, 10.0) - k1) / (0.1 * N / 10.0) - 1.0) < 1e-9
+    assert kr.k_exp(N, S_BE * 0.99, S_BE, d_aep, E_PA, 1.0) < 0.0
+    with pytest.raises(ValueError):
+        kr.k_exp(N, 0.5, S_BE, d_aep, E_PA, 0.0)
+    ks, best = kr.k_exp_curve([(1e5, 0.60, 1.0), (1e6, 0.62, 1.1), (1e7, 0.63, 1.4)], N, 0.5, d_aep, E_PA)
+    assert best == 1e6 and ks[1] == max(ks)
