@@ -69,6 +69,40 @@ def b2(c_h: float, D: list[int], lam: list[dict]) -> float:
     return c_h * sum(7.0 * d / sum(f / a for a, f in l.items()) for d, l in zip(D, lam))
 
 
+def efficiency(entropy_my: float, m: int, rates, I_AB: float) -> float:
+    """The reconciliation efficiency beta of sliced reconciliation (Sec. III-B):
+    (H(M(Y)) - m + sum_j R_j) / I_AB, with H(M(Y)) the entropy of Bob's m-bit
+    labels per quadrature and R_j the rate of slice j's code (0 for a
+    disclosed slice, 1 for one not sent)."""
+    if len(rates) != m:
+        raise ValueError("one rate per slice")
+    return (entropy_my - m + float(sum(rates))) / I_AB
+
+
+def quantiser_information(thresholds, snr: float) -> tuple[float, float]:
+    """(H(M(Y)), I(M(Y); X)) in bits per quadrature for X ~ N(0, 1),
+    Y = X + N(0, 1/snr) and the quantiser M with the given ascending
+    thresholds: H from the interval probabilities of Y ~ N(0, 1 + 1/snr);
+    I = H - H(M(Y) | X), the conditional entropy integrated over x by
+    adaptive quadrature.  With rates R_j equal to the slice capacities,
+    beta = I(M(Y); X) / I_AB (the slices' chain rule)."""
+    import numpy as np
+    from scipy.integrate import quad
+    from scipy.special import ndtr
+    t = np.concatenate([[-np.inf], np.asarray(thresholds, dtype=np.float64), [np.inf]])
+
+    def ent(p):
+        p = p[p > 0.0]
+        return float(-(p * np.log2(p)).sum())
+
+    H = ent(np.diff(ndtr(t / math.sqrt(1.0 + 1.0 / snr))))
+    sn = math.sqrt(1.0 / snr)
+    dens = lambda x: math.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+    Hc = quad(lambda x: ent(np.diff(ndtr((t - x) / sn))) * dens(x), -12.0, 12.0,
+              points=[float(v) for v in t[1:-1]], limit=400, epsabs=1e-12, epsrel=1e-10)[0]
+    return H, H - Hc
+
+
 def k_exp(N: float, rate_sum: float, S_BE: float, d_aep: float, eps_pa: float, dt_exp: float) -> float:
     """K'_exp (Sec. V, the experimental key rate) in bits per second: the
     block's N quadratures reconciled with codes of summed rate sum_j R_j

@@ -139,3 +139,40 @@ def test_experimental_key_rate_is_the_finite_rate_with_measured_time_and_code_ra
         kr.k_exp(N, 0.5, S_BE, d_aep, E_PA, 0.0)
     ks, best = kr.k_exp_curve([(1e5, 0.60, 1.0), (1e6, 0.62, 1.1), (1e7, 0.63, 1.4)], N, 0.5, d_aep, E_PA)
     assert best == 1e6 and ks[1] == max(ks)
+
+
+def test_quantised_information_against_the_oracle_slice_capacities():
+    """I(M(Y); X) of the 16-level equiprobable quantiser at SNR 3 (adaptive
+    quadrature) against the sum of the four slice capacities
+    C_j = 1 - E[log2(1 + exp(-(1 - 2 s_j) L_j))] estimated by Monte Carlo from
+    the oracle's slice LLRs given the true lower slices (Sec. III-B steps 1-4):
+    the chain rule makes them equal when H(M(Y)) = m.  Also H(M(Y)) = m for
+    equiprobable thresholds, I(M(Y); X) <= I_AB rising towards it with m, and
+    beta = I(M(Y); X) / I_AB when every slice's rate is its capacity."""
+    import oracle
+    from paper_2108_08418_amd import inputs
+    snr, m = 3.0, 4
+    th = inputs.equiprobable_thresholds(m, 1 + 1 / snr)
+    H, I = kr.quantiser_information(th, snr)
+    assert abs(H - m) < 1e-12
+    n = 1 << 18
+    x, y = inputs.gaussian_pairs(n, snr, seed=2024)
+    S = oracle.quantize(y, th, m)
+    sig = math.sqrt(1 / snr)
+    caps = []
+    for j in range(m):
+        L = oracle.slice_llr(x, sig, th, m, oracle.GRAY, j, (1 << j) - 1, S)
+        s = S[j].astype(np.float64)
+        caps.append(1.0 - float(np.mean(np.logaddexp(0.0, -(1.0 - 2.0 * s) * L))) / math.log(2.0))
+    assert abs(sum(caps) - I) < 5e-3, (caps, sum(caps), I)
+    I_AB = kr.capacity(snr)
+    assert abs(kr.efficiency(H, m, caps, I_AB) - I / I_AB) < 5e-3
+    assert kr.efficiency(H, m, [0.0, 0.0, 0.1875, 0.4921875], I_AB) == pytest.approx(0.6796875, abs=1e-12)
+    prev = 0.0
+    for mm in (1, 2, 4, 6, 8):
+        Hm, Im = kr.quantiser_information(inputs.equiprobable_thresholds(mm, 1 + 1 / snr), snr)
+        assert abs(Hm - mm) < 1e-12 and prev < Im < I_AB
+        prev = Im
+    assert prev > 0.998 * I_AB
+    with pytest.raises(ValueError):
+        kr.efficiency(H, m, [0.5], I_AB)
