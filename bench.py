@@ -725,16 +725,17 @@ def summarize(args, d, stage_params, qcs, codes, n, F, N, t_total, prof, c, pers
         "bit_errors_vs_bob": {str(j): c[j]["bit_errors"] for j in (2, 3)},
         "reconciled_pairs_per_s": N / (t_total / args.steps),
         "key_rate_exp": key_rate_exp(args, N, sum(1 - qcs[j].m / n for j in (2, 3)), t_total / args.steps),
-        "reconciliation_efficiency": efficiency(th, [0.0, 0.0] + [1 - qcs[j].m / n for j in (2, 3)]),
+        "reconciliation_efficiency": efficiency([0.0, 0.0] + [1 - qcs[j].m / n for j in (2, 3)]),
         "_counts": c,
     }
 
 
-def efficiency(th, rates):
+def efficiency(rates):
     """beta of Sec. III-B for this setup: Bob's label entropy, the slices'
     rates (disclosed slices 0), I_AB = log2(1 + SNR) / 2; beside it the bound
     the quantiser sets, I(M(Y); X) / I_AB (beta with capacity-achieving codes)."""
-    from paper_2108_08418_amd import keyrate
+    from paper_2108_08418_amd import inputs, keyrate
+    th = inputs.equiprobable_thresholds(M_BITS, 1.0 + 1.0 / SNR)
     H, I = keyrate.quantiser_information(th, SNR)
     I_AB = keyrate.capacity(SNR)
     return {"beta": keyrate.efficiency(H, M_BITS, rates, I_AB), "quantiser_bound": I / I_AB,
