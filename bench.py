@@ -329,9 +329,10 @@ def _decoder_configs(args, api):
     """(key, {coded slice: (algo, store, schedule name, weights prefix)}) of the
     decoders one run times.  --decoder both (default): sum-product on the
     layered schedule (the headline), plain flooding sum-product (the baseline
-    the paper's belief propagation names), and learned min-sum with binary16
+    the paper's belief propagation names), learned min-sum with binary16
     messages on the flooding and on the layered schedule, on both coded
-    slices."""
+    slices, and, on the layered schedule, learned min-sum on slice 2 with
+    sum-product on slice 3 (each slice's decoder picked by its FER)."""
     sp = (api.SP, api.F32, args.schedule, "")
     nms = (api.NMS, api.F16, args.schedule, args.weights)
     if args.decoder == "both":
@@ -340,7 +341,7 @@ def _decoder_configs(args, api):
         learned = (api.NMS, api.F16, "auto", args.weights or "learned")
         learned_lay = (api.NMS, api.F16, "layered", args.weights or "learned")
         return [("sp_layered", {2: lay, 3: lay}), ("sp", {2: flood, 3: flood}), ("nms", {2: learned, 3: learned}),
-                ("nms_layered", {2: learned_lay, 3: learned_lay})]
+                ("nms_layered", {2: learned_lay, 3: learned_lay}), ("mixed_layered", {2: learned_lay, 3: lay})]
     if args.decoder == "sp":
         return [("sp", {2: sp, 3: sp})]
     return [("nms", {2: nms, 3: nms})]
@@ -575,7 +576,8 @@ def recon(args, wl, dev):
             "sp_layered: sum-product, layered schedule (the value above); sp: sum-product, flooding schedule "
             "(the baseline); nms: learned normalized min-sum, flooding, binary16 messages; nms_layered: the same "
             f"learned min-sum on the layered schedule, iteration t with the weights of flooding iteration "
-            f"{args.layered_weight_steps} t.  same_fer_as_flooding_sp: the FER over fer_frames lies inside "
+            f"{args.layered_weight_steps} t; mixed_layered: learned min-sum (binary16, layered) on slice 2, "
+            "sum-product (fp32, layered) on slice 3.  same_fer_as_flooding_sp: the FER over fer_frames lies inside "
             "flooding sum-product's 95 % Wilson interval")
     # the Gaussian-approximation iteration count (host model) beside the measured
     # mean: a binary-input AWGN channel carrying the capacity that Alice's LLRs
