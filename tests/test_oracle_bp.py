@@ -365,6 +365,35 @@ def test_prec32_values_are_floats_and_close_to_fp64(algo):
     assert err.max() < 16 * 2.0 ** -24
 
 
+@pytest.mark.parametrize("algo", [oracle.SP, oracle.NMS])
+def test_prec32_follows_fp64_over_twelve_iterations(algo):
+    """From the second iteration on, the binary32 mode forms each variable's
+    extrinsic message from its running posterior; the fp64 mode sums the other
+    edges directly.  On frames that decode, the two stay within a few hundred
+    binary32 roundings of the per-variable scale for 12 iterations (measured
+    3e-6), where a stale or missing term in either formulation moves a
+    posterior by a sizeable fraction of its scale; the hard decisions, the
+    stop iteration and the success flag agree exactly."""
+    code = I.lambda_half_rate_spec(2048).to_csr()
+    rng = np.random.default_rng(21)
+    bits = rng.integers(0, 2, (3, code.n)).astype(np.uint8)
+    llr = I.bpsk_llr(bits, 0.6, 22)
+    s, _ = oracle.syndrome(code, bits)
+    kw = dict(algo=algo, alpha=0.8, max_iter=12, early_stop=False, trace=True)
+    a = oracle.decode(code, llr, s, **kw)
+    b = oracle.decode(code, llr, s, prec32=True, **kw)
+    for t in range(1, 13):
+        err = np.abs(a["post_trace"][:, t] - b["post_trace"][:, t]) / a["scale_trace"][:, t]
+        assert err.max() < 1e-5, (t, err.max())
+    np.testing.assert_array_equal(a["bits"], b["bits"])
+    kw["early_stop"] = True
+    a = oracle.decode(code, llr, s, **kw)
+    b = oracle.decode(code, llr, s, prec32=True, **kw)
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    np.testing.assert_array_equal(a["ok"], b["ok"])
+    assert a["ok"].all() and (a["iters"] > 1).all()
+
+
 def test_prec32_min_sum_hand_computed_row():
     H = np.ones((1, 3), np.uint8)
     code = _csr_from_dense(H)
