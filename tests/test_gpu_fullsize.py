@@ -5,10 +5,11 @@ properties checked on every frame.
 * 2^27 Gaussian pairs at SNR 3 (16 equiprobable levels, 2048 sub-blocks of
   2^16 per coded slice): the benchmark's two-stage chain (slice 2 decoded,
   slice 3's LLRs picked by the decoded bits, slice 3 decoded) with each of
-  the benchmark's four decoders: sum-product on the layered schedule (the
-  headline), flooding sum-product (persistent kernel at 1024 threads) and
+  the benchmark's five decoders: sum-product on the layered schedule (the
+  headline), flooding sum-product (persistent kernel at 1024 threads),
   learned min-sum with binary16 messages on the flooding (persistent kernel)
-  and on the layered schedule.
+  and on the layered schedule, and learned min-sum on slice 2 with
+  sum-product on slice 3 (layered).
 * The uneven batch: 4096 sub-blocks of the rate-0.0625 MET code at SNR 0.16
   (2176 x 4096, 1024 x 16384, 640 x 65536, 256 x 262144 bits), min-sum
   alpha 0.75 with binary16 messages, persistent kernel at 1024 threads.
@@ -316,6 +317,51 @@ def test_recon_2p27_learned_min_sum_layered_chain_bit_exact(recon_2p27):
     chk = lambda j, csr, r, f, rj, s: _check_exact(r, f, rj["iters"], rj["ok"], rj["bits"], rj["post"])
     exact = _follow_sampled(R, res, ref, chk)
     assert exact[2] == len(R["frames"]) and exact[3] == len(R["frames"]), exact
+
+
+def test_recon_2p27_mixed_layered_chain_against_oracle(recon_2p27):
+    """The benchmark's per-slice decoder choice at 2^27 pairs, on the layered
+    schedule: learned min-sum with binary16 messages on slice 2 (layered
+    iteration t with the weights of flooding iteration 2 t), slice 3's LLRs
+    picked by its decoded bits, sum-product with fp32 messages on slice 3; two
+    launch shapes, bit-identical.  16 sampled sub-blocks followed through the
+    oracle's chain: slice 2 bit for bit against its binary32 layered min-sum
+    (binary16 storage); slice 3 against its fp64 layered sum-product, with
+    decisions, iteration counts and status exact on frames with a margin of
+    2^-6 of the scale."""
+    print("[full size: 2^27 pairs, learned NMS f16 layered on slice 2, SP layered on slice 3]", flush=True)
+    from paper_2108_08418_amd.train import layered_weights, load_weights
+    R = recon_2p27
+    w2 = layered_weights(load_weights("learned_slice2", extend_to=100))
+    kw2 = dict(algo=api.NMS, max_iter=int(w2.shape[0]), math=api.F32, store=api.F16, weights=_g(w2))
+    kw3 = dict(algo=api.SP, max_iter=100, math=api.F32, store=api.F32)
+    shapes = [dict(wg_threads=1024, lds_cache_kb=0), dict(wg_threads=512, lds_cache_kb=150)]
+    res = _run_chain(R, kw2, shapes, schedule=api.SCHED_LAYERED, kw3=kw3)
+    for j in (2, 3):
+        assert res[j]["ok"].mean() > 0.99, f"slice {j}: FER {1 - res[j]['ok'].mean():.3%}"
+    lay = {j: oracle.qc_layers(R["qcs"][j].mb, R["qcs"][j].Z) for j in (2, 3)}
+
+    def ref(j, csr, L, s):
+        L32 = L.astype(np.float32).astype(np.float64)[None, :]
+        if j == 2:
+            return oracle.decode_layered(csr, L32, s, layers=lay[2], algo=oracle.NMS, weights=w2.astype(np.float64),
+                                         max_iter=int(w2.shape[0]), store_half=True, prec32=True)
+        return oracle.decode_layered(csr, L32, s, layers=lay[3], algo=oracle.SP, max_iter=100, trace=True)
+
+    def chk(j, csr, r, f, rj, s):
+        if j == 2:
+            return _check_exact(r, f, rj["iters"], rj["ok"], rj["bits"], rj["post"])
+        t_o = int(r["iters"][0])
+        if not has_margin(csr, r["post_trace"][0], r["scale_trace"][0], t_o, s, 2.0 ** -6):
+            return False
+        assert int(rj["iters"][f]) == t_o, f"slice 3 frame {f}: iters {int(rj['iters'][f])} oracle {t_o}"
+        assert bool(rj["ok"][f]) == bool(r["ok"][0])
+        np.testing.assert_array_equal(rj["bits"][f], r["bits"][0])
+        return True
+
+    counted = _follow_sampled(R, res, ref, chk)
+    k = len(R["frames"])
+    assert counted[2] == k and counted[3] >= 0.75 * k, counted
 
 
 def _sweep_point(R, n, j):
