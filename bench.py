@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--s-be", type=float, default=None,
                     help="Holevo bound S_BE per pair: adds the experimental key rate K'_exp (Sec. V) of each "
                          "reconciliation step to its line (with --sweep: K'_exp against the sub-block length)")
-    ap.add_argument("--layered-weight-steps", type=int, default=2,
+    ap.add_argument("--layered-weight-steps", type=float, default=2,
                     help="on the layered schedule, iteration t uses the learned (flooding) weights of "
                          "iteration steps * t (1: the same index)")
     ap.add_argument("--schedule", default="auto", choices=["auto", "passes", "persistent", "group", "layered"])
@@ -576,7 +576,7 @@ def recon(args, wl, dev):
             "sp_layered: sum-product, layered schedule (the value above); sp: sum-product, flooding schedule "
             "(the baseline); nms: learned normalized min-sum, flooding, binary16 messages; nms_layered: the same "
             f"learned min-sum on the layered schedule, iteration t with the weights of flooding iteration "
-            f"{args.layered_weight_steps} t; mixed_layered: learned min-sum (binary16, layered) on slice 2, "
+            f"{args.layered_weight_steps:g} t; mixed_layered: learned min-sum (binary16, layered) on slice 2, "
             "sum-product (fp32, layered) on slice 3.  same_fer_as_flooding_sp: the FER over fer_frames lies inside "
             "flooding sum-product's 95 % Wilson interval")
     # the Gaussian-approximation iteration count (host model) beside the measured

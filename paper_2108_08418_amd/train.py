@@ -116,16 +116,17 @@ def load_weights(name: str, extend_to: int | None = None) -> np.ndarray:
     return w
 
 
-def layered_weights(w: np.ndarray, steps: int = 2) -> np.ndarray:
+def layered_weights(w: np.ndarray, steps: float = 2) -> np.ndarray:
     """Per-iteration weights for the layered schedule from weights learned
     through the flooding decoder: layered iteration t takes flooding
-    iteration ``steps * t`` (the last row held beyond), since one layered
-    iteration, which updates every check with the newest messages, carries
-    information about as far as two flooding iterations.  Same shape as w."""
-    if steps < 1:
+    iteration ``steps * t`` rounded to the nearest integer (ties to even; the
+    last row held beyond), since one layered iteration, which updates every
+    check with the newest messages, carries information about as far as two
+    flooding iterations.  Same shape as w."""
+    if not steps >= 1:
         raise ValueError("steps must be >= 1")
     T = w.shape[0]
-    return np.ascontiguousarray(w[np.minimum(steps * np.arange(T), T - 1)])
+    return np.ascontiguousarray(w[np.minimum(np.round(steps * np.arange(T)).astype(np.int64), T - 1)])
 
 
 def main():

@@ -14,6 +14,8 @@ def test_layered_weights_take_every_second_flooding_iteration():
         np.testing.assert_array_equal(lw[t], w[min(2 * t, 9)])
     np.testing.assert_array_equal(layered_weights(w, 1), w)
     np.testing.assert_array_equal(layered_weights(w, 3)[3], w[9])
+    # fractional steps take the nearest flooding iteration (ties to even)
+    np.testing.assert_array_equal(layered_weights(w, 1.5)[:5], w[[0, 2, 3, 4, 6]])
     with pytest.raises(ValueError):
         layered_weights(w, 0)
 
