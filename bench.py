@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+DEFAULT_WORKLOAD = "recon-2^27-nR2^16"
 WORKLOADS = {
     # 2^27 pairs at SNR 3 split into sub-blocks of 2^16: the n_R = 2^16 point
     # of the block-size sweep, with the 16-level / 4-slice setup
@@ -56,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="recon-2^27-nR2^16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--decoder", default="both", choices=["both", "sp", "nms"],
                     help="both: layered sum-product (the headline), flooding sum-product and learned min-sum, "
                          "timed one after the other")
@@ -80,6 +81,8 @@ def parse():
                     help="LDS posterior cache KiB of the persistent decoder (0 = auto, -1 = none)")
     ap.add_argument("--cpu-frames", type=int, default=48, help="sub-blocks per stage in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="with the default workload, skip the uneven-batch and training-step summaries")
     ap.add_argument("--seed", type=int, default=2108)
     ap.add_argument("--graph", action="store_true", help="replay the decode from a captured HIP graph")
     ap.add_argument("--sweep", action="store_true",
@@ -262,10 +265,37 @@ def main():
         return
     wl = WORKLOADS[args.workload]
     if wl.get("kind") == "ragged":
-        return ragged(args, wl, dev)
+        print(json.dumps(ragged(args, wl, dev)))
+        return
     if wl.get("kind") == "train":
-        return train_step(args, wl, dev)
-    print(json.dumps(recon(args, wl, dev)))
+        print(json.dumps(train_step(args, wl, dev)))
+        return
+    res = recon(args, wl, dev)
+    if args.workload == DEFAULT_WORKLOAD and not args.no_other_workloads:
+        res["other_workloads"] = other_workloads(args, dev)
+    print(json.dumps(res))
+
+
+def other_workloads(args, dev):
+    """The uneven MET batch (normalized min-sum, alpha 0.75, binary16
+    messages, flooding and layered) and the unrolled min-sum training step,
+    each timed by its own routine after the headline step (their own
+    warm-up, autotuning and timed steps); the summary of each in the
+    headline line."""
+    import copy
+    out = {}
+    runs = (("ragged-4096-frames", "auto", ragged), ("ragged-4096-frames", "layered", ragged),
+            ("train-nms-r12-n16384-T20", "auto", train_step))
+    for name, sched, fn in runs:
+        a = copy.copy(args)
+        a.workload, a.decoder, a.weights, a.schedule, a.graph = name, "nms", "", sched, False
+        a.wg = a.min_waves = a.lds_cache_kb = a.group_wgs = 0
+        r = fn(a, WORKLOADS[name], dev)
+        key = name if fn is train_step else f"{name}/{'layered' if sched == 'layered' else 'flooding'}"
+        out[key] = {k: r[k] for k in ("metric", "value", "unit", "ms_per_step", "steps", "dtype", "config",
+                                      "roofline", "fer", "mean_iters", "forward_ms", "adjoint_ms") if k in r}
+        print(f"# {key}: {r['ms_per_step']:.2f} ms/step, {r['value']:.3e} bits/s", file=sys.stderr, flush=True)
+    return out
 
 
 def llr_forms(args, dev):
@@ -890,7 +920,7 @@ def ragged(args, wl, dev):
         "bit_errors": int(err.sum()),
         "autotune_ms_per_decode": tuned,
     }
-    print(json.dumps(result))
+    return result
 
 
 def adjoint_bytes(F, E, n, T, K):
@@ -971,7 +1001,7 @@ def train_step(args, wl, dev):
         "edge_iterations_per_s": 2.0 * F * E * T / step_s,
         "loss": float(loss),
     }
-    print(json.dumps(result))
+    return result
 
 
 def cpu_baseline(args, x_np, y_np, qcs, th, sig, n, dec):
